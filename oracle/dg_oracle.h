@@ -1,0 +1,104 @@
+/*
+ * FP64 CPU oracle for the modal discontinuous-Galerkin Euler scheme of
+ * Bauer et al., "Simulating Turbulence Using the Astrophysical Discontinuous
+ * Galerkin Code TENET" (arXiv 1602.09079).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * definition that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no code, header, table or constant with the GPU library.
+ *
+ * Every array is FP64 on the host.  State layout (also the GPU layout):
+ *   y[i][l][z][y][x], x fastest; i = field (rho, m_x, m_y, m_z, E);
+ *   l = mode index in the graded order listed by orc_mode_list().
+ *
+ * Parity status per function (pins live in tests/test_oracle_*.py):
+ *   tables, projection, rhs, hllc, flux, dt, step, totals  -- pinned
+ *   forcing table (OU + Helmholtz projection)               -- pinned (statistics, solenoidality)
+ *   restriction                                             -- pinned (exactness, conservation)
+ *   MLP forward/backward/Adam                               -- pinned (finite differences, textbook Adam)
+ */
+#ifndef DG_ORACLE_H
+#define DG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t k;          /* polynomial degree, 0..3 */
+    int32_t n[3];       /* cells per axis */
+    double box[3];      /* box lengths; cells are box[a]/n[a] wide */
+    double gamma;       /* adiabatic index */
+    double cfl;         /* Courant factor C of Sec. 2.4 */
+} orc_cfg;
+
+typedef struct {
+    int32_t nmodes;          /* number of Fourier modes in the table */
+    const int32_t *nvec;     /* [nmodes][3] integer wave vectors */
+    const double *ahat;      /* [nmodes][3][2] complex amplitude (re, im) per component */
+} orc_forcing;
+
+/* ---- Sec. 2.1: basis ---- */
+int    orc_nmodes(int k);
+void   orc_mode_list(int k, int32_t *uvw);                 /* [N][3] degrees (u,v,w) */
+void   orc_gauss_legendre(int n, double *x, double *w);   /* n-point rule on [-1,1] */
+double orc_pleg(int u, double x);                         /* scaled Legendre sqrt(2u+1) P_u */
+double orc_dpleg(int u, double x);                        /* its derivative */
+void   orc_basis(int k, const double xi[3], double *phi);          /* [N] */
+void   orc_basis_grad(int k, const double xi[3], double *dphi);    /* [3][N] */
+
+/* ---- Sec. 2.2: initial conditions by Gauss-quadrature L2 projection ----
+ * qp: point values [5][c][b][a][cell] at the (k+1)^3 Gauss points of every
+ * cell (a,b,c = Gauss index along x,y,z).  y: [5][N][cell]. */
+void orc_project(const orc_cfg *cfg, const double *qp, double *y);
+/* point coordinates of the Gauss points in cell-relative units: the x-coordinate
+ * of Gauss index a in cell ix is (ix + (1 + xi_a)/2) * box/n */
+
+/* ---- Sec. 2.3: the operator ---- */
+void orc_euler_flux(const double q[5], int axis, double gamma, double F[5]);
+void orc_hllc(const double qL[5], const double qR[5], int axis, double gamma, double F[5]);
+/* r = R(y) with dy/dt + R(y) = 0 (eq. dg:eqn:time); frc may be NULL */
+void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double *r);
+
+/* ---- Sec. 2.4: time step from cell means, global minimum ---- */
+double orc_dt(const orc_cfg *cfg, const double *y);
+
+/* ---- Sec. 2.3: SSP-RK3 in Shu-Osher form.  dt <= 0 selects the CFL time step
+ * of Sec. 2.4 at the start of every step.  t is advanced by the steps taken. */
+void orc_step(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t,
+              const orc_forcing *frc);
+/* a single stage: out = a*y0 + b*(yin - dt*R(yin)) */
+void orc_stage(const orc_cfg *cfg, const double *y0, const double *yin, double a, double b,
+               double dt, const orc_forcing *frc, double *out);
+
+/* conserved totals sum_K |K| w_{i,0}^K (pairwise summation) */
+void orc_totals(const orc_cfg *cfg, const double *y, double out[5]);
+
+/* ---- Sec. 3.1: driving field ----
+ * acceleration at physical point x: a_c(x) = sum_m Re(ahat_{m,c} exp(2 pi i n_m.x/L)) */
+void orc_accel(const orc_forcing *frc, const double box[3], const double x[3], double a[3]);
+/* One Ornstein-Uhlenbeck update of the complex amplitudes followed by the
+ * Helmholtz (solenoidal) projection and the paraboloid amplitude profile.
+ * theta: [nmodes][3][2] OU state (updated in place); z: [nmodes][3][2] standard
+ * normal draws; f = exp(-dt/t_s); sigma: OU standard deviation; a0: overall
+ * amplitude; kmin/kmax: band in units of 2 pi / L.  ahat out: [nmodes][3][2]. */
+void orc_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const double *z,
+                   double f, double sigma, double a0, double kmin, double kmax, double *ahat);
+
+/* ---- closure support (not in the paper) ---- */
+/* exact L2 restriction of a degree-kf state on (2n)^3 cells onto degree-kc on n^3 cells */
+void orc_restrict(int kf, int kc, const int32_t nc[3], const double *yf, double *yc);
+/* 140-128-128-20 tanh MLP: see orc_mlp_* in dg_oracle.c for the parameter layout */
+void orc_mlp_forward(int nin, int nh1, int nh2, int nout, const double *params,
+                     int batch, const double *x, double *h1, double *h2, double *yout);
+double orc_mlp_loss_grad(int nin, int nh1, int nh2, int nout, const double *params,
+                         int batch, const double *x, const double *target, double *grad);
+void orc_adam(int nparams, double *params, const double *grad, double *m, double *v,
+              int step, double lr, double beta1, double beta2, double eps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

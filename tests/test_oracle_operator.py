@@ -1,0 +1,275 @@
+"""Pins of the oracle's operator (Sec. 2.2-2.4 of arXiv 1602.09079): projection
+exactness, HLLC properties, free-stream preservation, conservation, the linear
+advection special case, convergence order k+1, the SSP-RK3 amplification factor
+and the CFL time step."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_09079_amd import synth
+
+G = 5.0 / 3.0
+
+
+def nodes(k):
+    return O.gauss_legendre(k + 1)[0]
+
+
+# ------------------------------------------------------------------ projection
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_projection_exact_for_degree_k_polynomials(k):
+    """Sec. 2.2: the (k+1)-point projection is exact for polynomial data of degree <= k."""
+    rng = np.random.default_rng(10 + k)
+    nc = 3
+    cfg = O.make_cfg(k, nc)
+    n = k + 1
+    x = nodes(k)
+    exps = [(u, v, w) for u in range(k + 1) for v in range(k + 1) for w in range(k + 1) if u + v + w <= k]
+    coef = rng.standard_normal((5, nc, nc, nc, len(exps)))  # per field per cell, monomials in xi
+    qp = np.zeros((5, n, n, n, nc, nc, nc))
+    for c, b, a in itertools.product(range(n), repeat=3):
+        mono = np.array([x[a] ** u * x[b] ** v * x[c] ** w for (u, v, w) in exps])
+        qp[:, c, b, a] = coef @ mono
+    y = O.project(cfg, qp)
+    # evaluate the modal expansion at random interior points and compare
+    for _ in range(6):
+        xi = rng.uniform(-1, 1, 3)
+        ph = O.basis(k, xi)
+        mono = np.array([xi[0] ** u * xi[1] ** v * xi[2] ** w for (u, v, w) in exps])
+        got = np.einsum("il...,l->i...", y, ph)
+        want = coef @ mono
+        np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+def test_mode_zero_is_cell_mean_for_linear_data():
+    k = 2
+    cfg = O.make_cfg(k, 4)
+    x = nodes(k)
+    n = k + 1
+    qp = np.zeros((5, n, n, n, 4, 4, 4))
+    # field = 2 + 0.5 X + 0.25 Y - Z in physical coordinates
+    h = 0.25
+    for c, b, a in itertools.product(range(n), repeat=3):
+        X = (np.arange(4)[None, None, :] + 0.5 * (1 + x[a])) * h
+        Y = (np.arange(4)[None, :, None] + 0.5 * (1 + x[b])) * h
+        Z = (np.arange(4)[:, None, None] + 0.5 * (1 + x[c])) * h
+        qp[:, c, b, a] = 2 + 0.5 * X + 0.25 * Y - Z
+    y = O.project(cfg, qp)
+    ctr = (np.arange(4) + 0.5) * h
+    mean = 2 + 0.5 * ctr[None, None, :] + 0.25 * ctr[None, :, None] - ctr[:, None, None]
+    np.testing.assert_allclose(y[0, 0], mean, atol=1e-14)
+
+
+# ------------------------------------------------------------------ HLLC
+
+def cons(rho, v, p, g=G):
+    v = np.asarray(v, dtype=float)
+    return np.array([rho, *(rho * v), p / (g - 1) + 0.5 * rho * v.dot(v)])
+
+
+def rand_state(rng, vmax=0.8):
+    return cons(rng.uniform(0.3, 2.0), rng.uniform(-vmax, vmax, 3), rng.uniform(0.3, 2.0))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_hllc_consistency(axis):
+    rng = np.random.default_rng(axis)
+    for _ in range(50):
+        q = rand_state(rng, vmax=3.0)
+        np.testing.assert_allclose(O.hllc(q, q, axis, G), O.euler_flux(q, axis, G), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_hllc_exact_contact(axis):
+    """Equal pressure and velocity, jump in density: HLLC returns the upwind flux."""
+    rng = np.random.default_rng(5 + axis)
+    for sgn in (+1, -1):
+        v = rng.uniform(-0.5, 0.5, 3)
+        v[axis] = sgn * abs(v[axis]) + sgn * 0.05
+        qL = cons(1.3, v, 0.9)
+        qR = cons(0.6, v, 0.9)
+        up = qL if sgn > 0 else qR
+        np.testing.assert_allclose(O.hllc(qL, qR, axis, G), O.euler_flux(up, axis, G), rtol=1e-13, atol=1e-14)
+
+
+def test_hllc_supersonic_upwinding():
+    rng = np.random.default_rng(7)
+    for axis in range(3):
+        for _ in range(10):
+            qL = rand_state(rng)
+            qR = rand_state(rng)
+            for q in (qL, qR):
+                c = math.sqrt(G * (G - 1) * (q[4] - 0.5 * (q[1:4] ** 2).sum() / q[0]) / q[0])
+                # make the normal velocity strongly supersonic to the right
+                v = q[1:4] / q[0]
+                v[axis] = 3.0 * c + 1.0 + 2.0 * abs(v).max()
+                q[:] = cons(q[0], v, (G - 1) * (q[4] - 0.5 * q[0] * (q[1:4] / q[0]).dot(q[1:4] / q[0])))
+            cL = math.sqrt(G * 1.0)
+            F = O.hllc(qL, qR, axis, G)
+            np.testing.assert_allclose(F, O.euler_flux(qL, axis, G), rtol=1e-13)
+            # mirrored: everything moving left
+            mL, mR = qL.copy(), qR.copy()
+            mL[1 + axis] *= -1
+            mR[1 + axis] *= -1
+            np.testing.assert_allclose(O.hllc(mR, mL, axis, G), O.euler_flux(mL, axis, G), rtol=1e-13)
+
+
+def test_hllc_rotation_and_mirror_symmetry():
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        qL, qR = rand_state(rng), rand_state(rng)
+        F0 = O.hllc(qL, qR, 0, G)
+        # rotation: relabel axes (x,y,z) -> (y,z,x)
+        for axis in (1, 2):
+            perm = [(j - axis) % 3 for j in range(3)]  # component j of the rotated state = component perm[j]
+            rL = np.array([qL[0], *[qL[1 + perm[j]] for j in range(3)], qL[4]])
+            rR = np.array([qR[0], *[qR[1 + perm[j]] for j in range(3)], qR[4]])
+            Fa = O.hllc(rL, rR, axis, G)
+            np.testing.assert_allclose(Fa[[0, 4]], F0[[0, 4]], rtol=1e-13, atol=1e-14)
+            np.testing.assert_allclose([Fa[1 + j] for j in range(3)], [F0[1 + perm[j]] for j in range(3)],
+                                       rtol=1e-13, atol=1e-14)
+        # mirror x -> -x: swap sides, flip normal components; flux flips sign except normal momentum
+        mL, mR = qR.copy(), qL.copy()
+        mL[1] *= -1
+        mR[1] *= -1
+        Fm = O.hllc(mL, mR, 0, G)
+        want = -F0.copy()
+        want[1] = F0[1]
+        np.testing.assert_allclose(Fm, want, rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------------------------------ operator
+
+def turb_state(k, nc, seed=9079, mach=0.3):
+    cfg = O.make_cfg(k, nc)
+    qp = synth.turbulence(nc, nodes(k), seed=seed, mach=mach).numpy()
+    return cfg, O.project(cfg, qp)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_free_stream_preservation(k):
+    nc = (4, 3, 5)
+    cfg = O.make_cfg(k, nc, box=(1.0, 0.75, 1.25))
+    qp = synth.uniform_state(nc, nodes(k), rho=1.3, vel=(0.7, -0.4, 0.25), p=0.8)
+    y = O.project(cfg, qp)
+    r = O.rhs(cfg, y)
+    assert np.abs(r).max() < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_conservation(k):
+    """Only the surface term couples cells (Sec. 2.3): the cell-mean rows of R sum to zero."""
+    cfg, y = turb_state(k, 6)
+    r = O.rhs(cfg, y)
+    s = r[:, 0].reshape(5, -1).sum(axis=1)
+    scale = np.abs(r[:, 0]).reshape(5, -1).sum(axis=1)
+    assert np.all(np.abs(s) <= 1e-13 * scale + 1e-14)
+    t0 = O.totals(cfg, y)
+    y1, _ = O.step(cfg, y, 0.0, 3)
+    np.testing.assert_allclose(O.totals(cfg, y1), t0, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_linear_advection_special_case(k):
+    """Uniform p and v: the Euler system reduces to linear advection of rho; the
+    scheme keeps m = rho v and E = p/(g-1) + rho |v|^2/2 exactly, mode by mode."""
+    nc = 5
+    cfg = O.make_cfg(k, nc)
+    y = O.project(cfg, synth.advected_wave(nc, nodes(k), gamma=G))
+    y1, _ = O.step(cfg, y, 0.0, 4)
+    for a in range(3):
+        np.testing.assert_allclose(y1[1 + a], y1[0], atol=1e-14)
+    want_E = 1.5 * y1[0]
+    want_E[0] += 1.0 / (G - 1)
+    np.testing.assert_allclose(y1[4], want_E, atol=1e-13)
+
+
+def l2_error_vs_exact(cfg, y, t):
+    """Continuous L2 error of rho against the exact advected wave, with a (k+3)^3 rule."""
+    k = cfg.k
+    m = k + 3
+    x, w = O.gauss_legendre(m)
+    nc = cfg.n[0]
+    ex = synth.advected_wave(nc, x, gamma=G, t=t)[0]  # [c][b][a][z][y][x]
+    err = 0.0
+    for c, b, a in itertools.product(range(m), repeat=3):
+        ph = O.basis(k, [x[a], x[b], x[c]])
+        num = np.einsum("l...,l->...", y[0], ph)
+        err += (w[a] * w[b] * w[c] / 8.0) * ((num - ex[c, b, a]) ** 2).sum()
+    return math.sqrt(err / nc ** 3)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_convergence_order_k_plus_1(k):
+    """Sec. 2: spatial order p = k+1 on the smooth advected wave."""
+    T = 0.02
+    errs = []
+    sizes = [4, 8, 16]
+    for nc in sizes:
+        cfg = O.make_cfg(k, nc)
+        y = O.project(cfg, synth.advected_wave(nc, nodes(k), gamma=G))
+        dx = 1.0 / nc
+        # SSP-RK3 is third order: for k = 3 shrink dt like dx^(4/3)
+        h = 0.3 / (2 * k + 1) * dx / (3 * (1.0 + math.sqrt(G))) * (dx / 0.25) ** (1.0 / 3.0 if k == 3 else 0.0)
+        ns = int(math.ceil(T / h))
+        y1, t = O.step(cfg, y, T / ns, ns)
+        errs.append(l2_error_vs_exact(cfg, y1, t))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert rates[-1] > k + 1 - 0.3, (errs, rates)
+
+
+def test_rk3_amplification_factor():
+    """k = 0 with uniform v: one Fourier mode of rho is an eigenvector of the
+    upwind operator; one SSP-RK3 step multiplies it by 1 + z + z^2/2 + z^3/6."""
+    nc = 8
+    cfg = O.make_cfg(0, nc)
+    v = np.array([1.0, 0.5, 0.25])
+    x = nodes(0)
+    qp = synth.advected_wave(nc, x, gamma=G, vel=tuple(v))
+    y = O.project(cfg, qp)
+    h = 0.01
+    y1, _ = O.step(cfg, y, h, 1)
+    # complex Fourier coefficient of the rho perturbation for mode (1,1,1)
+    idx = np.arange(nc)
+    e = np.exp(-2j * np.pi * (idx[None, None, :] + idx[None, :, None] + idx[:, None, None]) / nc)
+    c0 = (y[0, 0] * e).sum()
+    c1 = (y1[0, 0] * e).sum()
+    th = 2 * np.pi / nc
+    lam = -sum(vi * nc * (1 - np.exp(-1j * th)) for vi in v)
+    z = lam * h
+    np.testing.assert_allclose(c1 / c0, 1 + z + z * z / 2 + z ** 3 / 6, rtol=1e-12)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_dt_closed_form_uniform(k):
+    nc = (4, 5, 6)
+    box = (1.0, 2.0, 0.5)
+    cfg = O.make_cfg(k, nc, box=box, cfl=0.4)
+    vel = (0.3, -0.5, 0.2)
+    y = O.project(cfg, synth.uniform_state(nc, nodes(k), rho=1.2, vel=vel, p=0.7))
+    c = math.sqrt(G * 0.7 / 1.2)
+    rate = sum((abs(vel[a]) + c) / (box[a] / nc[a]) for a in range(3))
+    assert O.dt(cfg, y) == pytest.approx(0.4 / (2 * k + 1) / rate, rel=1e-14)
+
+
+def test_dt_advected_wave_first_step():
+    """Config-1 start: dt from the 2-point-Gauss cell means; p-bar = 1 and
+    v-bar = (1,1,1) in every cell, so dt = C/3 * dx / (3 (1 + c_max))."""
+    cfg = O.make_cfg(1, 16)
+    x = nodes(1)
+    y = O.project(cfg, synth.advected_wave(16, x, gamma=G))
+    rho_bar = y[0, 0]
+    # independent: 2-point Gauss mean of the density in each cell
+    X = (np.arange(16)[:, None] + 0.5 * (1 + x[None, :])) / 16  # [cell, gauss]
+    ph = X[:, None, None, :, None, None] + X[None, :, None, None, :, None] + X[None, None, :, None, None, :]
+    mean = (1 + 0.1 * np.sin(2 * np.pi * ph)).mean(axis=(3, 4, 5))
+    np.testing.assert_allclose(np.transpose(rho_bar, (2, 1, 0)), mean, atol=1e-15)
+    cmax = math.sqrt(G / mean.min())
+    dt = 0.3 / 3 * (1 / 16) / (3 * (1 + cmax))
+    assert O.dt(cfg, y) == pytest.approx(dt, rel=1e-13)
+    assert dt == pytest.approx(8.8353e-4, rel=1e-4)
