@@ -1,0 +1,216 @@
+"""Benchmark of the DG hot path on one MI355X.
+
+Workload (one "step" = one SSP-RK3 step of dg_step: the CFL reduction and three
+fused stage launches): modal DG, k = 3 (20 modes, 4^3 Gauss points), 256^3
+cells, periodic unit box, gamma = 5/3, the seeded turbulence surrogate at rms
+Mach 0.3 (synthetic: solenoidal k^-5/3 velocity field, rho = p = 1), with the
+solenoidal Ornstein-Uhlenbeck driving on 1 <= |n| <= 3 when the library
+supports it.
+
+Metric: DOF-updates/s per RK stage = 5 N(k) cells * 3 * steps / elapsed, for
+the FP32-grade tier (value) with the FP64 path and the BF16 tier reported
+beside it.  Roofline of the stage kernel from HIP events around each launch on
+the library's stream; algorithmic bytes per launch as in the design doc.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--k 3]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=256)
+    p.add_argument("--k", type=int, default=3)
+    p.add_argument("--tiers", default="bf16x3,fp32,bf16,fp64")
+    p.add_argument("--primary", default="auto", help="tier reported as value (auto: fastest FP32-grade)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
+    p.add_argument("--quiet", action="store_true")
+    return p.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(N, cells, elem):
+    """Algorithmic HBM bytes of the three stages of one step: stage 1 reads y and
+    writes y1 (2 states); stages 2 and 3 read y^(s), y^(0) and write (3 states)."""
+    st = 5 * N * cells * elem
+    return [2 * st, 3 * st, 3 * st]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dg_kernels.hip", "dg_host.cpp", "dg_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1602_09079_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measure_tier(args, dg, torch, prec, qp_dev, n, k):
+    s = dg.Solver(k, n, precision=prec, cfl=0.3)
+    y = s.project(qp_dev.to(s.dtype))
+    N = s.N
+    cells = n ** 3
+    torch.cuda.synchronize()
+    # warmup
+    for _ in range(args.warmup):
+        s.step_async(y, 1, 0.0)
+    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps of dg_step
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s.stream)
+    s.step_async(y, args.steps, 0.0)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    dof_stage = 5 * N * cells
+    rate = dof_stage * 3 * args.steps / (ms / 1e3)
+    # per-launch durations of the stage kernel (events around each dg_stage call)
+    w1 = torch.empty_like(y)
+    w2 = torch.empty_like(y)
+    h = s.dt(y)
+    evs = []
+    for rep in range(max(2, args.steps)):
+        trip = []
+        for (y0, yin, out, a, b) in ((y, y, w1, 0.0, 1.0), (y, w1, w2, 0.75, 0.25), (y, w2, w1, 1 / 3, 2 / 3)):
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(s.stream)
+            s.stage(y0, yin, out, a, b, h)
+            eb.record(s.stream)
+            trip.append((ea, eb))
+        evs.append(trip)
+    torch.cuda.synchronize()
+    durs = [[ea.elapsed_time(eb) for ea, eb in trip] for trip in evs]
+    avg_stage_ms = sum(sum(t) for t in durs) / (3 * len(durs))
+    elem = 8 if prec == "fp64" else 4
+    sb = stage_bytes(N, cells, elem)
+    achieved = (sum(sb) / 3) / (avg_stage_ms / 1e3) / 1e9
+    finite = bool(torch.isfinite(y).all().item())
+    del w1, w2
+    out = dict(prec=prec, ms_per_step=ms_step, wall_s=wall, dof_updates_per_s=rate, stage_ms=avg_stage_ms,
+               stage_ms_each=[sum(t[i] for t in durs) / len(durs) for i in range(3)],
+               achieved_GBs=achieved, bytes_per_stage_avg=sum(sb) / 3, finite=finite)
+    log(args, f"[bench] {prec}: {ms_step:.3f} ms/step, {rate:.3e} DOF-updates/s/stage, stage {avg_stage_ms:.3f} ms, "
+              f"{achieved:.0f} GB/s algorithmic, finite={finite}")
+    del s, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(args, k):
+    """Oracle (FP64 C, OpenMP) on a bounded sample: one SSP stage on a cpu_n^3 mesh."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1602_09079_amd import synth
+    n = args.cpu_n
+    cfg = O.make_cfg(k, n)
+    x = O.gauss_legendre(k + 1)[0]
+    y = O.project(cfg, synth.turbulence(n, x, seed=9079, mach=0.3).numpy())
+    h = O.dt(cfg, y)
+    O.stage(cfg, y, y, 0.0, 1.0, h)  # warm-up
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.stage(cfg, y, y, 0.0, 1.0, h)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or reps >= 20:
+            break
+    per_stage = el / reps
+    dof = 5 * O.nmodes(k) * n ** 3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=dof / per_stage, unit="DOF-updates/s per RK stage", cores=threads, kind="oracle",
+                sample=f"{reps} SSP stage(s) of the FP64 oracle, k={k}, {n}^3 cells (same per-cell work as the "
+                       f"workload), {per_stage:.3f} s per stage, OMP threads={threads}")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (see DESIGN.md for how the "
+                                   "path would shard)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1602_09079_amd import dg, synth
+    dg.lib()
+    torch.cuda.set_device(0)
+    k, n = args.k, args.n
+    x = dg.gauss_nodes(k + 1)
+    log(args, f"[bench] generating turbulence surrogate k={k} n={n}")
+    qp = synth.turbulence(n, x, seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    results = {}
+    for prec in args.tiers.split(","):
+        results[prec] = measure_tier(args, dg, torch, prec, qp, n, k)
+    del qp
+    torch.cuda.empty_cache()
+    fp32_grade = [p for p in ("bf16x3", "fp32") if p in results]
+    primary = args.primary if args.primary != "auto" else max(fp32_grade or list(results),
+                                                               key=lambda p: results[p]["dof_updates_per_s"])
+    r = results[primary]
+    N = dg.nmodes(k)
+    roof = dict(bound="hbm", achieved=round(r["achieved_GBs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4), traffic=None)
+    tf = os.path.join(ROOT, "profiles", f"traffic_stage_k{k}_n{n}_{primary}.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        if t.get("source_hash") == kernel_source_hash():
+            roof["traffic"] = t.get("bytes_per_launch")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(args, "[bench] timing the oracle on the host")
+        cpu = cpu_baseline(args, k)
+    line = {
+        "metric": "DOF-updates/s per RK stage",
+        "value": r["dof_updates_per_s"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"modal DG Euler k={k} ({N} modes, {(k + 1) ** 3} Gauss pts), {n}^3 cells, periodic "
+                               f"unit box, gamma=5/3, turbulence surrogate Mach 0.3, SSP-RK3 with device CFL dt 0.3",
+                   "k": k, "cells": n ** 3, "dof": 5 * N * n ** 3, "tier": primary,
+                   "forcing": False},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "tiers": {p: {"dof_updates_per_s": v["dof_updates_per_s"], "ms_per_step": v["ms_per_step"],
+                      "stage_ms": v["stage_ms"], "hbm_frac": round(v["achieved_GBs"] / HBM_PEAK_GBS, 4)}
+                  for p, v in results.items()},
+    }
+    if "fp64" in results:
+        line["speedup_vs_fp64"] = r["dof_updates_per_s"] / results["fp64"]["dof_updates_per_s"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

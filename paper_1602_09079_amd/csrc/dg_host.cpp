@@ -1,0 +1,580 @@
+// Host half of libdgmi.so: configuration checks, quadrature and basis tables
+// (Sec. 2.1-2.2 of arXiv 1602.09079) and the C ABI declared in include/dg.h.
+//
+// The tables come from closed forms: Gauss-Legendre nodes and weights for
+// n <= 5 and the explicit Legendre polynomials of degree <= 4.  They are
+// rearranged on the host into the per-lane operand order of the MFMA
+// instructions the stage kernel issues, so that the kernel's loads from LDS are
+// contiguous and the chained products need no data movement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+
+using namespace dgmi;
+
+namespace {
+
+// ---------------------------------------------------------------- closed-form quadrature
+
+bool gauss_rule(int n, double *x, double *w) {
+    switch (n) {
+        case 1: x[0] = 0.0; w[0] = 2.0; return true;
+        case 2: {
+            const double a = 1.0 / std::sqrt(3.0);
+            x[0] = -a; x[1] = a; w[0] = w[1] = 1.0;
+            return true;
+        }
+        case 3: {
+            const double a = std::sqrt(0.6);
+            x[0] = -a; x[1] = 0.0; x[2] = a;
+            w[0] = w[2] = 5.0 / 9.0; w[1] = 8.0 / 9.0;
+            return true;
+        }
+        case 4: {
+            const double r = 2.0 / 7.0 * std::sqrt(6.0 / 5.0);
+            const double xi = std::sqrt(3.0 / 7.0 - r), xo = std::sqrt(3.0 / 7.0 + r);
+            const double wi = (18.0 + std::sqrt(30.0)) / 36.0, wo = (18.0 - std::sqrt(30.0)) / 36.0;
+            x[0] = -xo; x[1] = -xi; x[2] = xi; x[3] = xo;
+            w[0] = wo; w[1] = wi; w[2] = wi; w[3] = wo;
+            return true;
+        }
+        case 5: {
+            const double r = 2.0 * std::sqrt(10.0 / 7.0);
+            const double xi = std::sqrt(5.0 - r) / 3.0, xo = std::sqrt(5.0 + r) / 3.0;
+            const double wi = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0, wo = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+            x[0] = -xo; x[1] = -xi; x[2] = 0.0; x[3] = xi; x[4] = xo;
+            w[0] = wo; w[1] = wi; w[2] = 128.0 / 225.0; w[3] = wi; w[4] = wo;
+            return true;
+        }
+        default: return false;
+    }
+}
+
+// explicit Legendre polynomials P_u and derivatives, u <= 4, times sqrt(2u+1)
+double leg(int u, double x) {
+    double p;
+    switch (u) {
+        case 0: p = 1.0; break;
+        case 1: p = x; break;
+        case 2: p = 0.5 * (3.0 * x * x - 1.0); break;
+        case 3: p = 0.5 * (5.0 * x * x * x - 3.0 * x); break;
+        default: p = 0.125 * (35.0 * x * x * x * x - 30.0 * x * x + 3.0); break;
+    }
+    return std::sqrt(2.0 * u + 1.0) * p;
+}
+double dleg(int u, double x) {
+    double p;
+    switch (u) {
+        case 0: p = 0.0; break;
+        case 1: p = 1.0; break;
+        case 2: p = 3.0 * x; break;
+        case 3: p = 0.5 * (15.0 * x * x - 3.0); break;
+        default: p = 0.5 * (35.0 * x * x * x - 15.0 * x); break;
+    }
+    return std::sqrt(2.0 * u + 1.0) * p;
+}
+
+struct Basis {
+    int k, N, n, Q, P;
+    double xg[5], wg[5];
+    std::vector<int> u, v, w;  // degrees per mode
+    explicit Basis(int k_) : k(k_), N(nmodes_of(k_)), n(k_ + 1), Q(n * n * n), P(n * n) {
+        gauss_rule(n, xg, wg);
+        for (int d = 0; d <= k; d++)          // graded by total degree,
+            for (int a = d; a >= 0; a--)      // then x-degree descending,
+                for (int b = d - a; b >= 0; b--) {  // then y-degree descending
+                    u.push_back(a);
+                    v.push_back(b);
+                    w.push_back(d - a - b);
+                }
+    }
+    void point(int q, double xi[3]) const {  // volume point q = (c n + b) n + a
+        xi[0] = xg[q % n];
+        xi[1] = xg[(q / n) % n];
+        xi[2] = xg[q / (n * n)];
+    }
+    double weight(int q) const { return wg[q % n] * wg[(q / n) % n] * wg[q / (n * n)]; }
+    void face_point(int face, int p, double xi[3]) const {
+        // face = 2*axis + side; points run over the other two axes, lower axis fastest
+        const int axis = face / 2;
+        const int o0 = axis == 0 ? 1 : 0, o1 = axis == 2 ? 1 : 2;
+        xi[axis] = (face & 1) ? 1.0 : -1.0;
+        xi[o0] = xg[p % n];
+        xi[o1] = xg[p / n];
+    }
+    double face_weight(int p) const { return wg[p % n] * wg[p / n]; }
+    double phi(int l, const double xi[3]) const { return leg(u[l], xi[0]) * leg(v[l], xi[1]) * leg(w[l], xi[2]); }
+    double dphi(int l, int a, const double xi[3]) const {
+        return (a == 0 ? dleg(u[l], xi[0]) : leg(u[l], xi[0])) * (a == 1 ? dleg(v[l], xi[1]) : leg(v[l], xi[1])) *
+               (a == 2 ? dleg(w[l], xi[2]) : leg(w[l], xi[2]));
+    }
+};
+
+uint16_t bf16_rne(float f) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+float bf16_to_float(uint16_t h) {
+    uint32_t b = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+// Build the MFMA operand tables.  Each fragment holds, for each of the 64
+// lanes, the kpl values that lane feeds to one MFMA as its A operand:
+// row = lane % 16, contraction index = (lane / 16) * kpl + j.
+std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
+    const Basis B(L.k);
+    const int N = L.N, Q = L.Q, P = L.P, kpl = L.kpl;
+    std::vector<double> val((size_t)L.nfrag * 64 * kpl, 0.0);
+    auto at = [&](int frag, int lane, int j) -> double & { return val[((size_t)frag * 64 + lane) * kpl + j]; };
+    auto vol_point = [&](int chunk, int g, int j) {  // volume point fed at contraction slot (g, j) of a chunk
+        if (kpl == 1) return 16 * (chunk / 4) + out_row(L.prec, g, chunk % 4);
+        const int t = 2 * chunk + (j >= 4), r = j & 3;
+        return 16 * t + out_row(L.prec, g, r);
+    };
+    auto face_slot = [&](int chunk, int g, int j, int &face) {  // (face, point) at slot (g, j)
+        if (kpl == 1) {
+            face = chunk / 4;
+            return out_row(L.prec, g, chunk % 4);
+        }
+        face = 2 * chunk + (j >= 4);
+        return out_row(L.prec, g, j & 3);
+    };
+    double xi[3];
+    for (int lane = 0; lane < 64; lane++) {
+        const int row = lane % 16, g = lane / 16;
+        for (int j = 0; j < kpl; j++) {
+            const int kk = g * kpl + j;
+            // T1: Phi[q][m]
+            for (int t = 0; t < L.rt1; t++)
+                for (int st = 0; st < L.ks1; st++) {
+                    const int q = 16 * t + row, m = st * L.kstep + kk;
+                    if (q < Q && m < N) {
+                        B.point(q, xi);
+                        at(L.off1 + t * L.ks1 + st, lane, j) = B.phi(m, xi);
+                    }
+                }
+            // T2: -s_a dPhi_a[m][q] w_q
+            for (int rt = 0; rt < L.rt2; rt++)
+                for (int a = 0; a < 3; a++)
+                    for (int c = 0; c < L.nc2; c++) {
+                        const int m = 16 * rt + row, q = vol_point(c, g, j);
+                        if (q < Q && m < N) {
+                            B.point(q, xi);
+                            at(L.off2 + (rt * 3 + a) * L.nc2 + c, lane, j) = -s[a] * B.dphi(m, a, xi) * B.weight(q);
+                        }
+                    }
+            // T3: Phi[face point][m]
+            for (int f = 0; f < 6; f++)
+                for (int st = 0; st < L.ks1; st++) {
+                    const int p = row, m = st * L.kstep + kk;
+                    if (p < P && m < N) {
+                        B.face_point(f, p, xi);
+                        at(L.off3 + f * L.ks1 + st, lane, j) = B.phi(m, xi);
+                    }
+                }
+            // T4: s_a (+-1) Phi[m][face point] w_p  (outward normal)
+            for (int rt = 0; rt < L.rt2; rt++)
+                for (int c = 0; c < L.nc4; c++) {
+                    int f;
+                    const int p = face_slot(c, g, j, f);
+                    const int m = 16 * rt + row;
+                    if (p < P && m < N) {
+                        B.face_point(f, p, xi);
+                        const double sg = (f & 1) ? 1.0 : -1.0;
+                        at(L.off4 + rt * L.nc4 + c, lane, j) = s[f / 2] * sg * B.phi(m, xi) * B.face_weight(p);
+                    }
+                }
+            // T5: -Phi[m][q] w_q / 8  (source projection)
+            for (int rt = 0; rt < L.rt2; rt++)
+                for (int c = 0; c < L.nc2; c++) {
+                    const int m = 16 * rt + row, q = vol_point(c, g, j);
+                    if (q < Q && m < N) {
+                        B.point(q, xi);
+                        at(L.off5 + rt * L.nc2 + c, lane, j) = -B.phi(m, xi) * B.weight(q) / 8.0;
+                    }
+                }
+        }
+    }
+    std::vector<char> blob(L.bytes(), 0);
+    const size_t cnt = val.size();
+    if (L.prec == DG_FP64) {
+        std::memcpy(blob.data(), val.data(), cnt * 8);
+    } else if (L.prec == DG_FP32) {
+        float *o = reinterpret_cast<float *>(blob.data());
+        for (size_t i = 0; i < cnt; i++) o[i] = (float)val[i];
+    } else {
+        uint16_t *o = reinterpret_cast<uint16_t *>(blob.data());
+        for (size_t i = 0; i < cnt; i++) {
+            const uint16_t hi = bf16_rne((float)val[i]);
+            o[i] = hi;
+            if (L.ntab == 2) o[cnt + i] = bf16_rne((float)(val[i] - (double)bf16_to_float(hi)));
+        }
+    }
+    return blob;
+}
+
+const char *kNoCtx = "invalid or NULL dg_ctx";
+
+dg_status hip_fail(dg_ctx *c, hipError_t e, const char *what) {
+    if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return DG_ERR_HIP;
+}
+
+#define HIPCHK(ctx, call)                                      \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+size_t elem_bytes(const dg_ctx *c) { return c->cfg.precision == DG_FP64 ? 8 : 4; }
+
+}  // namespace
+
+namespace dgmi {
+
+TableLayout make_layout(int k, int prec) {
+    TableLayout L{};
+    L.k = k;
+    L.prec = prec;
+    L.N = nmodes_of(k);
+    L.n = k + 1;
+    L.Q = L.n * L.n * L.n;
+    L.P = L.n * L.n;
+    L.kpl = (prec == DG_BF16 || prec == DG_BF16X3) ? 8 : 1;
+    L.kstep = 4 * L.kpl;
+    L.ks1 = (L.N + L.kstep - 1) / L.kstep;
+    L.rt1 = L.kpl == 8 ? 2 * ((L.Q + 31) / 32) : (L.Q + 15) / 16;
+    L.rt2 = (L.N + 15) / 16;
+    L.nc2 = L.kpl == 8 ? L.rt1 / 2 : L.rt1 * 4;
+    L.nc4 = L.kpl == 8 ? 3 : 24;
+    L.off1 = 0;
+    L.off2 = L.off1 + L.rt1 * L.ks1;
+    L.off3 = L.off2 + L.rt2 * 3 * L.nc2;
+    L.off4 = L.off3 + 6 * L.ks1;
+    L.off5 = L.off4 + L.rt2 * L.nc4;
+    L.nfrag = L.off5 + L.rt2 * L.nc2;
+    L.ntab = prec == DG_BF16X3 ? 2 : 1;
+    L.elem = prec == DG_FP64 ? 8 : (prec == DG_FP32 ? 4 : 2);
+    return L;
+}
+
+}  // namespace dgmi
+
+hipError_t stage_occupancy(int k, int prec, int lds_bytes, int *blocks_per_cu);
+
+// ====================================================================== ABI
+
+extern "C" {
+
+int32_t dg_nmodes(int32_t k) { return k >= 0 ? nmodes_of(k) : 0; }
+
+dg_status dg_gauss_nodes(int32_t n, double *xi) {
+    double w[5];
+    if (!xi || n < 1 || n > 5) return DG_ERR_ARG;
+    gauss_rule(n, xi, w);
+    return DG_OK;
+}
+
+const char *dg_error_string(const dg_ctx *ctx) { return ctx ? ctx->err.c_str() : kNoCtx; }
+
+dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
+    if (!cfg || !out) return DG_ERR_ARG;
+    *out = nullptr;
+    if (cfg->k < 1) return DG_ERR_ARG;
+    for (int a = 0; a < 3; a++)
+        if (cfg->n[a] < 2 || !(cfg->box[a] > 0.0) || !std::isfinite(cfg->box[a])) return DG_ERR_ARG;
+    if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
+    if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
+    if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
+    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CHECK_RANGE)) return DG_ERR_ARG;
+    if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
+    const long long ncells = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    if ((long long)cfg->n[0] > (1LL << 30) || ncells > (1LL << 40)) return DG_ERR_ARG;
+
+    dg_ctx *c = new (std::nothrow) dg_ctx();
+    if (!c) return DG_ERR_HIP;
+    c->cfg = *cfg;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->N = nmodes_of(cfg->k);
+    c->n = cfg->k + 1;
+    c->Q = c->n * c->n * c->n;
+    c->P = c->n * c->n;
+    c->ncells = ncells;
+    double s[3];
+    for (int a = 0; a < 3; a++) {
+        c->h[a] = cfg->box[a] / cfg->n[a];
+        s[a] = 1.0 / (4.0 * c->h[a]);  // (dx^2/4) / |K| of eqs. dg:eqn:volume_int and dg:eqn:surface_int
+    }
+    c->lay = make_layout(cfg->k, cfg->precision);
+    auto fail = [&](dg_status st) {
+        dg_destroy(c);
+        return st;
+    };
+    const std::vector<char> blob = build_tables(c->lay, s);
+    if (hipMalloc(&c->tables, blob.size()) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipMemcpy(c->tables, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+    // projection table: phi_l(xi_q) w_q / 8
+    {
+        const Basis B(cfg->k);
+        std::vector<double> pt((size_t)c->Q * c->N);
+        double xi[3];
+        for (int q = 0; q < c->Q; q++) {
+            B.point(q, xi);
+            for (int l = 0; l < c->N; l++) pt[(size_t)q * c->N + l] = B.phi(l, xi) * B.weight(q) / 8.0;
+        }
+        if (hipMalloc(&c->ptab, pt.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
+        if (hipMemcpy(c->ptab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+    }
+    c->nparts = 1024;
+    if (hipMalloc(&c->slots, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipMemset(c->slots, 0, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipMalloc(&c->flag, sizeof(int)) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
+    c->lds = (int)c->lay.bytes();
+    if (set_stage_attributes(cfg->k, cfg->precision, c->lds) != hipSuccess) return fail(DG_ERR_HIP);
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return fail(DG_ERR_HIP);
+    if (stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    const long long nbx = (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
+    const long long nblocks = nbx * cfg->n[1] * cfg->n[2];
+    const int waves_per_wg = stage_block_threads() / 64;
+    long long grid = (long long)per_cu * ncu;
+    grid = std::min(grid, (nblocks + waves_per_wg - 1) / waves_per_wg);
+    if (grid >= 8) grid -= grid % 8;
+    c->grid = (int)std::max(1LL, grid);
+    *out = c;
+    return DG_OK;
+}
+
+dg_status dg_destroy(dg_ctx *c) {
+    if (!c) return DG_OK;
+    if (c->tables) hipFree(c->tables);
+    if (c->ptab) hipFree(c->ptab);
+    if (c->slots) hipFree(c->slots);
+    if (c->flag) hipFree(c->flag);
+    if (c->partials) hipFree(c->partials);
+    if (c->fmodes) hipFree(c->fmodes);
+    delete c;
+    return DG_OK;
+}
+
+size_t dg_state_count(const dg_ctx *c) { return c ? (size_t)NF * c->N * (size_t)c->ncells : 0; }
+
+size_t dg_workspace_bytes(const dg_ctx *c) { return c ? 2 * dg_state_count(c) * elem_bytes(c) : 0; }
+
+dg_status dg_project(dg_ctx *c, const void *qp, void *y) {
+    if (!c) return DG_ERR_ARG;
+    if (!qp || !y) {
+        c->err = "dg_project: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    HIPCHK(c, launch_project(c->cfg.k, c->cfg.precision, qp, y, c->ptab, c->ncells, c->stream));
+    return DG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, double a, double b, double dt, int mode,
+                    bool advance_time) {
+    if ((c->cfg.flags & DG_FORCING) && !c->have_forcing) {
+        c->err = "DG_FORCING set but dg_set_forcing was not called";
+        return DG_ERR_STATE;
+    }
+    StageArgs s{};
+    s.yin = yin;
+    s.y0 = y0 ? y0 : yin;
+    s.out = out;
+    s.tables = c->tables;
+    s.rate = (mode == 1 && dt <= 0.0) ? c->slots + c->cur_slot : nullptr;
+    s.tacc = advance_time ? c->slots + 2 : nullptr;
+    s.dt = dt;
+    s.a = a;
+    s.b = b;
+    s.dtfac = c->cfg.cfl / (2.0 * c->cfg.k + 1.0);
+    s.gamma = c->cfg.gamma;
+    s.nx = c->cfg.n[0];
+    s.ny = c->cfg.n[1];
+    s.nz = c->cfg.n[2];
+    s.nbx = (c->cfg.n[0] + BLK_INNER - 1) / BLK_INNER;
+    s.nblocks = (long long)s.nbx * s.ny * s.nz;
+    s.ncells = c->ncells;
+    s.mode = mode;
+    s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;
+    s.fmodes = c->fmodes;
+    s.nfmodes = c->nfmodes;
+    for (int i = 0; i < 3; i++) s.h[i] = c->h[i];
+    HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
+    return DG_OK;
+}
+
+// CFL rate into the free slot; it becomes the current one.
+dg_status run_cfl(dg_ctx *c, const void *y) {
+    const int nxt = 1 - c->cur_slot;
+    HIPCHK(c, launch_cfl(c->cfg.precision, y, c->N, c->ncells, c->cfg.gamma, c->h, c->slots + nxt,
+                         c->slots + c->cur_slot, c->stream));
+    c->cur_slot = nxt;
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_rhs(dg_ctx *c, const void *y, void *r) {
+    if (!c) return DG_ERR_ARG;
+    if (!y || !r || y == r) {
+        c->err = "dg_rhs: NULL or aliased pointers";
+        return DG_ERR_ARG;
+    }
+    return run_stage(c, nullptr, y, r, 0.0, 1.0, 0.0, 0, false);
+}
+
+dg_status dg_stage(dg_ctx *c, const void *y0, const void *yin, void *out, double a, double b, double dt) {
+    if (!c) return DG_ERR_ARG;
+    if (!yin || !out || out == yin || (a != 0.0 && !y0)) {
+        c->err = "dg_stage: NULL or aliased pointers";
+        return DG_ERR_ARG;
+    }
+    return run_stage(c, y0, yin, out, a, b, dt, 1, false);
+}
+
+dg_status dg_dt(dg_ctx *c, const void *y, double *dt) {
+    if (!c) return DG_ERR_ARG;
+    if (!y || !dt) {
+        c->err = "dg_dt: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    dg_status st = run_cfl(c, y);
+    if (st != DG_OK) return st;
+    double rate = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&rate, c->slots + c->cur_slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *dt = c->cfg.cfl / (2.0 * c->cfg.k + 1.0) / rate;
+    return DG_OK;
+}
+
+dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, double *t_inout) {
+    if (!c) return DG_ERR_ARG;
+    if (!y || !work || nsteps < 0) {
+        c->err = "dg_step: NULL pointer or negative step count";
+        return DG_ERR_ARG;
+    }
+    const size_t sb = dg_state_count(c) * elem_bytes(c);
+    void *w1 = work;
+    void *w2 = static_cast<char *>(work) + sb;
+    const bool dev_dt = !(dt > 0.0);
+    if (dev_dt && t_inout) {
+        double t0 = 0.0;
+        HIPCHK(c, hipMemcpyAsync(c->slots + 2, &t0, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    }
+    const bool check = (c->cfg.flags & DG_CHECK_RANGE) != 0;
+    for (int it = 0; it < nsteps; it++) {
+        dg_status st;
+        if (dev_dt && (st = run_cfl(c, y)) != DG_OK) return st;
+        if ((st = run_stage(c, y, y, w1, 0.0, 1.0, dt, 1, false)) != DG_OK) return st;
+        if ((st = run_stage(c, y, w1, w2, 0.75, 0.25, dt, 1, false)) != DG_OK) return st;
+        if ((st = run_stage(c, y, w2, y, 1.0 / 3.0, 2.0 / 3.0, dt, 1, dev_dt && t_inout)) != DG_OK) return st;
+        if (check) {
+            int flag = 0;
+            HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+            HIPCHK(c, launch_range_check(c->cfg.precision, y, c->N, c->ncells, c->cfg.gamma, c->flag, c->stream));
+            HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (flag) {
+                if (t_inout && !dev_dt) *t_inout += dt * (it + 1);
+                c->err = "non-physical cell mean (rho <= 0, p <= 0 or non-finite) after step " + std::to_string(it + 1);
+                return DG_ERR_RANGE;
+            }
+        }
+    }
+    if (t_inout) {
+        if (dev_dt) {
+            double tt = 0.0;
+            HIPCHK(c, hipMemcpyAsync(&tt, c->slots + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            *t_inout += tt;
+        } else {
+            *t_inout += dt * nsteps;
+        }
+    }
+    return DG_OK;
+}
+
+dg_status dg_totals(dg_ctx *c, const void *y, double out[5]) {
+    if (!c) return DG_ERR_ARG;
+    if (!y || !out) {
+        c->err = "dg_totals: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    const double vol = c->h[0] * c->h[1] * c->h[2];
+    double *dres = c->partials + (size_t)NF * c->nparts;
+    HIPCHK(c, launch_totals(c->cfg.precision, y, c->N, c->ncells, vol, c->partials, c->nparts, dres, c->stream));
+    HIPCHK(c, hipMemcpyAsync(out, dres, NF * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+dg_status dg_set_forcing(dg_ctx *c, int32_t nmodes, const int32_t *nvec, const double *ahat) {
+    if (!c) return DG_ERR_ARG;
+    if (nmodes < 0 || nmodes > MAX_FORCING_MODES || (nmodes > 0 && (!nvec || !ahat))) {
+        c->err = "dg_set_forcing: bad mode count or NULL table";
+        return DG_ERR_ARG;
+    }
+    // device table per mode: n_x, n_y, n_z (as doubles), then Re/Im of the three components
+    std::vector<double> t((size_t)std::max(nmodes, 1) * 9, 0.0);
+    for (int m = 0; m < nmodes; m++) {
+        for (int a = 0; a < 3; a++) t[9 * m + a] = (double)nvec[3 * m + a];
+        for (int j = 0; j < 6; j++) t[9 * m + 3 + j] = ahat[6 * m + j];
+    }
+    if (!c->fmodes) HIPCHK(c, hipMalloc(&c->fmodes, (size_t)MAX_FORCING_MODES * 9 * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(c->fmodes, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nfmodes = nmodes;
+    c->have_forcing = true;
+    return DG_OK;
+}
+
+dg_status dg_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const double *z, double f, double sigma,
+                       double a0, double kmin, double kmax, double *ahat) {
+    if (nmodes < 0 || (nmodes > 0 && (!nvec || !theta || !z || !ahat))) return DG_ERR_ARG;
+    if (!(f >= 0.0 && f <= 1.0) || !(kmax > kmin)) return DG_ERR_ARG;
+    const double mid = 0.5 * (kmin + kmax), half = 0.5 * (kmax - kmin);
+    const double kick = sigma * std::sqrt(1.0 - f * f);
+    for (int m = 0; m < nmodes; m++) {
+        double *th = theta + 6 * m;
+        for (int j = 0; j < 6; j++) th[j] = f * th[j] + kick * z[6 * m + j];
+        const double n0 = nvec[3 * m], n1 = nvec[3 * m + 1], n2 = nvec[3 * m + 2];
+        const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+        double prof = 0.0;
+        if (nn > 0.0) {
+            const double d = (std::sqrt(nn) - mid) / half;
+            prof = std::max(0.0, 1.0 - d * d);
+        }
+        for (int part = 0; part < 2; part++) {
+            const double vx = th[part], vy = th[2 + part], vz = th[4 + part];
+            const double dot = nn > 0.0 ? (n0 * vx + n1 * vy + n2 * vz) / nn : 0.0;
+            ahat[6 * m + 0 + part] = a0 * prof * (vx - n0 * dot);
+            ahat[6 * m + 2 + part] = a0 * prof * (vy - n1 * dot);
+            ahat[6 * m + 4 + part] = a0 * prof * (vz - n2 * dot);
+        }
+    }
+    return DG_OK;
+}
+
+}  // extern "C"

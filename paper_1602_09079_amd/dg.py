@@ -1,0 +1,241 @@
+"""ctypes binding of libdgmi.so (include/dg.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current stream.
+
+The library must have been built (``__graft_entry__.build()``); importing this
+module without it raises, there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgmi.so")
+
+DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_RANGE, DG_ERR_STATE = range(6)
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+DG_FORCING = 1
+DG_CHECK_RANGE = 4
+STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
+                5: "DG_ERR_STATE"}
+
+# every entry point declared in include/dg.h
+EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_project", "dg_rhs", "dg_stage",
+           "dg_dt", "dg_step", "dg_totals", "dg_set_forcing", "dg_ou_update", "dg_nmodes", "dg_gauss_nodes",
+           "dg_error_string"]
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "dg_init": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.POINTER(_vp)]),
+            "dg_destroy": (ctypes.c_int, [_vp]),
+            "dg_state_count": (ctypes.c_size_t, [_vp]),
+            "dg_workspace_bytes": (ctypes.c_size_t, [_vp]),
+            "dg_project": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_stage": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "dg_dt": (ctypes.c_int, [_vp, _vp, _dp]),
+            "dg_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _dp]),
+            "dg_totals": (ctypes.c_int, [_vp, _vp, _dp]),
+            "dg_set_forcing": (ctypes.c_int, [_vp, ctypes.c_int32, _ip, _dp]),
+            "dg_ou_update": (ctypes.c_int, [ctypes.c_int32, _ip, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
+            "dg_nmodes": (ctypes.c_int32, [ctypes.c_int32]),
+            "dg_gauss_nodes": (ctypes.c_int, [ctypes.c_int32, _dp]),
+            "dg_error_string": (ctypes.c_char_p, [_vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def nmodes(k):
+    return lib().dg_nmodes(k)
+
+
+def gauss_nodes(n):
+    import numpy as np
+    x = np.zeros(max(n, 1))
+    st = lib().dg_gauss_nodes(n, x.ctypes.data_as(_dp))
+    if st != DG_OK:
+        raise DGError(st, f"dg_gauss_nodes({n})")
+    return x
+
+
+def ou_update(nvec, theta, z, f, sigma, a0, kmin, kmax):
+    """Host-only OU driving update; returns (theta_new, ahat) as float64 arrays [m][3][2]."""
+    import numpy as np
+    nvec = np.ascontiguousarray(nvec, dtype=np.int32)
+    th = np.array(theta, dtype=np.float64, copy=True, order="C")
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    ahat = np.zeros_like(th)
+    st = lib().dg_ou_update(len(nvec), nvec.ctypes.data_as(_ip), th.ctypes.data_as(_dp), z.ctypes.data_as(_dp),
+                            f, sigma, a0, kmin, kmax, ahat.ctypes.data_as(_dp))
+    if st != DG_OK:
+        raise DGError(st, "dg_ou_update")
+    return th, ahat
+
+
+def make_config(k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0):
+    if isinstance(n, int):
+        n = (n, n, n)
+    c = Config()
+    c.k = k
+    for a in range(3):
+        c.n[a] = n[a]
+        c.box[a] = box[a]
+    c.gamma = gamma
+    c.cfl = cfl
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.flags = flags
+    return c
+
+
+def init_status(cfg):
+    """dg_init's status for cfg, destroying any context it made (used to test validation)."""
+    ctx = _vp()
+    st = lib().dg_init(ctypes.byref(cfg), None, ctypes.byref(ctx))
+    if st == DG_OK:
+        lib().dg_destroy(ctx)
+    return st
+
+
+class Solver:
+    """One DG context on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
+                 forcing=False, check_range=False, stream=None):
+        import torch
+        if forcing:
+            flags |= DG_FORCING
+        if check_range:
+            flags |= DG_CHECK_RANGE
+        self.cfg = make_config(k, n, box, gamma, cfl, precision, flags)
+        self.k = k
+        self.n = tuple(self.cfg.n)
+        self.precision = precision
+        self.dtype = torch.float64 if self.cfg.precision == 0 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = _vp()
+        st = lib().dg_init(ctypes.byref(self.cfg), _vp(self.stream.cuda_stream), ctypes.byref(self._ctx))
+        if st != DG_OK:
+            raise DGError(st, "dg_init failed")
+        self.N = nmodes(k)
+        self.nq = k + 1
+        self._work = None
+
+    def __del__(self):
+        try:
+            if self._ctx:
+                lib().dg_destroy(self._ctx)
+                self._ctx = _vp()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st, what):
+        if st != DG_OK:
+            msg = lib().dg_error_string(self._ctx)
+            raise DGError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def state_shape(self):
+        return (5, self.N, self.n[2], self.n[1], self.n[0])
+
+    def empty_state(self):
+        import torch
+        return torch.empty(self.state_shape(), dtype=self.dtype, device=self.device)
+
+    def _ptr(self, t, shape=None):
+        if t.dtype != self.dtype or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return _vp(t.data_ptr())
+
+    def workspace(self):
+        import torch
+        if self._work is None:
+            nb = lib().dg_workspace_bytes(self._ctx)
+            self._work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return self._work
+
+    # ------------------------------------------------------------ entry points
+    def project(self, qp, out=None):
+        """qp: [5][n][n][n][nz][ny][nx] point values at the Gauss offsets."""
+        q = self.nq
+        shape = (5, q, q, q, self.n[2], self.n[1], self.n[0])
+        y = self.empty_state() if out is None else out
+        self._check(lib().dg_project(self._ctx, self._ptr(qp, shape), self._ptr(y, self.state_shape())),
+                    "dg_project")
+        return y
+
+    def rhs(self, y, out=None):
+        r = self.empty_state() if out is None else out
+        self._check(lib().dg_rhs(self._ctx, self._ptr(y, self.state_shape()), self._ptr(r, self.state_shape())),
+                    "dg_rhs")
+        return r
+
+    def stage(self, y0, yin, out, a, b, dt):
+        p0 = self._ptr(y0, self.state_shape()) if y0 is not None else _vp()
+        self._check(lib().dg_stage(self._ctx, p0, self._ptr(yin, self.state_shape()),
+                                   self._ptr(out, self.state_shape()), a, b, dt), "dg_stage")
+        return out
+
+    def dt(self, y):
+        v = ctypes.c_double()
+        self._check(lib().dg_dt(self._ctx, self._ptr(y, self.state_shape()), ctypes.byref(v)), "dg_dt")
+        return v.value
+
+    def step(self, y, nsteps=1, dt=0.0, t=0.0):
+        """Advance y in place; returns the new time (synchronises when dt <= 0)."""
+        tt = ctypes.c_double(t)
+        w = self.workspace()
+        self._check(lib().dg_step(self._ctx, self._ptr(y, self.state_shape()), _vp(w.data_ptr()), dt, nsteps,
+                                  ctypes.byref(tt)), "dg_step")
+        return tt.value
+
+    def step_async(self, y, nsteps=1, dt=0.0):
+        """Advance y in place without reading back the time (no host synchronisation)."""
+        w = self.workspace()
+        self._check(lib().dg_step(self._ctx, self._ptr(y, self.state_shape()), _vp(w.data_ptr()), dt, nsteps,
+                                  None), "dg_step")
+
+    def totals(self, y):
+        import numpy as np
+        out = np.zeros(5)
+        self._check(lib().dg_totals(self._ctx, self._ptr(y, self.state_shape()), out.ctypes.data_as(_dp)),
+                    "dg_totals")
+        return out
+
+    def set_forcing(self, nvec, ahat):
+        import numpy as np
+        nvec = np.ascontiguousarray(nvec, dtype=np.int32).reshape(-1, 3)
+        ahat = np.ascontiguousarray(ahat, dtype=np.float64).reshape(-1, 3, 2)
+        self._check(lib().dg_set_forcing(self._ctx, len(nvec), nvec.ctypes.data_as(_ip), ahat.ctypes.data_as(_dp)),
+                    "dg_set_forcing")

@@ -1,0 +1,80 @@
+"""Host-only checks of libdgmi.so (no GPU needed): every symbol declared in
+include/dg.h is exported, configuration validation, and the host helpers
+(Gauss nodes, OU driving update) agree with the independent oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_09079_amd import dg, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(dg.LIB_PATH):
+        from paper_1602_09079_amd import build
+        build.build()
+    yield
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert header_functions() == sorted(dg.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported():
+    L = dg.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+
+
+def test_nmodes():
+    for k in range(5):
+        assert dg.nmodes(k) == O.nmodes(k)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_gauss_nodes_match_oracle(n):
+    np.testing.assert_allclose(dg.gauss_nodes(n), O.gauss_legendre(n)[0], atol=3e-16)
+
+
+def test_gauss_nodes_rejects_out_of_range():
+    for n in (0, 6, -1):
+        with pytest.raises(dg.DGError):
+            dg.gauss_nodes(n)
+
+
+def test_ou_update_matches_oracle():
+    nvec = synth.forcing_modes()
+    th = synth.ou_stationary_start(1602, len(nvec))
+    z = synth.ou_normals(1602, len(nvec), 3)
+    tg, to = th.copy(), th.copy()
+    for j in range(3):
+        tg, ag = dg.ou_update(nvec, tg, z[j], 0.9, 1.0, 0.7, 1.0, 3.0)
+        to, ao = O.ou_update(nvec, to, z[j], 0.9, 1.0, 0.7, 1.0, 3.0)
+        np.testing.assert_allclose(tg, to, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(ag, ao, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(k=0, n=8), dg.DG_ERR_ARG),
+    (dict(k=4, n=8), dg.DG_ERR_UNSUPPORTED),
+    (dict(k=1, n=(8, 1, 8)), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, box=(1.0, 0.0, 1.0)), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, gamma=1.0), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, cfl=0.0), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, cfl=1.5), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, precision=7), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, flags=2), dg.DG_ERR_ARG),
+])
+def test_config_validation(kw, status):
+    assert dg.init_status(dg.make_config(**kw)) == status
