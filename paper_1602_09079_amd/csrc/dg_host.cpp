@@ -131,21 +131,24 @@ float bf16_to_float(uint16_t h) {
     return f;
 }
 
-// Build the MFMA operand tables.  Each fragment holds, for each of the 64
-// lanes, the kpl values that lane feeds to one MFMA as its A operand:
-// row = lane % 16, contraction index = (lane / 16) * kpl + j.
+// Build the MFMA operand tables.  A fragment holds, for each of the 64 lanes,
+// the values that lane feeds to one MFMA as its A operand: row = lane % 16,
+// contraction index = (lane / 16) * kpl + j.  Contraction indices over volume
+// or face points are permuted to match the lane layout of the MFMA results that
+// are fed as B operands (see out_row).
 std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     const Basis B(L.k);
-    const int N = L.N, Q = L.Q, P = L.P, kpl = L.kpl;
-    std::vector<double> val((size_t)L.nfrag * 64 * kpl, 0.0);
-    auto at = [&](int frag, int lane, int j) -> double & { return val[((size_t)frag * 64 + lane) * kpl + j]; };
-    auto vol_point = [&](int chunk, int g, int j) {  // volume point fed at contraction slot (g, j) of a chunk
-        if (kpl == 1) return 16 * (chunk / 4) + out_row(L.prec, g, chunk % 4);
-        const int t = 2 * chunk + (j >= 4), r = j & 3;
-        return 16 * t + out_row(L.prec, g, r);
+    const int N = L.N, Q = L.Q, P = L.P;
+    // values in FP64, one vector per table: [frag][lane][j]
+    std::vector<double> t1((size_t)L.rt1 * L.ks1 * 64 * L.kpl, 0.0), t2((size_t)L.rt2 * 3 * L.nc2 * 64 * L.kpl2, 0.0),
+        t3((size_t)6 * L.ks1 * 64 * L.kpl, 0.0), t4((size_t)L.rt2 * L.nc4 * 64 * L.kpl, 0.0),
+        t5((size_t)L.rt2 * L.nc2 * 64 * L.kpl2, 0.0);
+    auto vol_point = [&](int chunk, int g, int j) {  // volume point at contraction slot (g, j) of a chunk
+        if (L.kpl2 == 1) return 16 * (chunk / 4) + out_row(L.prec, g, chunk % 4);
+        return 16 * chunk + out_row(L.prec, g, j);
     };
     auto face_slot = [&](int chunk, int g, int j, int &face) {  // (face, point) at slot (g, j)
-        if (kpl == 1) {
+        if (L.kpl == 1) {
             face = chunk / 4;
             return out_row(L.prec, g, chunk % 4);
         }
@@ -155,38 +158,25 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     double xi[3];
     for (int lane = 0; lane < 64; lane++) {
         const int row = lane % 16, g = lane / 16;
-        for (int j = 0; j < kpl; j++) {
-            const int kk = g * kpl + j;
-            // T1: Phi[q][m]
-            for (int t = 0; t < L.rt1; t++)
+        for (int j = 0; j < L.kpl; j++) {
+            const int kk = g * L.kpl + j;
+            for (int t = 0; t < L.rt1; t++)  // T1: Phi[q][m]
                 for (int st = 0; st < L.ks1; st++) {
                     const int q = 16 * t + row, m = st * L.kstep + kk;
                     if (q < Q && m < N) {
                         B.point(q, xi);
-                        at(L.off1 + t * L.ks1 + st, lane, j) = B.phi(m, xi);
+                        t1[(((size_t)t * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
                     }
                 }
-            // T2: -s_a dPhi_a[m][q] w_q
-            for (int rt = 0; rt < L.rt2; rt++)
-                for (int a = 0; a < 3; a++)
-                    for (int c = 0; c < L.nc2; c++) {
-                        const int m = 16 * rt + row, q = vol_point(c, g, j);
-                        if (q < Q && m < N) {
-                            B.point(q, xi);
-                            at(L.off2 + (rt * 3 + a) * L.nc2 + c, lane, j) = -s[a] * B.dphi(m, a, xi) * B.weight(q);
-                        }
-                    }
-            // T3: Phi[face point][m]
-            for (int f = 0; f < 6; f++)
+            for (int f = 0; f < 6; f++)  // T3: Phi[face point][m]
                 for (int st = 0; st < L.ks1; st++) {
                     const int p = row, m = st * L.kstep + kk;
                     if (p < P && m < N) {
                         B.face_point(f, p, xi);
-                        at(L.off3 + f * L.ks1 + st, lane, j) = B.phi(m, xi);
+                        t3[(((size_t)f * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
                     }
                 }
-            // T4: s_a (+-1) Phi[m][face point] w_p  (outward normal)
-            for (int rt = 0; rt < L.rt2; rt++)
+            for (int rt = 0; rt < L.rt2; rt++)  // T4: s_a (+-1) Phi[m][face point] w_p, outward normal
                 for (int c = 0; c < L.nc4; c++) {
                     int f;
                     const int p = face_slot(c, g, j, f);
@@ -194,35 +184,48 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                     if (p < P && m < N) {
                         B.face_point(f, p, xi);
                         const double sg = (f & 1) ? 1.0 : -1.0;
-                        at(L.off4 + rt * L.nc4 + c, lane, j) = s[f / 2] * sg * B.phi(m, xi) * B.face_weight(p);
+                        t4[(((size_t)rt * L.nc4 + c) * 64 + lane) * L.kpl + j] = s[f / 2] * sg * B.phi(m, xi) * B.face_weight(p);
                     }
                 }
-            // T5: -Phi[m][q] w_q / 8  (source projection)
+        }
+        for (int j = 0; j < L.kpl2; j++) {
             for (int rt = 0; rt < L.rt2; rt++)
                 for (int c = 0; c < L.nc2; c++) {
                     const int m = 16 * rt + row, q = vol_point(c, g, j);
                     if (q < Q && m < N) {
                         B.point(q, xi);
-                        at(L.off5 + rt * L.nc2 + c, lane, j) = -B.phi(m, xi) * B.weight(q) / 8.0;
+                        for (int a = 0; a < 3; a++)  // T2: -s_a dPhi_a[m][q] w_q
+                            t2[((((size_t)rt * 3 + a) * L.nc2 + c) * 64 + lane) * L.kpl2 + j] =
+                                -s[a] * B.dphi(m, a, xi) * B.weight(q);
+                        // T5: -Phi[m][q] w_q / 8 (source projection)
+                        t5[(((size_t)rt * L.nc2 + c) * 64 + lane) * L.kpl2 + j] = -B.phi(m, xi) * B.weight(q) / 8.0;
                     }
                 }
         }
     }
     std::vector<char> blob(L.bytes(), 0);
-    const size_t cnt = val.size();
-    if (L.prec == DG_FP64) {
-        std::memcpy(blob.data(), val.data(), cnt * 8);
-    } else if (L.prec == DG_FP32) {
-        float *o = reinterpret_cast<float *>(blob.data());
-        for (size_t i = 0; i < cnt; i++) o[i] = (float)val[i];
-    } else {
-        uint16_t *o = reinterpret_cast<uint16_t *>(blob.data());
-        for (size_t i = 0; i < cnt; i++) {
-            const uint16_t hi = bf16_rne((float)val[i]);
-            o[i] = hi;
-            if (L.ntab == 2) o[cnt + i] = bf16_rne((float)(val[i] - (double)bf16_to_float(hi)));
+    auto put = [&](const std::vector<double> &v, size_t off) {
+        const size_t cnt = v.size();
+        if (L.prec == DG_FP64) {
+            std::memcpy(blob.data() + off, v.data(), cnt * 8);
+        } else if (L.prec == DG_FP32) {
+            float *o = reinterpret_cast<float *>(blob.data() + off);
+            for (size_t i = 0; i < cnt; i++) o[i] = (float)v[i];
+        } else {
+            uint16_t *hi = reinterpret_cast<uint16_t *>(blob.data() + off);
+            uint16_t *lo = reinterpret_cast<uint16_t *>(blob.data() + L.set_bytes + off);
+            for (size_t i = 0; i < cnt; i++) {
+                const uint16_t h = bf16_rne((float)v[i]);
+                hi[i] = h;
+                if (L.ntab == 2) lo[i] = bf16_rne((float)(v[i] - (double)bf16_to_float(h)));
+            }
         }
-    }
+    };
+    put(t1, L.o1);
+    put(t2, L.o2);
+    put(t3, L.o3);
+    put(t4, L.o4);
+    put(t5, L.o5);
     return blob;
 }
 
@@ -253,21 +256,25 @@ TableLayout make_layout(int k, int prec) {
     L.n = k + 1;
     L.Q = L.n * L.n * L.n;
     L.P = L.n * L.n;
-    L.kpl = (prec == DG_BF16 || prec == DG_BF16X3) ? 8 : 1;
+    const bool bf = prec == DG_BF16 || prec == DG_BF16X3;
+    L.kpl = bf ? 8 : 1;
+    L.kpl2 = bf ? 4 : 1;
     L.kstep = 4 * L.kpl;
     L.ks1 = (L.N + L.kstep - 1) / L.kstep;
-    L.rt1 = L.kpl == 8 ? 2 * ((L.Q + 31) / 32) : (L.Q + 15) / 16;
+    L.rt1 = (L.Q + 15) / 16;
     L.rt2 = (L.N + 15) / 16;
-    L.nc2 = L.kpl == 8 ? L.rt1 / 2 : L.rt1 * 4;
-    L.nc4 = L.kpl == 8 ? 3 : 24;
-    L.off1 = 0;
-    L.off2 = L.off1 + L.rt1 * L.ks1;
-    L.off3 = L.off2 + L.rt2 * 3 * L.nc2;
-    L.off4 = L.off3 + 6 * L.ks1;
-    L.off5 = L.off4 + L.rt2 * L.nc4;
-    L.nfrag = L.off5 + L.rt2 * L.nc2;
-    L.ntab = prec == DG_BF16X3 ? 2 : 1;
+    L.nc2 = bf ? L.rt1 : L.rt1 * 4;
+    L.nc4 = bf ? 3 : 24;
     L.elem = prec == DG_FP64 ? 8 : (prec == DG_FP32 ? 4 : 2);
+    L.fb1 = (size_t)64 * L.kpl * L.elem;
+    L.fb2 = (size_t)64 * L.kpl2 * L.elem;
+    L.o1 = 0;
+    L.o2 = L.o1 + (size_t)L.rt1 * L.ks1 * L.fb1;
+    L.o3 = L.o2 + (size_t)L.rt2 * 3 * L.nc2 * L.fb2;
+    L.o4 = L.o3 + (size_t)6 * L.ks1 * L.fb1;
+    L.o5 = L.o4 + (size_t)L.rt2 * L.nc4 * L.fb1;
+    L.set_bytes = L.o5 + (size_t)L.rt2 * L.nc2 * L.fb2;
+    L.ntab = prec == DG_BF16X3 ? 2 : 1;
     return L;
 }
 
@@ -301,6 +308,14 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
     if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CHECK_RANGE)) return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
+    {
+        // the kernels address one field of a state with 32-bit unsigned byte offsets
+        const double field_bytes = (double)nmodes_of(cfg->k) * cfg->n[0] * cfg->n[1] * cfg->n[2] *
+                                   (cfg->precision == DG_FP64 ? 8.0 : 4.0);
+        const double qp_field_bytes = (double)(cfg->k + 1) * (cfg->k + 1) * (cfg->k + 1) * cfg->n[0] * cfg->n[1] *
+                                      cfg->n[2] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
+        if (field_bytes >= 4294967296.0 || qp_field_bytes >= 4294967296.0 * 5) return DG_ERR_UNSUPPORTED;
+    }
     const long long ncells = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
     if ((long long)cfg->n[0] > (1LL << 30) || ncells > (1LL << 40)) return DG_ERR_ARG;
 
@@ -349,11 +364,16 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipGetDevice(&dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    // z chunk length: long sweeps, but at least ~3 work items per resident wave
     const long long nbx = (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
-    const long long nblocks = nbx * cfg->n[1] * cfg->n[2];
     const int waves_per_wg = stage_block_threads() / 64;
+    const long long resident = (long long)per_cu * ncu * waves_per_wg;
+    long long zl = (nbx * cfg->n[1] * cfg->n[2]) / std::max(1LL, 3 * resident);
+    zl = std::max(1LL, std::min(32LL, std::min(zl, (long long)cfg->n[2])));
+    c->zlen = (int)zl;
+    const long long nitems = nbx * cfg->n[1] * ((cfg->n[2] + zl - 1) / zl);
     long long grid = (long long)per_cu * ncu;
-    grid = std::min(grid, (nblocks + waves_per_wg - 1) / waves_per_wg);
+    grid = std::min(grid, (nitems + waves_per_wg - 1) / waves_per_wg);
     if (grid >= 8) grid -= grid % 8;
     c->grid = (int)std::max(1LL, grid);
     *out = c;
@@ -412,7 +432,8 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.ny = c->cfg.n[1];
     s.nz = c->cfg.n[2];
     s.nbx = (c->cfg.n[0] + BLK_INNER - 1) / BLK_INNER;
-    s.nblocks = (long long)s.nbx * s.ny * s.nz;
+    s.zlen = c->zlen;
+    s.nitems = (long long)s.nbx * s.ny * ((s.nz + c->zlen - 1) / c->zlen);
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;

@@ -23,22 +23,26 @@ inline int nmodes_of(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 // register r.  FP32/BF16 accumulators: 4g + r.  FP64 (16x16x4f64): g + 4r.
 inline int out_row(int prec, int g, int r) { return prec == DG_FP64 ? g + 4 * r : 4 * g + r; }
 
-// Geometry of the MFMA fragment tables for one (k, precision).
+// Geometry of the MFMA operand tables for one (k, precision).  A "fragment" is
+// what the 64 lanes feed to one MFMA as its A operand.  GEMM1/3/4 use the wide
+// MFMA (K = 4 for FP32/FP64, K = 32 for BF16: kpl values per lane); GEMM2/5
+// (contractions over the volume points, fed straight from GEMM1's results) use
+// K = 4 / K = 16 (kpl2 values per lane) so that one 16-point tile is one chunk.
 struct TableLayout {
     int k, prec;
     int N, n, Q, P;
-    int kpl;         // operand values per lane per MFMA (1 for FP32/FP64, 8 for BF16)
-    int kstep;       // K extent of one MFMA (4 or 32)
+    int kpl, kpl2;   // operand values per lane: (1, 1) for FP32/FP64, (8, 4) for BF16
+    int kstep;       // K extent of the wide MFMA (4 or 32)
     int ks1;         // K steps over the modes
-    int rt1;         // volume-point row tiles (even for kpl = 8)
-    int rt2;         // mode row tiles of the result
-    int nc2;         // B chunks per flux direction over the volume points
-    int nc4;         // B chunks over the six faces
-    int off1, off2, off3, off4, off5, nfrag;  // fragment offsets of the five tables
-    int ntab;        // 1, or 2 for split (hi, lo) BF16 tables
+    int rt1;         // volume-point row tiles, ceil(Q/16)
+    int rt2;         // mode row tiles of the result, ceil(N/16)
+    int nc2;         // chunks over the volume points: rt1*4 (kpl2 = 1) or rt1 (kpl2 = 4)
+    int nc4;         // chunks over the six faces: 24 (kpl = 1) or 3 (kpl = 8)
     size_t elem;     // bytes per table element
-    size_t frag_bytes() const { return (size_t)64 * kpl * elem; }
-    size_t bytes() const { return frag_bytes() * nfrag * ntab; }
+    size_t fb1, fb2; // bytes per fragment of the wide / narrow tables
+    size_t o1, o2, o3, o4, o5, set_bytes;  // byte offsets of the five tables in one set
+    int ntab;        // 1, or 2 for split (hi, lo) BF16 tables (the lo set follows)
+    size_t bytes() const { return set_bytes * ntab; }
 };
 
 TableLayout make_layout(int k, int prec);
@@ -55,7 +59,8 @@ struct StageArgs {
     double gamma;
     int nx, ny, nz;
     int nbx;              // x-blocks per row
-    long long nblocks;
+    int zlen;             // cells per z chunk swept by one wave
+    long long nitems;     // work items: nbx * ny * ceil(nz / zlen)
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
@@ -96,6 +101,7 @@ struct dg_ctx {
     int nfmodes = 0;
     bool have_forcing = false;
     int grid = 0;
+    int zlen = 1;                  // z chunk length of the stage sweep
     int cur_slot = 1;              // slot holding the latest CFL rate
     int lds = 0;
     long long step_count = 0;

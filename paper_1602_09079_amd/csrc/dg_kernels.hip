@@ -1,31 +1,40 @@
 // HIP kernels of libdgmi.so for gfx950 (MI355X).
 //
 // The fused SSP stage kernel evaluates the modal DG operator of Bauer et al.
-// (arXiv 1602.09079), Sec. 2.3, for blocks of 16 cells that are consecutive in
+// (arXiv 1602.09079), Sec. 2.3, on blocks of 16 cells that are consecutive in
 // x.  Every basis contraction is a dense GEMM over cells on the matrix cores:
 //
-//   GEMM1  q(xi_q)        = Phi[q][l]         * w[l][cell]      (modal -> volume points)
-//   GEMM2  R[l]          += -s_a dPhi_a[l][q] * F_a(q)[q][cell]  (volume integral, eq. dg:eqn:volume_int)
-//   GEMM3  q(face point)  = Phif[p][l]        * w[l][cell]      (traces on the six faces)
-//   GEMM4  R[l]          += s_a (+-) Phif[l][p] * Fhat[p][cell]  (surface lift, eq. dg:eqn:surface_int)
-//   GEMM5  R[l]          -= Phi[l][q] w_q/8   * S(q)[q][cell]    (driving source, Sec. 3.1)
+//   GEMM1  q(xi_q)        = Phi[q][l]           * w[l][cell]        (modal -> volume points)
+//   GEMM2  R[l]          += -s_a dPhi_a[l][q] w_q * (F_a(q) - F_a(qbar))  (eq. dg:eqn:volume_int)
+//   GEMM3  q(face point)  = Phif[p][l]          * w[l][cell]        (traces on the six faces)
+//   GEMM4  R[l]          += s_a (+-) Phif[l][p] w_p * (Fhat - F_a(qbar))  (eq. dg:eqn:surface_int)
+//   GEMM5  R[l]          -= Phi[l][q] w_q / 8   * S(q)              (driving source, Sec. 3.1)
 //
-// Cells are the 16 columns of each MFMA tile.  The result registers of GEMM1
-// and GEMM3 are used directly as B operands of GEMM2 and GEMM4: the contraction
-// index of the tables is permuted on the host to match the output lane layout,
-// so no data is moved between the chained products.  The Euler flux and the HLLC
-// Riemann solver run on the vector ALUs in that same lane layout.
+// The 16 cells are the columns of each MFMA tile.  The result registers of
+// GEMM1 and GEMM3 are fed directly as B operands of GEMM2 and GEMM4: the
+// contraction index of the tables is permuted on the host to match the result
+// lane layout, so no data moves between the chained products.  The Euler flux
+// and the HLLC Riemann solver run on the vector ALUs in that same layout.
+//
+// Deviation form: mode 0 (the cell mean qbar) is kept out of the products and
+// added back in full precision, and the cell-mean flux F(qbar) is subtracted from
+// every volume and face flux before projection.  The subtracted terms cancel
+// exactly because the Gauss rules integrate the basis derivatives and the face
+// traces exactly, so the operator is unchanged while reduced-precision rounding
+// acts on the in-cell variation instead of the mean.
 //
 // Faces: the x-neighbour of a column is the adjacent lane of its 16-lane row
-// (DPP row shifts); a block's columns 0 and 15 are halo cells whose results are
-// discarded, so consecutive blocks overlap by two cells.  The y- and z-neighbour
-// traces are computed from the neighbouring blocks' weights (loaded through L2)
-// with the same GEMM3 tables, so each face flux is computed from bitwise
-// identical inputs on both sides and the scheme stays conservative to round-off.
+// (DPP row shifts); columns 0 and 15 of a block are halo cells whose results are
+// discarded (consecutive blocks overlap by two cells).  Each wave sweeps a chunk
+// of blocks along z, loading block z+1 while it computes block z; the flux on
+// the face between them is computed once and carried to the next step.  The
+// y-neighbour traces come from the neighbouring rows' weights (through L2) with
+// the same GEMM3 tables, so a face flux is computed from bitwise identical inputs
+// on both sides.
 //
-// Persistent grid: each wave loops over blocks; the block range is split into 8
-// contiguous parts, one per XCD (workgroup id modulo 8), so that the y/z
-// neighbours a wave reads were recently loaded into the same XCD's L2.
+// Persistent grid: the work items (x-block, y row, z chunk) are split into 8
+// contiguous ranges, one per XCD (workgroup id modulo 8), so the rows a wave
+// reads as y-neighbours were recently loaded into the same XCD's L2.
 
 #include "dg_internal.h"
 
@@ -36,6 +45,8 @@ namespace dgmi {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 
 template <int K>
 struct Dims {
@@ -46,24 +57,30 @@ struct Dims {
 };
 
 // ------------------------------------------------------------------ precision policies
+//
+// S: storage type; C: pointwise arithmetic; Acc: MFMA accumulator.
+// AF/BF: wide A/B operands (GEMM1/3/4), AF2/BF2: narrow ones (GEMM2/5).
 
 template <int PREC>
 struct Prec;
 
 template <>
 struct Prec<DG_FP64> {
-    using S = double;  // storage
-    using C = double;  // pointwise arithmetic
+    using S = double;
+    using C = double;
     using Acc = d4;
-    static constexpr int KPL = 1, KSTEP = 4;
+    static constexpr int KPL = 1, KPL2 = 1, KSTEP = 4, ESZ = 8;
     struct AF { double v; };
+    using AF2 = AF;
     struct BF { double v; };
-    __device__ static AF lda(const char *lds, int frag, int lane) {
-        return AF{reinterpret_cast<const double *>(lds)[frag * 64 + lane]};
-    }
+    using BF2 = BF;
+    __device__ static AF lda(const char *p) { return AF{*reinterpret_cast<const double *>(p)}; }
+    __device__ static AF2 lda2(const char *p) { return lda(p); }
     __device__ static Acc mma(Acc c, AF a, BF b) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a.v, b.v, c, 0, 0, 0); }
+    __device__ static Acc mma2(Acc c, AF2 a, BF2 b) { return mma(c, a, b); }
     __device__ static int orow(int g, int r) { return g + 4 * r; }
     __device__ static BF mkb(const C *v) { return BF{v[0]}; }
+    __device__ static BF2 mkb2(const C *v) { return BF{v[0]}; }
     __device__ static C rcp(C x) { return 1.0 / x; }
     __device__ static C sqrt_(C x) { return __builtin_sqrt(x); }
 };
@@ -73,15 +90,18 @@ struct Prec<DG_FP32> {
     using S = float;
     using C = float;
     using Acc = f4;
-    static constexpr int KPL = 1, KSTEP = 4;
+    static constexpr int KPL = 1, KPL2 = 1, KSTEP = 4, ESZ = 4;
     struct AF { float v; };
+    using AF2 = AF;
     struct BF { float v; };
-    __device__ static AF lda(const char *lds, int frag, int lane) {
-        return AF{reinterpret_cast<const float *>(lds)[frag * 64 + lane]};
-    }
+    using BF2 = BF;
+    __device__ static AF lda(const char *p) { return AF{*reinterpret_cast<const float *>(p)}; }
+    __device__ static AF2 lda2(const char *p) { return lda(p); }
     __device__ static Acc mma(Acc c, AF a, BF b) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v, b.v, c, 0, 0, 0); }
+    __device__ static Acc mma2(Acc c, AF2 a, BF2 b) { return mma(c, a, b); }
     __device__ static int orow(int g, int r) { return 4 * g + r; }
     __device__ static BF mkb(const C *v) { return BF{v[0]}; }
+    __device__ static BF2 mkb2(const C *v) { return BF{v[0]}; }
     __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
     __device__ static C sqrt_(C x) { return __builtin_amdgcn_sqrtf(x); }
 };
@@ -91,13 +111,18 @@ struct Prec<DG_BF16> {
     using S = float;
     using C = float;
     using Acc = f4;
-    static constexpr int KPL = 8, KSTEP = 32;
+    static constexpr int KPL = 8, KPL2 = 4, KSTEP = 32, ESZ = 2;
     struct AF { bf8 v; };
+    struct AF2 { bf4 v; };
     struct BF { bf8 v; };
-    __device__ static AF lda(const char *lds, int frag, int lane) {
-        return AF{reinterpret_cast<const bf8 *>(lds)[frag * 64 + lane]};
-    }
+    struct BF2 { bf4 v; };
+    __device__ static AF lda(const char *p) { return AF{*reinterpret_cast<const bf8 *>(p)}; }
+    __device__ static AF2 lda2(const char *p) { return AF2{*reinterpret_cast<const bf4 *>(p)}; }
     __device__ static Acc mma(Acc c, AF a, BF b) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0); }
+    __device__ static Acc mma2(Acc c, AF2 a, BF2 b) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a.v), __builtin_bit_cast(s4, b.v), c, 0,
+                                                          0, 0);
+    }
     __device__ static int orow(int g, int r) { return 4 * g + r; }
     __device__ static BF mkb(const C *v) {
         BF b;
@@ -105,46 +130,68 @@ struct Prec<DG_BF16> {
         for (int j = 0; j < 8; j++) b.v[j] = (__bf16)v[j];
         return b;
     }
-    __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
-    __device__ static C sqrt_(C x) { return __builtin_amdgcn_sqrtf(x); }
-};
-
-// FP32-grade contractions from BF16 matrix cores: x = hi + lo with hi = bf16(x),
-// lo = bf16(x - hi); a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (lo_a lo_b dropped).
-template <>
-struct Prec<DG_BF16X3> {
-    using S = float;
-    using C = float;
-    using Acc = f4;
-    static constexpr int KPL = 8, KSTEP = 32;
-    struct AF { bf8 hi, lo; };
-    struct BF { bf8 hi, lo; };
-    static constexpr int HALF_OFFSET_FRAGS = 0;  // lo tables follow the hi tables (offset passed at run time)
-    __device__ static AF lda2(const char *lds, int frag, int lane, int lo_off) {
-        const bf8 *t = reinterpret_cast<const bf8 *>(lds);
-        return AF{t[frag * 64 + lane], t[(lo_off + frag) * 64 + lane]};
-    }
-    __device__ static Acc mma(Acc c, AF a, BF b) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
-    }
-    __device__ static int orow(int g, int r) { return 4 * g + r; }
-    __device__ static BF mkb(const C *v) {
-        BF b;
+    __device__ static BF2 mkb2(const C *v) {
+        BF2 b;
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            __bf16 h = (__bf16)v[j];
-            b.hi[j] = h;
-            b.lo[j] = (__bf16)(v[j] - (float)h);
-        }
+        for (int j = 0; j < 4; j++) b.v[j] = (__bf16)v[j];
         return b;
     }
     __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
     __device__ static C sqrt_(C x) { return __builtin_amdgcn_sqrtf(x); }
 };
 
-// ------------------------------------------------------------------ lane exchange
+// FP32-grade contractions on BF16 matrix cores: x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi); a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (lo_a lo_b dropped,
+// relative size 2^-18).  The lo tables follow the hi tables at +LO bytes.
+template <>
+struct Prec<DG_BF16X3> {
+    using S = float;
+    using C = float;
+    using Acc = f4;
+    static constexpr int KPL = 8, KPL2 = 4, KSTEP = 32, ESZ = 2;
+    struct AF { bf8 hi, lo; };
+    struct AF2 { bf4 hi, lo; };
+    struct BF { bf8 hi, lo; };
+    struct BF2 { bf4 hi, lo; };
+    static __device__ inline int lo_bytes();
+    __device__ static Acc mma(Acc c, AF a, BF b) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
+    }
+    __device__ static Acc mma2(Acc c, AF2 a, BF2 b) {
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a.lo), __builtin_bit_cast(s4, b.hi), c, 0,
+                                                       0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a.hi), __builtin_bit_cast(s4, b.lo), c, 0,
+                                                       0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a.hi), __builtin_bit_cast(s4, b.hi), c,
+                                                          0, 0, 0);
+    }
+    __device__ static int orow(int g, int r) { return 4 * g + r; }
+    template <int L, class V>
+    __device__ static void split(const C *v, V &hi, V &lo) {
+#pragma unroll
+        for (int j = 0; j < L; j++) {
+            const __bf16 h = (__bf16)v[j];
+            hi[j] = h;
+            lo[j] = (__bf16)(v[j] - (float)h);
+        }
+    }
+    __device__ static BF mkb(const C *v) {
+        BF b;
+        split<8>(v, b.hi, b.lo);
+        return b;
+    }
+    __device__ static BF2 mkb2(const C *v) {
+        BF2 b;
+        split<4>(v, b.hi, b.lo);
+        return b;
+    }
+    __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static C sqrt_(C x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// ------------------------------------------------------------------ lane exchange (DPP row shifts)
 
 __device__ inline float dpp_shr1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
@@ -153,15 +200,15 @@ __device__ inline float dpp_shl1(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, true));
 }
 __device__ inline double dpp_shr1(double v) {
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x111, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, true);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x111, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ inline double dpp_shl1(double v) {
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x101, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xf, 0xf, true);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x101, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -170,120 +217,167 @@ __device__ inline double dpp_shl1(double v) {
 // Ideal-gas Euler flux along the three axes at one point, Sec. 2.3.
 template <class PR, class C>
 __device__ inline void euler_flux3(const C q[5], C g1, C F[3][5]) {
-    C inv = PR::rcp(q[0]);
-    C u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
-    C p = g1 * (q[4] - C(0.5) * (q[1] * u + q[2] * v + q[3] * w));
-    C ep = q[4] + p;
+    const C inv = PR::rcp(q[0]);
+    const C u = q[1] * inv, v = q[2] * inv, w = q[3] * inv;
+    const C p = g1 * (q[4] - C(0.5) * (q[1] * u + q[2] * v + q[3] * w));
+    const C ep = q[4] + p;
     F[0][0] = q[1]; F[0][1] = q[1] * u + p; F[0][2] = q[2] * u; F[0][3] = q[3] * u; F[0][4] = ep * u;
     F[1][0] = q[2]; F[1][1] = q[1] * v;     F[1][2] = q[2] * v + p; F[1][3] = q[3] * v; F[1][4] = ep * v;
     F[2][0] = q[3]; F[2][1] = q[1] * w;     F[2][2] = q[2] * w; F[2][3] = q[3] * w + p; F[2][4] = ep * w;
 }
 
 // HLLC numerical flux across a face normal to AXIS, left state qL, right state
-// qR (Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics, ch. 10,
-// Davis wave-speed bounds).  S* >= 0 takes the left star state.  Written without
-// branches: the side K is selected first and only its flux and star state are formed.
+// qR (Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics, ch. 10:
+// Davis wave-speed bounds; the star flux in the form
+//   F*_K = (S* (S_K U_K - F_K) + S_K p* D*) / (S_K - S*),  D* = (0, n, S*),
+//   p* = p_K + rho_K (S_K - u_K)(S* - u_K),
+// which equals F_K + S_K (U*_K - U_K) of the star-state form).  S* >= 0 takes the
+// left star state.  Branch-free: side K is selected first, only its flux is formed.
 template <class PR, int AXIS, class C>
 __device__ inline void hllc(const C qL[5], const C qR[5], C gam, C F[5]) {
     const C g1 = gam - C(1);
-    C iL = PR::rcp(qL[0]), iR = PR::rcp(qR[0]);
-    C uL = qL[1 + AXIS] * iL, uR = qR[1 + AXIS] * iR;
-    C pL = g1 * (qL[4] - C(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
-    C pR = g1 * (qR[4] - C(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
-    C cL = PR::sqrt_(gam * pL * iL), cR = PR::sqrt_(gam * pR * iR);
-    C SL = __builtin_fmin(uL - cL, uR - cR);
-    C SR = __builtin_fmax(uL + cL, uR + cR);
-    C dL = qL[0] * (SL - uL), dR = qR[0] * (SR - uR);
-    C Ss = (pR - pL + qL[1 + AXIS] * (SL - uL) - qR[1 + AXIS] * (SR - uR)) / (dL - dR);
-    bool left = (Ss >= C(0)) || (SL >= C(0));
+    const C iL = PR::rcp(qL[0]), iR = PR::rcp(qR[0]);
+    const C uL = qL[1 + AXIS] * iL, uR = qR[1 + AXIS] * iR;
+    const C pL = g1 * (qL[4] - C(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
+    const C pR = g1 * (qR[4] - C(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
+    const C cL = PR::sqrt_(gam * pL * iL), cR = PR::sqrt_(gam * pR * iR);
+    const C SL = __builtin_fmin(uL - cL, uR - cR);
+    const C SR = __builtin_fmax(uL + cL, uR + cR);
+    const C sL = SL - uL, sR = SR - uR;
+    const C dL = qL[0] * sL, dR = qR[0] * sR;
+    const C Ss = (pR - pL + qL[1 + AXIS] * sL - qR[1 + AXIS] * sR) * PR::rcp(dL - dR);
+    const bool left = (Ss >= C(0)) || (SL >= C(0));
     C q[5];
 #pragma unroll
     for (int i = 0; i < 5; i++) q[i] = left ? qL[i] : qR[i];
-    C iK = left ? iL : iR, uK = left ? uL : uR, pK = left ? pL : pR, SK = left ? SL : SR, dK = left ? dL : dR;
-    // physical flux of side K
+    const C uK = left ? uL : uR, pK = left ? pL : pR, SK = left ? SL : SR, dK = left ? dL : dR;
     C FK[5];
     FK[0] = q[1 + AXIS];
 #pragma unroll
     for (int j = 0; j < 3; j++) FK[1 + j] = q[1 + j] * uK;
     FK[1 + AXIS] += pK;
     FK[4] = (q[4] + pK) * uK;
-    // star state of side K
-    C fac = dK / (SK - Ss);
-    C U[5];
-    U[0] = fac;
+    const bool plain = (SL >= C(0)) || (!left && SR <= C(0));
+    const C pst = pK + dK * (Ss - uK);
+    const C inv = PR::rcp(SK - Ss);
+    C Fs[5];
 #pragma unroll
-    for (int j = 0; j < 3; j++) U[1 + j] = fac * q[1 + j] * iK;
-    U[1 + AXIS] = fac * Ss;
-    U[4] = fac * (q[4] * iK + (Ss - uK) * (Ss + pK / dK));
-    bool plain = (SL >= C(0)) || (!left && SR <= C(0));
+    for (int i = 0; i < 5; i++) Fs[i] = Ss * (SK * q[i] - FK[i]);
+    Fs[1 + AXIS] += SK * pst;
+    Fs[4] += SK * pst * Ss;
 #pragma unroll
-    for (int i = 0; i < 5; i++) F[i] = plain ? FK[i] : FK[i] + SK * (U[i] - q[i]);
+    for (int i = 0; i < 5; i++) F[i] = plain ? FK[i] : Fs[i] * inv;
 }
 
-// ------------------------------------------------------------------ the fused stage kernel
+// ------------------------------------------------------------------ table geometry (matches make_layout)
 
 template <int K, int PREC>
 struct StageCfg {
     using D = Dims<K>;
     using PR = Prec<PREC>;
     static constexpr int N = D::N, Q = D::Q, P = D::P;
-    static constexpr int KPL = PR::KPL, KSTEP = PR::KSTEP;
+    static constexpr int KPL = PR::KPL, KPL2 = PR::KPL2, KSTEP = PR::KSTEP;
     static constexpr int KS1 = (N + KSTEP - 1) / KSTEP;
-    static constexpr int RT1 = KPL == 8 ? 2 * ((Q + 31) / 32) : (Q + 15) / 16;
+    static constexpr int RT1 = (Q + 15) / 16;
     static constexpr int RT2 = (N + 15) / 16;
-    static constexpr int NC2 = KPL == 8 ? RT1 / 2 : RT1 * 4;
+    static constexpr int NC2 = KPL2 == 4 ? RT1 : RT1 * 4;
     static constexpr int NC4 = KPL == 8 ? 3 : 24;
-    static constexpr int OFF1 = 0;
-    static constexpr int OFF2 = OFF1 + RT1 * KS1;
-    static constexpr int OFF3 = OFF2 + RT2 * 3 * NC2;
-    static constexpr int OFF4 = OFF3 + 6 * KS1;
-    static constexpr int OFF5 = OFF4 + RT2 * NC4;
-    static constexpr int NFRAG = OFF5 + RT2 * NC2;
+    static constexpr int FB1 = 64 * KPL * PR::ESZ, FB2 = 64 * KPL2 * PR::ESZ;
+    static constexpr int O1 = 0;
+    static constexpr int O2 = O1 + RT1 * KS1 * FB1;
+    static constexpr int O3 = O2 + RT2 * 3 * NC2 * FB2;
+    static constexpr int O4 = O3 + 6 * KS1 * FB1;
+    static constexpr int O5 = O4 + RT2 * NC4 * FB1;
+    static constexpr int SET = O5 + RT2 * NC2 * FB2;
+    static constexpr int NTAB = PREC == DG_BF16X3 ? 2 : 1;
+    static constexpr bool QFULL = (Q % 16) == 0;  // no padded volume rows
+    static constexpr bool PFULL = P == 16;        // no padded face rows
 };
 
-template <int PREC>
+// Reads A-operand fragments from the LDS copy of the tables.  refresh() hides the
+// lane offset from loop-invariant code motion so fragments are re-read where they
+// are used instead of being hoisted into (and exhausting) the register file.
+template <int K, int PREC>
 struct TabReader {
+    using SC = StageCfg<K, PREC>;
+    using PR = Prec<PREC>;
     const char *lds;
-    int lane;
-    int lo_off;
-    __device__ typename Prec<PREC>::AF operator()(int frag) const {
-        if constexpr (PREC == DG_BF16X3)
-            return Prec<PREC>::lda2(lds, frag, lane, lo_off);
-        else
-            return Prec<PREC>::lda(lds, frag, lane);
+    int off1, off2;  // this lane's byte offset inside a wide / narrow fragment
+    __device__ void refresh() {
+        asm volatile("" : "+v"(off1));
+        asm volatile("" : "+v"(off2));
     }
+    __device__ typename PR::AF wide(int byte) const {
+        if constexpr (PREC == DG_BF16X3)
+            return typename PR::AF{*reinterpret_cast<const bf8 *>(lds + byte + off1),
+                                   *reinterpret_cast<const bf8 *>(lds + SC::SET + byte + off1)};
+        else
+            return PR::lda(lds + byte + off1);
+    }
+    __device__ typename PR::AF2 narrow(int byte) const {
+        if constexpr (PREC == DG_BF16X3)
+            return typename PR::AF2{*reinterpret_cast<const bf4 *>(lds + byte + off2),
+                                    *reinterpret_cast<const bf4 *>(lds + SC::SET + byte + off2)};
+        else
+            return PR::lda2(lds + byte + off2);
+    }
+    __device__ typename PR::AF t1(int t, int s) const { return wide(SC::O1 + (t * SC::KS1 + s) * SC::FB1); }
+    __device__ typename PR::AF2 t2(int rt, int al, int c) const {
+        return narrow(SC::O2 + ((rt * 3 + al) * SC::NC2 + c) * SC::FB2);
+    }
+    __device__ typename PR::AF t3(int f, int s) const { return wide(SC::O3 + (f * SC::KS1 + s) * SC::FB1); }
+    __device__ typename PR::AF t4(int rt, int c) const { return wide(SC::O4 + (rt * SC::NC4 + c) * SC::FB1); }
+    __device__ typename PR::AF2 t5(int rt, int c) const { return narrow(SC::O5 + (rt * SC::NC2 + c) * SC::FB2); }
 };
 
 constexpr int STAGE_THREADS = 256;
 
+// Waves per SIMD the stage kernel is compiled for (register budget 512 / this).
+#ifndef DG_STAGE_WAVES_PER_EU
+#define DG_STAGE_WAVES_PER_EU 2
+#endif
+
+// The weights of one block of 16 cells in B-operand layout, without mode 0,
+// plus the cell means in full precision.
 template <int K, int PREC>
-__global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(StageArgs a) {
+struct Blk {
+    typename Prec<PREC>::BF w[NF][StageCfg<K, PREC>::KS1];
+    typename Prec<PREC>::C qbar[NF];
+};
+
+// element e of field i of a state, addressed from the field's (uniform) base with
+// a 32-bit unsigned byte offset
+template <class S>
+__device__ inline S ld(const S *base, long long fieldstride, int i, unsigned e) {
+    const char *fb = reinterpret_cast<const char *>(base + (long long)i * fieldstride);
+    return *reinterpret_cast<const S *>(fb + e * (unsigned)sizeof(S));
+}
+
+template <int K, int PREC>
+__global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES_PER_EU, DG_STAGE_WAVES_PER_EU))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
     using PR = typename SC::PR;
     using C = typename PR::C;
     using S = typename PR::S;
     using Acc = typename PR::Acc;
-    using BF = typename PR::BF;
+    using B = Blk<K, PREC>;
     constexpr int N = SC::N, Q = SC::Q, P = SC::P;
-    constexpr int KPL = SC::KPL, KSTEP = SC::KSTEP, KS1 = SC::KS1;
-    constexpr int RT1 = SC::RT1, RT2 = SC::RT2, NC2 = SC::NC2, NC4 = SC::NC4;
+    constexpr int KPL = SC::KPL, KPL2 = SC::KPL2, KSTEP = SC::KSTEP, KS1 = SC::KS1;
+    constexpr int RT1 = SC::RT1, RT2 = SC::RT2;
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
-        // stage the fragment tables into LDS
-        constexpr int ntab = PREC == DG_BF16X3 ? 2 : 1;
-        constexpr size_t esz = PREC == DG_FP64 ? 8 : (PREC == DG_FP32 ? 4 : 2);
-        constexpr size_t bytes = (size_t)SC::NFRAG * 64 * KPL * esz * ntab;
+        constexpr int bytes = SC::SET * SC::NTAB;
         const int4 *src = reinterpret_cast<const int4 *>(a.tables);
         int4 *dst = reinterpret_cast<int4 *>(lds);
-        for (size_t j = threadIdx.x; j < bytes / 16; j += STAGE_THREADS) dst[j] = src[j];
+        for (int j = threadIdx.x; j < bytes / 16; j += STAGE_THREADS) dst[j] = src[j];
         __syncthreads();
     }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15;
     const int g = lane >> 4;
-    const TabReader<PREC> T{lds, lane, SC::NFRAG};
+    TabReader<K, PREC> T{lds, lane * KPL * PR::ESZ, lane * KPL2 * PR::ESZ};
 
     const C gam = (C)a.gamma;
     const C g1 = gam - C(1);
@@ -295,264 +389,302 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(StageArgs a) {
     const S *__restrict__ y0 = reinterpret_cast<const S *>(a.y0);
     S *out = reinterpret_cast<S *>(a.out);
     const long long nc = a.ncells;
+    const long long fstride = (long long)N * nc;
+    const unsigned ncu = (unsigned)nc;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
-    // XCD-aware assignment of blocks to waves
+    // ---------------- building blocks
+    auto load = [&](unsigned cell, B &b) {
+#pragma unroll
+        for (int i = 0; i < NF; i++) b.qbar[i] = (C)ld(yin, fstride, i, cell);
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int s = 0; s < KS1; s++) {
+                C v[KPL];
+#pragma unroll
+                for (int j = 0; j < KPL; j++) {
+                    const int m = s * KSTEP + g * KPL + j;
+                    const int mc = m < 1 ? 1 : (m > N - 1 ? N - 1 : m);
+                    const C x = (C)ld(yin, fstride, i, (unsigned)mc * ncu + cell);
+                    v[j] = (m >= 1 && m < N) ? x : C(0);
+                }
+                b.w[i][s] = PR::mkb(v);
+            }
+    };
+    auto trace = [&](const B &b, int face, C tr[NF][4]) {
+        Acc t[NF];
+#pragma unroll
+        for (int i = 0; i < NF; i++) t[i] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS1; s++) {
+            const auto A = T.t3(face, s);
+#pragma unroll
+            for (int i = 0; i < NF; i++) t[i] = PR::mma(t[i], A, b.w[i][s]);
+        }
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) tr[i][r] = (C)t[i][r] + b.qbar[i];
+    };
+    auto riemann = [&](auto axis_c, const C tl[NF][4], const C tr_[NF][4], C Fo[NF][4]) {
+        constexpr int AX = decltype(axis_c)::value;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const bool valid = SC::PFULL || PR::orow(g, r) < P;
+            C qL[5], qR[5], F[5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                qL[i] = valid ? tl[i][r] : C(i == 0 ? 1 : (i == 4 ? 2 : 0));
+                qR[i] = valid ? tr_[i][r] : C(i == 0 ? 1 : (i == 4 ? 2 : 0));
+            }
+            hllc<PR, AX>(qL, qR, gam, F);
+#pragma unroll
+            for (int i = 0; i < 5; i++) Fo[i][r] = F[i];
+        }
+    };
+    // the cell-mean flux along one axis (recomputed where needed, to save registers)
+    auto mean_flux = [&](const B &b, int axis, C Fb[5]) {
+        C F3[3][5];
+        euler_flux3<PR>(b.qbar, g1, F3);
+#pragma unroll
+        for (int i = 0; i < 5; i++) Fb[i] = F3[axis][i];
+    };
+    // lift of the two face fluxes of one axis, minus the cell-mean flux
+    auto lift = [&](int axis, const B &b, const C Fm[NF][4], const C Fp[NF][4], Acc acc[NF][RT2]) {
+        C Fb[5];
+        mean_flux(b, axis, Fb);
+        C vm[NF][4], vp[NF][4];
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const bool valid = SC::PFULL || PR::orow(g, r) < P;
+                vm[i][r] = valid ? Fm[i][r] - Fb[i] : C(0);
+                vp[i][r] = valid ? Fp[i][r] - Fb[i] : C(0);
+            }
+        if constexpr (KPL == 1) {
+#pragma unroll
+            for (int side = 0; side < 2; side++)
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int rt = 0; rt < RT2; rt++) {
+                        const auto A = T.t4(rt, (2 * axis + side) * 4 + r);
+#pragma unroll
+                        for (int i = 0; i < NF; i++)
+                            acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(side ? &vp[i][r] : &vm[i][r]));
+                    }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NF; i++) {
+                C v[8];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    v[r] = vm[i][r];
+                    v[4 + r] = vp[i][r];
+                }
+                const auto bf = PR::mkb(v);
+#pragma unroll
+                for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma(acc[i][rt], T.t4(rt, axis), bf);
+            }
+        }
+    };
+    // volume integral: GEMM1 -> flux deviation -> GEMM2, one 16-point tile at a time
+    auto volume = [&](const B &b, Acc acc[NF][RT2]) {
+        C Fb[3][5];
+        euler_flux3<PR>(b.qbar, g1, Fb);
+#pragma unroll
+        for (int t = 0; t < RT1; t++) {
+            Acc d[NF];
+#pragma unroll
+            for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS1; s++) {
+                const auto A = T.t1(t, s);
+#pragma unroll
+                for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, b.w[i][s]);
+            }
+            // primitive quantities at this lane's 4 points of the tile
+            C mx[4], my[4], mz[4], ep[4], vel[3][4], p[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
+                C q[5];
+#pragma unroll
+                for (int i = 0; i < 5; i++) q[i] = valid ? (C)d[i][r] + b.qbar[i] : b.qbar[i];
+                const C inv = PR::rcp(q[0]);
+                mx[r] = q[1]; my[r] = q[2]; mz[r] = q[3];
+                vel[0][r] = q[1] * inv; vel[1][r] = q[2] * inv; vel[2][r] = q[3] * inv;
+                p[r] = g1 * (q[4] - C(0.5) * (q[1] * vel[0][r] + q[2] * vel[1][r] + q[3] * vel[2][r]));
+                ep[r] = q[4] + p[r];
+            }
+#pragma unroll
+            for (int al = 0; al < 3; al++) {
+                C F[5][4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
+                    C f[5];
+                    f[0] = al == 0 ? mx[r] : (al == 1 ? my[r] : mz[r]);
+                    f[1] = mx[r] * vel[al][r];
+                    f[2] = my[r] * vel[al][r];
+                    f[3] = mz[r] * vel[al][r];
+                    f[1 + al] += p[r];
+                    f[4] = ep[r] * vel[al][r];
+#pragma unroll
+                    for (int i = 0; i < 5; i++) F[i][r] = valid ? f[i] - Fb[al][i] : C(0);
+                }
+                if constexpr (KPL2 == 1) {
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int rt = 0; rt < RT2; rt++) {
+                            const auto A = T.t2(rt, al, t * 4 + r);
+#pragma unroll
+                            for (int i = 0; i < NF; i++) acc[i][rt] = PR::mma2(acc[i][rt], A, PR::mkb2(&F[i][r]));
+                        }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NF; i++) {
+                        const auto bf = PR::mkb2(F[i]);
+#pragma unroll
+                        for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t2(rt, al, t), bf);
+                    }
+                }
+            }
+        }
+    };
+
+    // ---------------- work items: (x-block, y row, z chunk), x-block fastest
     const int nxcd = gridDim.x < 8 ? (int)gridDim.x : 8;
     const int xcd = blockIdx.x % nxcd;
     const int wgs_x = (gridDim.x - xcd + nxcd - 1) / nxcd;
     const long long wid = (long long)(blockIdx.x / nxcd) * (STAGE_THREADS / 64) + wave;
     const long long wcount = (long long)wgs_x * (STAGE_THREADS / 64);
-    const long long b_lo = a.nblocks * xcd / nxcd, b_hi = a.nblocks * (xcd + 1) / nxcd;
+    const long long i_lo = a.nitems * xcd / nxcd, i_hi = a.nitems * (xcd + 1) / nxcd;
 
-    for (long long blk = b_lo + wid; blk < b_hi; blk += wcount) {
-        const int bx = (int)(blk % a.nbx);
-        const long long rest = blk / a.nbx;
+    for (long long item = i_lo + wid; item < i_hi; item += wcount) {
+        const int bx = (int)(item % a.nbx);
+        const long long rest = item / a.nbx;
         const int iy = (int)(rest % ny);
-        const int iz = (int)(rest / ny);
-        const int xraw = BLK_INNER * bx - 1 + col;          // may be -1 or >= nx: periodic wrap
+        const int zc = (int)(rest / ny);
+        const int z0 = zc * a.zlen;
+        const int z1 = z0 + a.zlen < nz ? z0 + a.zlen : nz;
+        const int xraw = BLK_INNER * bx - 1 + col;  // -1 .. : periodic wrap
         const int xc = (xraw % nx + nx) % nx;
-        const long long rowbase = ((long long)iz * ny + iy) * nx;
-        const long long cell = rowbase + xc;
+        const bool keep = col >= 1 && col <= BLK_INNER && xraw < nx;
+        auto cidx = [&](int yy, int zz) -> unsigned {
+            yy = (yy + ny) % ny;
+            zz = (zz + nz) % nz;
+            return (unsigned)(((long long)zz * ny + yy) * nx + xc);
+        };
 
-        auto load_w = [&](long long cidx, BF w[NF][KS1]) {
+        T.refresh();
+        B cur;
+        load(cidx(iy, z0), cur);
+        C Fz[NF][4];  // flux on the -z face of the current block
+        {
+            B prv;
+            load(cidx(iy, z0 - 1), prv);
+            C tp[NF][4], tm[NF][4];
+            trace(prv, 5, tp);
+            trace(cur, 4, tm);
+            riemann(std::integral_constant<int, 2>{}, tp, tm, Fz);
+        }
+        for (int z = z0; z < z1; z++) {
+            T.refresh();
+            B nxt;
+            load(cidx(iy, z + 1), nxt);
+            Acc acc[NF][RT2];
 #pragma unroll
             for (int i = 0; i < NF; i++)
 #pragma unroll
-                for (int s = 0; s < KS1; s++) {
-                    C v[KPL];
+                for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
+
+            volume(cur, acc);
+            {  // x faces: the left neighbour's + trace sits in the adjacent lane
+                C tl[NF][4], Fm[NF][4], Fp[NF][4];
+                {
+                    C tp[NF][4];
+                    trace(cur, 1, tp);
 #pragma unroll
-                    for (int j = 0; j < KPL; j++) {
-                        const int m = s * KSTEP + g * KPL + j;
-                        v[j] = m < N ? (C)yin[((long long)i * N + m) * nc + cidx] : C(0);
-                    }
-                    w[i][s] = PR::mkb(v);
+                    for (int i = 0; i < NF; i++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) tl[i][r] = dpp_shr1(tp[i][r]);
                 }
-        };
-        auto trace = [&](const BF w[NF][KS1], int face, Acc tr[NF]) {
+                {
+                    C tm[NF][4];
+                    trace(cur, 0, tm);
+                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fm);
+                }
 #pragma unroll
-            for (int i = 0; i < NF; i++) tr[i] = Acc{0, 0, 0, 0};
+                for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int s = 0; s < KS1; s++) {
-                const auto A = T(SC::OFF3 + face * KS1 + s);
-#pragma unroll
-                for (int i = 0; i < NF; i++) tr[i] = PR::mma(tr[i], A, w[i][s]);
+                    for (int r = 0; r < 4; r++) Fp[i][r] = dpp_shl1(Fm[i][r]);
+                lift(0, cur, Fm, Fp, acc);
             }
-        };
-
-        BF w[NF][KS1];
-        load_w(cell, w);
-
-        Acc acc[NF][RT2];
-#pragma unroll
-        for (int i = 0; i < NF; i++)
-#pragma unroll
-            for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
-
-        // ---------------- volume integral: GEMM1 -> flux -> GEMM2
-        if constexpr (KPL == 1) {
-#pragma unroll
-            for (int t = 0; t < RT1; t++) {
-                Acc d[NF];
-#pragma unroll
-                for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < KS1; s++) {
-                    const auto A = T(SC::OFF1 + t * KS1 + s);
-#pragma unroll
-                    for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, w[i][s]);
+            {  // y faces: neighbour rows' traces from their weights
+                C Fm[NF][4], Fp[NF][4];
+                {
+                    B nb;
+                    load(cidx(iy - 1, z), nb);
+                    C tn[NF][4], tm[NF][4];
+                    trace(nb, 3, tn);
+                    trace(cur, 2, tm);
+                    riemann(std::integral_constant<int, 1>{}, tn, tm, Fm);
                 }
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const bool valid = 16 * t + PR::orow(g, r) < Q;
-                    C q[5], F[3][5];
-#pragma unroll
-                    for (int i = 0; i < 5; i++) q[i] = valid ? d[i][r] : C(1);
-                    euler_flux3<PR>(q, g1, F);
-#pragma unroll
-                    for (int al = 0; al < 3; al++)
-#pragma unroll
-                        for (int i = 0; i < 5; i++) F[al][i] = valid ? F[al][i] : C(0);
-#pragma unroll
-                    for (int rt = 0; rt < RT2; rt++)
-#pragma unroll
-                        for (int al = 0; al < 3; al++) {
-                            const auto A = T(SC::OFF2 + (rt * 3 + al) * NC2 + t * 4 + r);
-#pragma unroll
-                            for (int i = 0; i < NF; i++) acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(&F[al][i]));
-                        }
+                {
+                    B nb;
+                    load(cidx(iy + 1, z), nb);
+                    C tn[NF][4], tp[NF][4];
+                    trace(nb, 2, tn);
+                    trace(cur, 3, tp);
+                    riemann(std::integral_constant<int, 1>{}, tp, tn, Fp);
                 }
+                lift(1, cur, Fm, Fp, acc);
             }
-        } else {
-#pragma unroll
-            for (int tp = 0; tp < RT1 / 2; tp++) {
-                C Fv[3][5][8];
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int t = 2 * tp + h;
-                    Acc d[NF];
-#pragma unroll
-                    for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
-                    const auto A = T(SC::OFF1 + t * KS1);
-#pragma unroll
-                    for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, w[i][0]);
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const bool valid = 16 * t + PR::orow(g, r) < Q;
-                        C q[5], F[3][5];
-#pragma unroll
-                        for (int i = 0; i < 5; i++) q[i] = valid ? d[i][r] : C(1);
-                        euler_flux3<PR>(q, g1, F);
-#pragma unroll
-                        for (int al = 0; al < 3; al++)
-#pragma unroll
-                            for (int i = 0; i < 5; i++) Fv[al][i][4 * h + r] = valid ? F[al][i] : C(0);
-                    }
+            {  // z faces: -z flux carried from the previous step, +z flux with block z+1
+                C Fn[NF][4];
+                {
+                    C tp[NF][4], tm[NF][4];
+                    trace(cur, 5, tp);
+                    trace(nxt, 4, tm);
+                    riemann(std::integral_constant<int, 2>{}, tp, tm, Fn);
                 }
+                lift(2, cur, Fz, Fn, acc);
+#pragma unroll
+                for (int i = 0; i < NF; i++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) Fz[i][r] = Fn[i][r];
+            }
+            // combine and store the interior columns
+            if (keep) {
+                const unsigned cell = cidx(iy, z);
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++)
 #pragma unroll
-                    for (int al = 0; al < 3; al++) {
-                        const auto A = T(SC::OFF2 + (rt * 3 + al) * NC2 + tp);
+                    for (int r = 0; r < 4; r++) {
+                        const int m = 16 * rt + PR::orow(g, r);
+                        if (m < N) {
+                            const unsigned e = (unsigned)m * ncu + cell;
 #pragma unroll
-                        for (int i = 0; i < NF; i++) acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(Fv[al][i]));
-                    }
-            }
-        }
-
-        // ---------------- surface integral: traces -> HLLC -> lift, one axis at a time
-        auto lift = [&](int axis, const C Fm[NF][4], const C Fp[NF][4]) {
-            if constexpr (KPL == 1) {
-#pragma unroll
-                for (int side = 0; side < 2; side++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++)
-#pragma unroll
-                        for (int rt = 0; rt < RT2; rt++) {
-                            const auto A = T(SC::OFF4 + rt * NC4 + (2 * axis + side) * 4 + r);
-#pragma unroll
-                            for (int i = 0; i < NF; i++)
-                                acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(side ? &Fp[i][r] : &Fm[i][r]));
-                        }
-            } else {
-#pragma unroll
-                for (int rt = 0; rt < RT2; rt++) {
-                    const auto A = T(SC::OFF4 + rt * NC4 + axis);
-#pragma unroll
-                    for (int i = 0; i < NF; i++) {
-                        C v[8];
-#pragma unroll
-                        for (int r = 0; r < 4; r++) {
-                            v[r] = Fm[i][r];
-                            v[4 + r] = Fp[i][r];
-                        }
-                        acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(v));
-                    }
-                }
-            }
-        };
-        auto riemann = [&](auto axis_c, const Acc tl[NF], const Acc tr_[NF], C Fo[NF][4]) {
-            constexpr int AX = decltype(axis_c)::value;
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const bool valid = PR::orow(g, r) < P;
-                C qL[5], qR[5], F[5];
-#pragma unroll
-                for (int i = 0; i < 5; i++) {
-                    qL[i] = valid ? (C)tl[i][r] : C(1);
-                    qR[i] = valid ? (C)tr_[i][r] : C(1);
-                }
-                if (!valid) { qL[4] = qR[4] = C(2); }
-                hllc<PR, AX>(qL, qR, gam, F);
-#pragma unroll
-                for (int i = 0; i < 5; i++) Fo[i][r] = valid ? F[i] : C(0);
-            }
-        };
-
-        // x faces: left neighbour's + trace comes from the adjacent lane
-        {
-            Acc tm[NF], tp[NF];
-            trace(w, 0, tm);
-            trace(w, 1, tp);
-            Acc tl[NF];
-#pragma unroll
-            for (int i = 0; i < NF; i++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) tl[i][r] = dpp_shr1((C)tp[i][r]);
-            C Fm[NF][4], Fp[NF][4];
-            riemann(std::integral_constant<int, 0>{}, tl, tm, Fm);
-#pragma unroll
-            for (int i = 0; i < NF; i++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) Fp[i][r] = dpp_shl1(Fm[i][r]);
-            lift(0, Fm, Fp);
-        }
-        // y faces
-        {
-            C Fm[NF][4], Fp[NF][4];
-            {
-                BF wn[NF][KS1];
-                load_w(((long long)iz * ny + (iy + ny - 1) % ny) * nx + xc, wn);
-                Acc tn[NF], tm[NF];
-                trace(wn, 3, tn);
-                trace(w, 2, tm);
-                riemann(std::integral_constant<int, 1>{}, tn, tm, Fm);
-            }
-            {
-                BF wn[NF][KS1];
-                load_w(((long long)iz * ny + (iy + 1) % ny) * nx + xc, wn);
-                Acc tn[NF], tp[NF];
-                trace(wn, 2, tn);
-                trace(w, 3, tp);
-                riemann(std::integral_constant<int, 1>{}, tp, tn, Fp);
-            }
-            lift(1, Fm, Fp);
-        }
-        // z faces
-        {
-            C Fm[NF][4], Fp[NF][4];
-            {
-                BF wn[NF][KS1];
-                load_w(((long long)((iz + nz - 1) % nz) * ny + iy) * nx + xc, wn);
-                Acc tn[NF], tm[NF];
-                trace(wn, 5, tn);
-                trace(w, 4, tm);
-                riemann(std::integral_constant<int, 2>{}, tn, tm, Fm);
-            }
-            {
-                BF wn[NF][KS1];
-                load_w(((long long)((iz + 1) % nz) * ny + iy) * nx + xc, wn);
-                Acc tn[NF], tp[NF];
-                trace(wn, 4, tn);
-                trace(w, 5, tp);
-                riemann(std::integral_constant<int, 2>{}, tp, tn, Fp);
-            }
-            lift(2, Fm, Fp);
-        }
-
-        // ---------------- combine and store the interior columns
-        const bool keep = col >= 1 && col <= BLK_INNER && xraw < nx && xraw >= 0 && (BLK_INNER * bx + col - 1) < nx;
-        if (keep) {
-#pragma unroll
-            for (int rt = 0; rt < RT2; rt++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int m = 16 * rt + PR::orow(g, r);
-                    if (m < N) {
-#pragma unroll
-                        for (int i = 0; i < NF; i++) {
-                            const long long idx = ((long long)i * N + m) * nc + cell;
-                            const C R = (C)acc[i][rt][r];
-                            if (a.mode == 0) {
-                                out[idx] = (S)R;
-                            } else {
-                                const C yv = (C)yin[idx];
-                                const C base = (C)a.b * (yv - dt * R);
-                                out[idx] = (S)(a.a != 0.0 ? (C)a.a * (C)y0[idx] + base : base);
+                            for (int i = 0; i < NF; i++) {
+                                const C R = (C)acc[i][rt][r];
+                                S *dst = reinterpret_cast<S *>(reinterpret_cast<char *>(out + (long long)i * fstride) +
+                                                               e * (unsigned)sizeof(S));
+                                if (a.mode == 0) {
+                                    *dst = (S)R;
+                                } else {
+                                    const C yv = (C)ld(yin, fstride, i, e);
+                                    const C base = (C)a.b * (yv - dt * R);
+                                    *dst = (S)(a.a != 0.0 ? (C)a.a * (C)ld(y0, fstride, i, e) + base : base);
+                                }
                             }
                         }
                     }
-                }
+            }
+            cur = nxt;
         }
     }
 }
