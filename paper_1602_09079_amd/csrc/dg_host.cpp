@@ -141,19 +141,19 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     const int N = L.N, Q = L.Q, P = L.P;
     // values in FP64, one vector per table: [frag][lane][j]
     std::vector<double> t1((size_t)L.rt1 * L.ks1 * 64 * L.kpl, 0.0), t2((size_t)L.rt2 * 3 * L.nc2 * 64 * L.kpl2, 0.0),
-        t3((size_t)6 * L.ks1 * 64 * L.kpl, 0.0), t4((size_t)L.rt2 * L.nc4 * 64 * L.kpl, 0.0),
+        t3((size_t)6 * L.ks1 * 64 * L.kpl, 0.0), t4((size_t)L.rt2 * L.nc4 * 64 * L.kpl2, 0.0),
         t5((size_t)L.rt2 * L.nc2 * 64 * L.kpl2, 0.0);
     auto vol_point = [&](int chunk, int g, int j) {  // volume point at contraction slot (g, j) of a chunk
         if (L.kpl2 == 1) return 16 * (chunk / 4) + out_row(L.prec, g, chunk % 4);
         return 16 * chunk + out_row(L.prec, g, j);
     };
     auto face_slot = [&](int chunk, int g, int j, int &face) {  // (face, point) at slot (g, j)
-        if (L.kpl == 1) {
+        if (L.kpl2 == 1) {
             face = chunk / 4;
             return out_row(L.prec, g, chunk % 4);
         }
-        face = 2 * chunk + (j >= 4);
-        return out_row(L.prec, g, j & 3);
+        face = chunk;
+        return out_row(L.prec, g, j);
     };
     double xi[3];
     for (int lane = 0; lane < 64; lane++) {
@@ -176,6 +176,8 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                         t3[(((size_t)f * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
                     }
                 }
+        }
+        for (int j = 0; j < L.kpl2; j++) {
             for (int rt = 0; rt < L.rt2; rt++)  // T4: s_a (+-1) Phi[m][face point] w_p, outward normal
                 for (int c = 0; c < L.nc4; c++) {
                     int f;
@@ -184,11 +186,9 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                     if (p < P && m < N) {
                         B.face_point(f, p, xi);
                         const double sg = (f & 1) ? 1.0 : -1.0;
-                        t4[(((size_t)rt * L.nc4 + c) * 64 + lane) * L.kpl + j] = s[f / 2] * sg * B.phi(m, xi) * B.face_weight(p);
+                        t4[(((size_t)rt * L.nc4 + c) * 64 + lane) * L.kpl2 + j] = s[f / 2] * sg * B.phi(m, xi) * B.face_weight(p);
                     }
                 }
-        }
-        for (int j = 0; j < L.kpl2; j++) {
             for (int rt = 0; rt < L.rt2; rt++)
                 for (int c = 0; c < L.nc2; c++) {
                     const int m = 16 * rt + row, q = vol_point(c, g, j);
@@ -264,7 +264,7 @@ TableLayout make_layout(int k, int prec) {
     L.rt1 = (L.Q + 15) / 16;
     L.rt2 = (L.N + 15) / 16;
     L.nc2 = bf ? L.rt1 : L.rt1 * 4;
-    L.nc4 = bf ? 3 : 24;
+    L.nc4 = bf ? 6 : 24;
     L.elem = prec == DG_FP64 ? 8 : (prec == DG_FP32 ? 4 : 2);
     L.fb1 = (size_t)64 * L.kpl * L.elem;
     L.fb2 = (size_t)64 * L.kpl2 * L.elem;
@@ -272,7 +272,7 @@ TableLayout make_layout(int k, int prec) {
     L.o2 = L.o1 + (size_t)L.rt1 * L.ks1 * L.fb1;
     L.o3 = L.o2 + (size_t)L.rt2 * 3 * L.nc2 * L.fb2;
     L.o4 = L.o3 + (size_t)6 * L.ks1 * L.fb1;
-    L.o5 = L.o4 + (size_t)L.rt2 * L.nc4 * L.fb1;
+    L.o5 = L.o4 + (size_t)L.rt2 * L.nc4 * L.fb2;
     L.set_bytes = L.o5 + (size_t)L.rt2 * L.nc2 * L.fb2;
     L.ntab = prec == DG_BF16X3 ? 2 : 1;
     return L;

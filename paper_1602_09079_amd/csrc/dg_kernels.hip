@@ -281,13 +281,13 @@ struct StageCfg {
     static constexpr int RT1 = (Q + 15) / 16;
     static constexpr int RT2 = (N + 15) / 16;
     static constexpr int NC2 = KPL2 == 4 ? RT1 : RT1 * 4;
-    static constexpr int NC4 = KPL == 8 ? 3 : 24;
+    static constexpr int NC4 = KPL2 == 4 ? 6 : 24;
     static constexpr int FB1 = 64 * KPL * PR::ESZ, FB2 = 64 * KPL2 * PR::ESZ;
     static constexpr int O1 = 0;
     static constexpr int O2 = O1 + RT1 * KS1 * FB1;
     static constexpr int O3 = O2 + RT2 * 3 * NC2 * FB2;
     static constexpr int O4 = O3 + 6 * KS1 * FB1;
-    static constexpr int O5 = O4 + RT2 * NC4 * FB1;
+    static constexpr int O5 = O4 + RT2 * NC4 * FB2;
     static constexpr int SET = O5 + RT2 * NC2 * FB2;
     static constexpr int NTAB = PREC == DG_BF16X3 ? 2 : 1;
     static constexpr bool QFULL = (Q % 16) == 0;  // no padded volume rows
@@ -326,16 +326,16 @@ struct TabReader {
         return narrow(SC::O2 + ((rt * 3 + al) * SC::NC2 + c) * SC::FB2);
     }
     __device__ typename PR::AF t3(int f, int s) const { return wide(SC::O3 + (f * SC::KS1 + s) * SC::FB1); }
-    __device__ typename PR::AF t4(int rt, int c) const { return wide(SC::O4 + (rt * SC::NC4 + c) * SC::FB1); }
+    __device__ typename PR::AF2 t4(int rt, int c) const { return narrow(SC::O4 + (rt * SC::NC4 + c) * SC::FB2); }
     __device__ typename PR::AF2 t5(int rt, int c) const { return narrow(SC::O5 + (rt * SC::NC2 + c) * SC::FB2); }
 };
 
 constexpr int STAGE_THREADS = 256;
 
-// Waves per SIMD the stage kernel is compiled for (register budget 512 / this).
-#ifndef DG_STAGE_WAVES_PER_EU
-#define DG_STAGE_WAVES_PER_EU 2
-#endif
+// Waves per SIMD the stage kernel is compiled for (register budget 512 / this):
+// two for the FP32-storage tiers, one for FP64, whose doubles need the full file.
+template <int PREC>
+constexpr int stage_waves_per_eu() { return PREC == DG_FP64 ? 1 : 2; }
 
 // The weights of one block of 16 cells in B-operand layout, without mode 0,
 // plus the cell means in full precision.
@@ -354,7 +354,7 @@ __device__ inline S ld(const S *base, long long fieldstride, int i, unsigned e) 
 }
 
 template <int K, int PREC>
-__global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(DG_STAGE_WAVES_PER_EU, DG_STAGE_WAVES_PER_EU))) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
     using PR = typename SC::PR;
     using C = typename PR::C;
@@ -450,43 +450,33 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(D
 #pragma unroll
         for (int i = 0; i < 5; i++) Fb[i] = F3[axis][i];
     };
-    // lift of the two face fluxes of one axis, minus the cell-mean flux
-    auto lift = [&](int axis, const B &b, const C Fm[NF][4], const C Fp[NF][4], Acc acc[NF][RT2]) {
+    // lift of one face flux (face = 2*axis + side) minus the cell-mean flux, GEMM4
+    auto lift = [&](int face, const B &b, const C Fh[NF][4], Acc acc[NF][RT2]) {
         C Fb[5];
-        mean_flux(b, axis, Fb);
-        C vm[NF][4], vp[NF][4];
+        mean_flux(b, face >> 1, Fb);
+        C v[NF][4];
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const bool valid = SC::PFULL || PR::orow(g, r) < P;
-                vm[i][r] = valid ? Fm[i][r] - Fb[i] : C(0);
-                vp[i][r] = valid ? Fp[i][r] - Fb[i] : C(0);
+                v[i][r] = valid ? Fh[i][r] - Fb[i] : C(0);
             }
-        if constexpr (KPL == 1) {
+        if constexpr (KPL2 == 1) {
 #pragma unroll
-            for (int side = 0; side < 2; side++)
+            for (int r = 0; r < 4; r++)
 #pragma unroll
-                for (int r = 0; r < 4; r++)
+                for (int rt = 0; rt < RT2; rt++) {
+                    const auto A = T.t4(rt, face * 4 + r);
 #pragma unroll
-                    for (int rt = 0; rt < RT2; rt++) {
-                        const auto A = T.t4(rt, (2 * axis + side) * 4 + r);
-#pragma unroll
-                        for (int i = 0; i < NF; i++)
-                            acc[i][rt] = PR::mma(acc[i][rt], A, PR::mkb(side ? &vp[i][r] : &vm[i][r]));
-                    }
+                    for (int i = 0; i < NF; i++) acc[i][rt] = PR::mma2(acc[i][rt], A, PR::mkb2(&v[i][r]));
+                }
         } else {
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                C v[8];
+                const auto bf = PR::mkb2(v[i]);
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    v[r] = vm[i][r];
-                    v[4 + r] = vp[i][r];
-                }
-                const auto bf = PR::mkb(v);
-#pragma unroll
-                for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma(acc[i][rt], T.t4(rt, axis), bf);
+                for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t4(rt, face), bf);
             }
         }
     };
@@ -602,9 +592,10 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(D
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
 
+            lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
             volume(cur, acc);
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
-                C tl[NF][4], Fm[NF][4], Fp[NF][4];
+                C tl[NF][4], Fh[NF][4];
                 {
                     C tp[NF][4];
                     trace(cur, 1, tp);
@@ -616,47 +607,49 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(D
                 {
                     C tm[NF][4];
                     trace(cur, 0, tm);
-                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fm);
+                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fh);
                 }
+                lift(0, cur, Fh, acc);
+                // the + face flux of a column is the - face flux of its right neighbour
 #pragma unroll
                 for (int i = 0; i < NF; i++)
 #pragma unroll
-                    for (int r = 0; r < 4; r++) Fp[i][r] = dpp_shl1(Fm[i][r]);
-                lift(0, cur, Fm, Fp, acc);
+                    for (int r = 0; r < 4; r++) Fh[i][r] = dpp_shl1(Fh[i][r]);
+                lift(1, cur, Fh, acc);
             }
             {  // y faces: neighbour rows' traces from their weights
-                C Fm[NF][4], Fp[NF][4];
+                C Fh[NF][4];
                 {
-                    B nb;
-                    load(cidx(iy - 1, z), nb);
-                    C tn[NF][4], tm[NF][4];
-                    trace(nb, 3, tn);
+                    C tn[NF][4];
+                    {
+                        B nb;
+                        load(cidx(iy - 1, z), nb);
+                        trace(nb, 3, tn);
+                    }
+                    C tm[NF][4];
                     trace(cur, 2, tm);
-                    riemann(std::integral_constant<int, 1>{}, tn, tm, Fm);
+                    riemann(std::integral_constant<int, 1>{}, tn, tm, Fh);
                 }
+                lift(2, cur, Fh, acc);
                 {
-                    B nb;
-                    load(cidx(iy + 1, z), nb);
-                    C tn[NF][4], tp[NF][4];
-                    trace(nb, 2, tn);
+                    C tn[NF][4];
+                    {
+                        B nb;
+                        load(cidx(iy + 1, z), nb);
+                        trace(nb, 2, tn);
+                    }
+                    C tp[NF][4];
                     trace(cur, 3, tp);
-                    riemann(std::integral_constant<int, 1>{}, tp, tn, Fp);
+                    riemann(std::integral_constant<int, 1>{}, tp, tn, Fh);
                 }
-                lift(1, cur, Fm, Fp, acc);
+                lift(3, cur, Fh, acc);
             }
-            {  // z faces: -z flux carried from the previous step, +z flux with block z+1
-                C Fn[NF][4];
-                {
-                    C tp[NF][4], tm[NF][4];
-                    trace(cur, 5, tp);
-                    trace(nxt, 4, tm);
-                    riemann(std::integral_constant<int, 2>{}, tp, tm, Fn);
-                }
-                lift(2, cur, Fz, Fn, acc);
-#pragma unroll
-                for (int i = 0; i < NF; i++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) Fz[i][r] = Fn[i][r];
+            {  // +z face with block z+1; its flux is the -z flux of the next step
+                C tp[NF][4], tm[NF][4];
+                trace(cur, 5, tp);
+                trace(nxt, 4, tm);
+                riemann(std::integral_constant<int, 2>{}, tp, tm, Fz);
+                lift(5, cur, Fz, acc);
             }
             // combine and store the interior columns
             if (keep) {
