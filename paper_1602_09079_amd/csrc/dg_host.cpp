@@ -163,7 +163,7 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
             for (int t = 0; t < L.rt1; t++)  // T1: Phi[q][m]
                 for (int st = 0; st < L.ks1; st++) {
                     const int q = 16 * t + row, m = st * L.kstep + kk;
-                    if (q < Q && m < N) {
+                    if (q < Q && m >= 1 && m < N) {  // mode 0 (the mean) is added apart
                         B.point(q, xi);
                         t1[(((size_t)t * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
                     }
@@ -171,7 +171,7 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
             for (int f = 0; f < 6; f++)  // T3: Phi[face point][m]
                 for (int st = 0; st < L.ks1; st++) {
                     const int p = row, m = st * L.kstep + kk;
-                    if (p < P && m < N) {
+                    if (p < P && m >= 1 && m < N) {  // mode 0 (the mean) is added apart
                         B.face_point(f, p, xi);
                         t3[(((size_t)f * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
                     }

@@ -47,6 +47,34 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bv2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// round-to-nearest-even float -> bf16 conversion of pairs (one v_cvt_pk_bf16_f32 each)
+template <int L, class V>
+__device__ inline void to_bf16(const float *v, V &out) {
+#pragma unroll
+    for (int j = 0; j < L; j += 2) {
+        const bv2 h = __builtin_convertvector((fv2){v[j], v[j + 1]}, bv2);
+        out[j] = h[0];
+        out[j + 1] = h[1];
+    }
+}
+// x = hi + lo split: hi = bf16(x), lo = bf16(x - hi)
+template <int L, class V>
+__device__ inline void to_bf16x2(const float *v, V &hi, V &lo) {
+#pragma unroll
+    for (int j = 0; j < L; j += 2) {
+        const bv2 h = __builtin_convertvector((fv2){v[j], v[j + 1]}, bv2);
+        const fv2 hf = __builtin_convertvector(h, fv2);
+        const bv2 l = __builtin_convertvector((fv2){v[j] - hf[0], v[j + 1] - hf[1]}, bv2);
+        hi[j] = h[0];
+        hi[j + 1] = h[1];
+        lo[j] = l[0];
+        lo[j + 1] = l[1];
+    }
+}
 
 template <int K>
 struct Dims {
@@ -126,14 +154,12 @@ struct Prec<DG_BF16> {
     __device__ static int orow(int g, int r) { return 4 * g + r; }
     __device__ static BF mkb(const C *v) {
         BF b;
-#pragma unroll
-        for (int j = 0; j < 8; j++) b.v[j] = (__bf16)v[j];
+        to_bf16<8>(v, b.v);
         return b;
     }
     __device__ static BF2 mkb2(const C *v) {
         BF2 b;
-#pragma unroll
-        for (int j = 0; j < 4; j++) b.v[j] = (__bf16)v[j];
+        to_bf16<4>(v, b.v);
         return b;
     }
     __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
@@ -168,23 +194,14 @@ struct Prec<DG_BF16X3> {
                                                           0, 0, 0);
     }
     __device__ static int orow(int g, int r) { return 4 * g + r; }
-    template <int L, class V>
-    __device__ static void split(const C *v, V &hi, V &lo) {
-#pragma unroll
-        for (int j = 0; j < L; j++) {
-            const __bf16 h = (__bf16)v[j];
-            hi[j] = h;
-            lo[j] = (__bf16)(v[j] - (float)h);
-        }
-    }
     __device__ static BF mkb(const C *v) {
         BF b;
-        split<8>(v, b.hi, b.lo);
+        to_bf16x2<8>(v, b.hi, b.lo);
         return b;
     }
     __device__ static BF2 mkb2(const C *v) {
         BF2 b;
-        split<4>(v, b.hi, b.lo);
+        to_bf16x2<4>(v, b.hi, b.lo);
         return b;
     }
     __device__ static C rcp(C x) { return __builtin_amdgcn_rcpf(x); }
@@ -345,12 +362,31 @@ struct Blk {
     typename Prec<PREC>::C qbar[NF];
 };
 
-// element e of field i of a state, addressed from the field's (uniform) base with
-// a 32-bit unsigned byte offset
+// Buffer access to one field of a state: a resource per field (base, size in
+// bytes), a per-lane byte offset in a VGPR and a wave-uniform byte offset in an
+// SGPR.  All offsets the kernel forms lie inside the field.
+constexpr int BUF_DWORD3 = 0x00020000;  // 32-bit data format (gfx9 family)
+
+// The base is passed through an opaque copy so the resource is rebuilt (a few
+// scalar instructions) where it is used instead of being kept live in SGPRs.
 template <class S>
-__device__ inline S ld(const S *base, long long fieldstride, int i, unsigned e) {
-    const char *fb = reinterpret_cast<const char *>(base + (long long)i * fieldstride);
-    return *reinterpret_cast<const S *>(fb + e * (unsigned)sizeof(S));
+__device__ inline __amdgpu_buffer_rsrc_t field_rsrc(const S *base, long long fieldstride, int i) {
+    const S *p = base + (long long)i * fieldstride;
+    asm volatile("" : "+s"(p));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0,
+                                             (int)(unsigned)(fieldstride * (long long)sizeof(S)), BUF_DWORD3);
+}
+__device__ inline float bload(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline double bload(double, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ inline void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, 0, 0);
+}
+__device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
 }
 
 template <int K, int PREC>
@@ -374,7 +410,7 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         __syncthreads();
     }
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int col = lane & 15;
     const int g = lane >> 4;
     TabReader<K, PREC> T{lds, lane * KPL * PR::ESZ, lane * KPL2 * PR::ESZ};
@@ -385,8 +421,8 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     if (a.rate) dtd = a.dtfac / a.rate[0];
     const C dt = (C)dtd;
     if (a.tacc && blockIdx.x == 0 && threadIdx.x == 0) a.tacc[0] += dtd;
-    const S *__restrict__ yin = reinterpret_cast<const S *>(a.yin);
-    const S *__restrict__ y0 = reinterpret_cast<const S *>(a.y0);
+    const S *yin = reinterpret_cast<const S *>(a.yin);
+    const S *y0 = reinterpret_cast<const S *>(a.y0);
     S *out = reinterpret_cast<S *>(a.out);
     const long long nc = a.ncells;
     const long long fstride = (long long)N * nc;
@@ -394,23 +430,37 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
     // ---------------- building blocks
-    auto load = [&](unsigned cell, B &b) {
+    // Per-lane byte offsets of the rows this lane feeds to the B operand
+    // (mode m = s*KSTEP + g*KPL + j; rows past the last mode are clamped to it,
+    // their table entries are zero, and so are mode 0's: the mean enters apart).
+    unsigned boff[KS1][KPL];
+    unsigned xoff = 0;
+    const unsigned esz = (unsigned)sizeof(S);
+    auto set_lane_offsets = [&](int xc) {
+        xoff = (unsigned)xc * esz;
 #pragma unroll
-        for (int i = 0; i < NF; i++) b.qbar[i] = (C)ld(yin, fstride, i, cell);
+        for (int s = 0; s < KS1; s++)
 #pragma unroll
-        for (int i = 0; i < NF; i++)
+            for (int j = 0; j < KPL; j++) {
+                const int m = s * KSTEP + g * KPL + j;
+                boff[s][j] = (unsigned)(m < N ? m : N - 1) * ncu * esz + xoff;
+            }
+    };
+    // block whose first column sits at cell index rowbase (wave-uniform) + xc
+    auto load = [&](unsigned rowbase, B &b) {
+        const unsigned so = rowbase * esz;
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            const auto rs = field_rsrc(yin, fstride, i);
+            b.qbar[i] = (C)bload(S(), rs, xoff, so);
 #pragma unroll
             for (int s = 0; s < KS1; s++) {
                 C v[KPL];
 #pragma unroll
-                for (int j = 0; j < KPL; j++) {
-                    const int m = s * KSTEP + g * KPL + j;
-                    const int mc = m < 1 ? 1 : (m > N - 1 ? N - 1 : m);
-                    const C x = (C)ld(yin, fstride, i, (unsigned)mc * ncu + cell);
-                    v[j] = (m >= 1 && m < N) ? x : C(0);
-                }
+                for (int j = 0; j < KPL; j++) v[j] = (C)bload(S(), rs, boff[s][j], so);
                 b.w[i][s] = PR::mkb(v);
             }
+        }
     };
     auto trace = [&](const B &b, int face, C tr[NF][4]) {
         Acc t[NF];
@@ -564,10 +614,11 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         const int xraw = BLK_INNER * bx - 1 + col;  // -1 .. : periodic wrap
         const int xc = (xraw % nx + nx) % nx;
         const bool keep = col >= 1 && col <= BLK_INNER && xraw < nx;
-        auto cidx = [&](int yy, int zz) -> unsigned {
-            yy = (yy + ny) % ny;
-            zz = (zz + nz) % nz;
-            return (unsigned)(((long long)zz * ny + yy) * nx + xc);
+        set_lane_offsets(xc);
+        auto cidx = [&](int yy, int zz) -> unsigned {  // first cell of the row (wave-uniform)
+            yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+            zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+            return (unsigned)(((long long)zz * ny + yy) * nx);
         };
 
         T.refresh();
@@ -653,25 +704,26 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
             }
             // combine and store the interior columns
             if (keep) {
-                const unsigned cell = cidx(iy, z);
+                const unsigned so = cidx(iy, z) * esz;
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++)
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int m = 16 * rt + PR::orow(g, r);
                         if (m < N) {
-                            const unsigned e = (unsigned)m * ncu + cell;
+                            const unsigned e = (unsigned)m * ncu * esz + xoff;
 #pragma unroll
                             for (int i = 0; i < NF; i++) {
                                 const C R = (C)acc[i][rt][r];
-                                S *dst = reinterpret_cast<S *>(reinterpret_cast<char *>(out + (long long)i * fstride) +
-                                                               e * (unsigned)sizeof(S));
+                                const auto ro = field_rsrc(out, fstride, i);
                                 if (a.mode == 0) {
-                                    *dst = (S)R;
+                                    bstore((S)R, ro, e + so);
                                 } else {
-                                    const C yv = (C)ld(yin, fstride, i, e);
+                                    const C yv = (C)bload(S(), field_rsrc(yin, fstride, i), e, so);
                                     const C base = (C)a.b * (yv - dt * R);
-                                    *dst = (S)(a.a != 0.0 ? (C)a.a * (C)ld(y0, fstride, i, e) + base : base);
+                                    const C res = a.a != 0.0 ? (C)a.a * (C)bload(S(), field_rsrc(y0, fstride, i), e, so) + base
+                                                             : base;
+                                    bstore((S)res, ro, e + so);
                                 }
                             }
                         }
