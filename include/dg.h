@@ -9,10 +9,12 @@
  * ---------------------------------------
  * State.  A state holds the weights w_{i,l}^K of Sec. 2 (the expansion of the
  *   five conserved fields in the orthonormal scaled-Legendre basis of Sec.
- *   2.1).  Element order is y[i][l][z][y][x] with x fastest; i = 0..4 is
- *   (rho, m_x, m_y, m_z, E); l = 0..N(k)-1 runs over the modes of total degree
- *   <= k, graded by degree d = 0..k, then u descending, then v descending,
- *   w = d-u-v (k=1: (000),(100),(010),(001)).  Mode 0 is the cell mean.
+ *   2.1).  Element order is y[z][y][i][l][x] with x fastest: for every row of
+ *   cells (fixed y, z) the 5 N(k) rows of that row's weights form one
+ *   contiguous slab.  i = 0..4 is (rho, m_x, m_y, m_z, E); l = 0..N(k)-1 runs
+ *   over the modes of total degree <= k, graded by degree d = 0..k, then u
+ *   descending, then v descending, w = d-u-v (k=1: (000),(100),(010),(001)).
+ *   Mode 0 is the cell mean.
  *   The basis is normalised so that (1/8) int_{[-1,1]^3} phi_l phi_m = delta_lm.
  * Storage type.  double for DG_FP64, float for DG_FP32, DG_BF16 and
  *   DG_BF16X3 (the last two differ only in how the contractions run).
@@ -74,7 +76,8 @@ typedef struct {
  * upload them and allocate the context's small device slots (dt, time,
  * partial sums).  hip_stream: a hipStream_t (NULL = default stream).
  * DG_ERR_ARG and no context for: k < 1, any n < 2, box <= 0, gamma <= 1,
- * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3. */
+ * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3
+ * or a slab (5 N(k) n[0] elements) of 2 GiB or more. */
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out);
 
 /* Release the context and its device memory.  NULL is accepted. */

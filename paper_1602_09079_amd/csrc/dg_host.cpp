@@ -309,12 +309,9 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CHECK_RANGE)) return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
     {
-        // the kernels address one field of a state with 32-bit unsigned byte offsets
-        const double field_bytes = (double)nmodes_of(cfg->k) * cfg->n[0] * cfg->n[1] * cfg->n[2] *
-                                   (cfg->precision == DG_FP64 ? 8.0 : 4.0);
-        const double qp_field_bytes = (double)(cfg->k + 1) * (cfg->k + 1) * (cfg->k + 1) * cfg->n[0] * cfg->n[1] *
-                                      cfg->n[2] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
-        if (field_bytes >= 4294967296.0 || qp_field_bytes >= 4294967296.0 * 5) return DG_ERR_UNSUPPORTED;
+        // the stage kernel addresses one (z, y) slab of 5 N(k) rows of n[0] cells with 32-bit offsets
+        const double slab_bytes = 5.0 * nmodes_of(cfg->k) * cfg->n[0] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
+        if (slab_bytes >= 2147483648.0) return DG_ERR_UNSUPPORTED;
     }
     const long long ncells = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
     if ((long long)cfg->n[0] > (1LL << 30) || ncells > (1LL << 40)) return DG_ERR_ARG;
@@ -402,7 +399,7 @@ dg_status dg_project(dg_ctx *c, const void *qp, void *y) {
         c->err = "dg_project: NULL pointer";
         return DG_ERR_ARG;
     }
-    HIPCHK(c, launch_project(c->cfg.k, c->cfg.precision, qp, y, c->ptab, c->ncells, c->stream));
+    HIPCHK(c, launch_project(c->cfg.k, c->cfg.precision, qp, y, c->ptab, c->ncells, c->cfg.n[0], c->stream));
     return DG_OK;
 }
 
@@ -447,7 +444,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
 // CFL rate into the free slot; it becomes the current one.
 dg_status run_cfl(dg_ctx *c, const void *y) {
     const int nxt = 1 - c->cur_slot;
-    HIPCHK(c, launch_cfl(c->cfg.precision, y, c->N, c->ncells, c->cfg.gamma, c->h, c->slots + nxt,
+    HIPCHK(c, launch_cfl(c->cfg.precision, y, c->N, c->cfg.n[0], c->ncells, c->cfg.gamma, c->h, c->slots + nxt,
                          c->slots + c->cur_slot, c->stream));
     c->cur_slot = nxt;
     return DG_OK;
@@ -514,7 +511,7 @@ dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, dou
         if (check) {
             int flag = 0;
             HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
-            HIPCHK(c, launch_range_check(c->cfg.precision, y, c->N, c->ncells, c->cfg.gamma, c->flag, c->stream));
+            HIPCHK(c, launch_range_check(c->cfg.precision, y, c->N, c->cfg.n[0], c->ncells, c->cfg.gamma, c->flag, c->stream));
             HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             if (flag) {
@@ -545,7 +542,7 @@ dg_status dg_totals(dg_ctx *c, const void *y, double out[5]) {
     }
     const double vol = c->h[0] * c->h[1] * c->h[2];
     double *dres = c->partials + (size_t)NF * c->nparts;
-    HIPCHK(c, launch_totals(c->cfg.precision, y, c->N, c->ncells, vol, c->partials, c->nparts, dres, c->stream));
+    HIPCHK(c, launch_totals(c->cfg.precision, y, c->N, c->cfg.n[0], c->ncells, vol, c->partials, c->nparts, dres, c->stream));
     HIPCHK(c, hipMemcpyAsync(out, dres, NF * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DG_OK;

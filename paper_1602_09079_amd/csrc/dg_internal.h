@@ -73,13 +73,13 @@ hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_b
 hipError_t set_stage_attributes(int k, int prec, int lds_bytes);
 int stage_block_threads();
 
-hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long ncells,
+hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long ncells, int nx,
                           hipStream_t s);
-hipError_t launch_cfl(int prec, const void *y, int N, long long ncells, double gamma, const double h[3],
+hipError_t launch_cfl(int prec, const void *y, int N, int nx, long long ncells, double gamma, const double h[3],
                       double *rate_slot, double *zero_slot, hipStream_t s);
-hipError_t launch_totals(int prec, const void *y, int N, long long ncells, double vol, double *partials,
+hipError_t launch_totals(int prec, const void *y, int N, int nx, long long ncells, double vol, double *partials,
                          int nparts, double *out, hipStream_t s);
-hipError_t launch_range_check(int prec, const void *y, int N, long long ncells, double gamma, int *flag,
+hipError_t launch_range_check(int prec, const void *y, int N, int nx, long long ncells, double gamma, int *flag,
                               hipStream_t s);
 
 }  // namespace dgmi

@@ -362,19 +362,21 @@ struct Blk {
     typename Prec<PREC>::C qbar[NF];
 };
 
-// Buffer access to one field of a state: a resource per field (base, size in
-// bytes), a per-lane byte offset in a VGPR and a wave-uniform byte offset in an
-// SGPR.  All offsets the kernel forms lie inside the field.
+// Buffer access to one (z, y) slab of a state: the state is stored
+// [z][y][i][l][x], so the 5 N rows of a y-row of cells (one per field and mode)
+// are one contiguous slab.  A resource per slab (base, size in bytes), a per-lane
+// byte offset in a VGPR (mode row and x) and a wave-uniform byte offset in an
+// SGPR (field).  All offsets the kernel forms lie inside the slab.
 constexpr int BUF_DWORD3 = 0x00020000;  // 32-bit data format (gfx9 family)
 
 // The base is passed through an opaque copy so the resource is rebuilt (a few
 // scalar instructions) where it is used instead of being kept live in SGPRs.
 template <class S>
-__device__ inline __amdgpu_buffer_rsrc_t field_rsrc(const S *base, long long fieldstride, int i) {
-    const S *p = base + (long long)i * fieldstride;
+__device__ inline __amdgpu_buffer_rsrc_t slab_rsrc(const S *base, long long slab_elems, long long r) {
+    const S *p = base + r * slab_elems;
     asm volatile("" : "+s"(p));
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<S *>(p), (short)0,
-                                             (int)(unsigned)(fieldstride * (long long)sizeof(S)), BUF_DWORD3);
+                                             (int)(unsigned)(slab_elems * (long long)sizeof(S)), BUF_DWORD3);
 }
 __device__ inline float bload(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
@@ -425,8 +427,8 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     const S *y0 = reinterpret_cast<const S *>(a.y0);
     S *out = reinterpret_cast<S *>(a.out);
     const long long nc = a.ncells;
-    const long long fstride = (long long)N * nc;
-    const unsigned ncu = (unsigned)nc;
+    const long long slabn = (long long)NF * N * a.nx;  // elements per (z, y) slab
+    const unsigned nxu = (unsigned)a.nx;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
     // ---------------- building blocks
@@ -436,6 +438,7 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     unsigned boff[KS1][KPL];
     unsigned xoff = 0;
     const unsigned esz = (unsigned)sizeof(S);
+    const unsigned fbytes = (unsigned)N * nxu * esz;  // one field of a slab
     auto set_lane_offsets = [&](int xc) {
         xoff = (unsigned)xc * esz;
 #pragma unroll
@@ -443,15 +446,15 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 #pragma unroll
             for (int j = 0; j < KPL; j++) {
                 const int m = s * KSTEP + g * KPL + j;
-                boff[s][j] = (unsigned)(m < N ? m : N - 1) * ncu * esz + xoff;
+                boff[s][j] = (unsigned)(m < N ? m : N - 1) * nxu * esz + xoff;
             }
     };
-    // block whose first column sits at cell index rowbase (wave-uniform) + xc
-    auto load = [&](unsigned rowbase, B &b) {
-        const unsigned so = rowbase * esz;
+    // the block of slab r (wave-uniform) whose first column is at x = xc
+    auto load = [&](long long r, B &b) {
+        const auto rs = slab_rsrc(yin, slabn, r);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            const auto rs = field_rsrc(yin, fstride, i);
+            const unsigned so = (unsigned)i * fbytes;
             b.qbar[i] = (C)bload(S(), rs, xoff, so);
 #pragma unroll
             for (int s = 0; s < KS1; s++) {
@@ -615,10 +618,10 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         const int xc = (xraw % nx + nx) % nx;
         const bool keep = col >= 1 && col <= BLK_INNER && xraw < nx;
         set_lane_offsets(xc);
-        auto cidx = [&](int yy, int zz) -> unsigned {  // first cell of the row (wave-uniform)
+        auto cidx = [&](int yy, int zz) -> long long {  // slab index (wave-uniform), periodic
             yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
             zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-            return (unsigned)(((long long)zz * ny + yy) * nx);
+            return (long long)zz * ny + yy;
         };
 
         T.refresh();
@@ -704,25 +707,27 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
             }
             // combine and store the interior columns
             if (keep) {
-                const unsigned so = cidx(iy, z) * esz;
+                const long long rz = cidx(iy, z);
+                const auto ro = slab_rsrc(out, slabn, rz);
+                const auto ri = slab_rsrc(yin, slabn, rz);
+                const auto r0 = slab_rsrc(y0, slabn, rz);
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++)
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int m = 16 * rt + PR::orow(g, r);
                         if (m < N) {
-                            const unsigned e = (unsigned)m * ncu * esz + xoff;
+                            const unsigned e = (unsigned)m * nxu * esz + xoff;
 #pragma unroll
                             for (int i = 0; i < NF; i++) {
+                                const unsigned so = (unsigned)i * fbytes;
                                 const C R = (C)acc[i][rt][r];
-                                const auto ro = field_rsrc(out, fstride, i);
                                 if (a.mode == 0) {
                                     bstore((S)R, ro, e + so);
                                 } else {
-                                    const C yv = (C)bload(S(), field_rsrc(yin, fstride, i), e, so);
+                                    const C yv = (C)bload(S(), ri, e, so);
                                     const C base = (C)a.b * (yv - dt * R);
-                                    const C res = a.a != 0.0 ? (C)a.a * (C)bload(S(), field_rsrc(y0, fstride, i), e, so) + base
-                                                             : base;
+                                    const C res = a.a != 0.0 ? (C)a.a * (C)bload(S(), r0, e, so) + base : base;
                                     bstore((S)res, ro, e + so);
                                 }
                             }
@@ -785,10 +790,12 @@ namespace dgmi {
 
 template <int K, class S>
 __global__ void project_kernel(const S *__restrict__ qp, S *__restrict__ y, const double *__restrict__ ptab,
-                               long long nc) {
+                               long long nc, int nx) {
     constexpr int N = Dims<K>::N, Q = Dims<K>::Q;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= nc) return;
+    const long long r = cell / nx;
+    const int x = (int)(cell - r * nx);
     for (int i = 0; i < NF; i++) {
         double s[N];
 #pragma unroll
@@ -799,30 +806,30 @@ __global__ void project_kernel(const S *__restrict__ qp, S *__restrict__ y, cons
             for (int l = 0; l < N; l++) s[l] += v * ptab[q * N + l];
         }
 #pragma unroll
-        for (int l = 0; l < N; l++) y[((long long)i * N + l) * nc + cell] = (S)s[l];
+        for (int l = 0; l < N; l++) y[((r * NF + i) * N + l) * nx + x] = (S)s[l];
     }
 }
 
 template <int K>
-static hipError_t launch_project_k(int prec, const void *qp, void *y, const double *ptab, long long nc,
+static hipError_t launch_project_k(int prec, const void *qp, void *y, const double *ptab, long long nc, int nx,
                                    hipStream_t s) {
     const int th = 256;
     const long long nb = (nc + th - 1) / th;
     if (prec == DG_FP64)
         hipLaunchKernelGGL((project_kernel<K, double>), dim3(nb), dim3(th), 0, s, (const double *)qp, (double *)y,
-                           ptab, nc);
+                           ptab, nc, nx);
     else
         hipLaunchKernelGGL((project_kernel<K, float>), dim3(nb), dim3(th), 0, s, (const float *)qp, (float *)y, ptab,
-                           nc);
+                           nc, nx);
     return hipGetLastError();
 }
 
-hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long nc,
+hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long nc, int nx,
                           hipStream_t s) {
     switch (k) {
-        case 1: return launch_project_k<1>(prec, qp, y, ptab, nc, s);
-        case 2: return launch_project_k<2>(prec, qp, y, ptab, nc, s);
-        case 3: return launch_project_k<3>(prec, qp, y, ptab, nc, s);
+        case 1: return launch_project_k<1>(prec, qp, y, ptab, nc, nx, s);
+        case 2: return launch_project_k<2>(prec, qp, y, ptab, nc, nx, s);
+        case 3: return launch_project_k<3>(prec, qp, y, ptab, nc, nx, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -835,17 +842,23 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// index of mode 0 of field i of a cell in the [z][y][i][l][x] layout
+__device__ inline long long mean_index(long long cell, int i, int N, int nx) {
+    const long long r = cell / nx;
+    return ((r * NF + i) * N) * nx + (cell - r * nx);
+}
+
 template <class S>
-__global__ void cfl_kernel(const S *__restrict__ y, int N, long long nc, double gamma, double hx, double hy,
+__global__ void cfl_kernel(const S *__restrict__ y, int N, int nx, long long nc, double gamma, double hx, double hy,
                            double hz, double *rate_slot, double *zero_slot) {
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double rate = 0.0;
     if (cell < nc) {
-        const double rho = (double)y[(0LL * N) * nc + cell];
-        const double mx = (double)y[(1LL * N) * nc + cell];
-        const double my = (double)y[(2LL * N) * nc + cell];
-        const double mz = (double)y[(3LL * N) * nc + cell];
-        const double E = (double)y[(4LL * N) * nc + cell];
+        const double rho = (double)y[mean_index(cell, 0, N, nx)];
+        const double mx = (double)y[mean_index(cell, 1, N, nx)];
+        const double my = (double)y[mean_index(cell, 2, N, nx)];
+        const double mz = (double)y[mean_index(cell, 3, N, nx)];
+        const double E = (double)y[mean_index(cell, 4, N, nx)];
         const double inv = 1.0 / rho;
         const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) * inv);
         const double c = sqrt(gamma * p * inv);
@@ -858,16 +871,16 @@ __global__ void cfl_kernel(const S *__restrict__ y, int N, long long nc, double 
     if (blockIdx.x == 0 && threadIdx.x == 0 && zero_slot) *zero_slot = 0.0;
 }
 
-hipError_t launch_cfl(int prec, const void *y, int N, long long nc, double gamma, const double h[3],
+hipError_t launch_cfl(int prec, const void *y, int N, int nx, long long nc, double gamma, const double h[3],
                       double *rate_slot, double *zero_slot, hipStream_t s) {
     const int th = 256;
     const long long nb = (nc + th - 1) / th;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((cfl_kernel<double>), dim3(nb), dim3(th), 0, s, (const double *)y, N, nc, gamma, h[0], h[1],
-                           h[2], rate_slot, zero_slot);
+        hipLaunchKernelGGL((cfl_kernel<double>), dim3(nb), dim3(th), 0, s, (const double *)y, N, nx, nc, gamma, h[0],
+                           h[1], h[2], rate_slot, zero_slot);
     else
-        hipLaunchKernelGGL((cfl_kernel<float>), dim3(nb), dim3(th), 0, s, (const float *)y, N, nc, gamma, h[0], h[1],
-                           h[2], rate_slot, zero_slot);
+        hipLaunchKernelGGL((cfl_kernel<float>), dim3(nb), dim3(th), 0, s, (const float *)y, N, nx, nc, gamma, h[0],
+                           h[1], h[2], rate_slot, zero_slot);
     return hipGetLastError();
 }
 
@@ -876,14 +889,14 @@ hipError_t launch_cfl(int prec, const void *y, int N, long long nc, double gamma
 constexpr int TOT_THREADS = 256;
 
 template <class S>
-__global__ void totals_pass1(const S *__restrict__ y, int N, long long nc, double *partials, int nparts) {
+__global__ void totals_pass1(const S *__restrict__ y, int N, int nx, long long nc, double *partials, int nparts) {
     __shared__ double red[TOT_THREADS];
     const long long chunk = (nc + nparts - 1) / nparts;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = lo + chunk < nc ? lo + chunk : nc;
     for (int i = 0; i < NF; i++) {
         double s = 0.0;
-        for (long long c = lo + threadIdx.x; c < hi; c += TOT_THREADS) s += (double)y[((long long)i * N) * nc + c];
+        for (long long c = lo + threadIdx.x; c < hi; c += TOT_THREADS) s += (double)y[mean_index(c, i, N, nx)];
         red[threadIdx.x] = s;
         __syncthreads();
         for (int w = TOT_THREADS / 2; w > 0; w >>= 1) {
@@ -911,13 +924,13 @@ __global__ void totals_pass2(const double *partials, int nparts, double vol, dou
     }
 }
 
-hipError_t launch_totals(int prec, const void *y, int N, long long nc, double vol, double *partials, int nparts,
-                         double *out, hipStream_t s) {
+hipError_t launch_totals(int prec, const void *y, int N, int nx, long long nc, double vol, double *partials,
+                         int nparts, double *out, hipStream_t s) {
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((totals_pass1<double>), dim3(nparts), dim3(TOT_THREADS), 0, s, (const double *)y, N, nc,
+        hipLaunchKernelGGL((totals_pass1<double>), dim3(nparts), dim3(TOT_THREADS), 0, s, (const double *)y, N, nx, nc,
                            partials, nparts);
     else
-        hipLaunchKernelGGL((totals_pass1<float>), dim3(nparts), dim3(TOT_THREADS), 0, s, (const float *)y, N, nc,
+        hipLaunchKernelGGL((totals_pass1<float>), dim3(nparts), dim3(TOT_THREADS), 0, s, (const float *)y, N, nx, nc,
                            partials, nparts);
     hipLaunchKernelGGL(totals_pass2, dim3(1), dim3(TOT_THREADS), 0, s, partials, nparts, vol, out);
     return hipGetLastError();
@@ -926,27 +939,27 @@ hipError_t launch_totals(int prec, const void *y, int N, long long nc, double vo
 // ------------------------------------------------------------------ range check
 
 template <class S>
-__global__ void range_kernel(const S *__restrict__ y, int N, long long nc, double gamma, int *flag) {
+__global__ void range_kernel(const S *__restrict__ y, int N, int nx, long long nc, double gamma, int *flag) {
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= nc) return;
-    const double rho = (double)y[(0LL * N) * nc + cell];
-    const double mx = (double)y[(1LL * N) * nc + cell];
-    const double my = (double)y[(2LL * N) * nc + cell];
-    const double mz = (double)y[(3LL * N) * nc + cell];
-    const double E = (double)y[(4LL * N) * nc + cell];
+    const double rho = (double)y[mean_index(cell, 0, N, nx)];
+    const double mx = (double)y[mean_index(cell, 1, N, nx)];
+    const double my = (double)y[mean_index(cell, 2, N, nx)];
+    const double mz = (double)y[mean_index(cell, 3, N, nx)];
+    const double E = (double)y[mean_index(cell, 4, N, nx)];
     const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) / rho);
     const bool ok = rho > 0.0 && p > 0.0 && __builtin_isfinite(p) && __builtin_isfinite(rho);
     if (!ok) atomicOr(flag, 1);
 }
 
-hipError_t launch_range_check(int prec, const void *y, int N, long long nc, double gamma, int *flag,
+hipError_t launch_range_check(int prec, const void *y, int N, int nx, long long nc, double gamma, int *flag,
                               hipStream_t s) {
     const int th = 256;
     const long long nb = (nc + th - 1) / th;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((range_kernel<double>), dim3(nb), dim3(th), 0, s, (const double *)y, N, nc, gamma, flag);
+        hipLaunchKernelGGL((range_kernel<double>), dim3(nb), dim3(th), 0, s, (const double *)y, N, nx, nc, gamma, flag);
     else
-        hipLaunchKernelGGL((range_kernel<float>), dim3(nb), dim3(th), 0, s, (const float *)y, N, nc, gamma, flag);
+        hipLaunchKernelGGL((range_kernel<float>), dim3(nb), dim3(th), 0, s, (const float *)y, N, nx, nc, gamma, flag);
     return hipGetLastError();
 }
 

@@ -165,7 +165,8 @@ class Solver:
             raise DGError(st, f"{what}: {msg.decode() if msg else ''}")
 
     def state_shape(self):
-        return (5, self.N, self.n[2], self.n[1], self.n[0])
+        """[z][y][i][l][x]: each row of cells holds its 5 N rows of weights contiguously."""
+        return (self.n[2], self.n[1], 5, self.N, self.n[0])
 
     def empty_state(self):
         import torch

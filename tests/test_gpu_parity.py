@@ -20,6 +20,7 @@ import pytest
 
 import oracle as O
 from paper_1602_09079_amd import synth
+from tests.layout import from_abi, to_abi
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +51,16 @@ def to_dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
+def state_dev(y_oracle, dtype):
+    """An oracle-layout state as a device state in the library layout."""
+    return to_dev(to_abi(y_oracle), dtype)
+
+
+def state_host(y):
+    """A device state as a float64 array in the oracle layout."""
+    return from_abi(y.cpu().double().numpy())
+
+
 def turb_case(k, n, box, seed=9079, mach=0.3):
     cfg = O.make_cfg(k, n, box=box, gamma=G)
     x = O.gauss_legendre(k + 1)[0]
@@ -70,7 +81,7 @@ def test_project_parity(dgm, k, n, box, prec):
     cfg, qp, y_or = turb_case(k, n, box)
     s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
     y = s.project(to_dev(qp, s.dtype))
-    err = O.rel_l2(y.cpu().double().numpy(), y_or)
+    err = O.rel_l2(state_host(y), y_or)
     assert np.all(err <= (1e-14 if prec == "fp64" else 1e-6)), err
 
 
@@ -79,12 +90,12 @@ def test_project_parity(dgm, k, n, box, prec):
 def test_rhs_parity(dgm, k, n, box, prec):
     cfg, qp, y_or = turb_case(k, n, box)
     s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
-    r = s.rhs(to_dev(y_or, s.dtype))
+    r = s.rhs(state_dev(y_or, s.dtype))
     torch.cuda.synchronize()
     r_or = O.rhs(cfg, y_or if prec == "fp64" else y_or.astype(np.float32).astype(np.float64))
-    err = rhs_err(r.cpu().double().numpy(), r_or)
+    err = rhs_err(state_host(r), r_or)
     print(f"rhs k={k} {prec}: L2 error per field / max field norm {err}; plain per-field rel L2 "
-          f"{O.rel_l2(r.cpu().double().numpy(), r_or)}")
+          f"{O.rel_l2(state_host(r), r_or)}")
     assert np.all(np.isfinite(err)) and np.all(err <= TOL_RHS[prec]), err
 
 
@@ -94,10 +105,10 @@ def test_step_parity_fixed_dt(dgm, k, n, box, prec):
     cfg, qp, y_or = turb_case(k, n, box)
     h = O.dt(cfg, y_or)
     s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
-    y = to_dev(y_or, s.dtype)
+    y = state_dev(y_or, s.dtype)
     t = s.step(y, nsteps=3, dt=h)
     y1, t1 = O.step(cfg, y_or, h, 3)
-    err = O.rel_l2(y.cpu().double().numpy(), y1)
+    err = O.rel_l2(state_host(y), y1)
     print(f"step k={k} {prec}: rel L2 per field {err}")
     assert t == pytest.approx(t1, rel=1e-15)
     assert np.all(err <= TOL_STATE[prec]), err
@@ -108,7 +119,7 @@ def test_dt_parity(dgm, prec):
     k, n, box = 2, (17, 5, 4), (1.0, 1.0, 0.9)
     cfg, qp, y_or = turb_case(k, n, box, mach=0.6)
     s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
-    y = to_dev(y_or, s.dtype)
+    y = state_dev(y_or, s.dtype)
     ref = O.dt(cfg, y_or if prec == "fp64" else y_or.astype(np.float32).astype(np.float64))
     assert s.dt(y) == pytest.approx(ref, rel=1e-13)
 
@@ -127,11 +138,11 @@ def test_config1_advected_wave_device_dt(dgm, prec):
     y1, t1 = O.step(cfg, y_or, 0.0, 10)
     assert t == pytest.approx(t1, rel=1e-12 if prec == "fp64" else 1e-6)
     assert t1 == pytest.approx(10 * 8.8353e-4, rel=2e-3)
-    err = O.rel_l2(y.cpu().double().numpy(), y1)
+    err = O.rel_l2(state_host(y), y1)
     print(f"config1 {prec}: {err}")
     assert np.all(err <= TOL_STATE[prec]), err
     # velocity stays (1,1,1) mode by mode (linear-advection reduction)
-    yy = y.cpu().double().numpy()
+    yy = state_host(y)
     for a in range(3):
         assert np.abs(yy[1 + a] - yy[0]).max() <= (1e-13 if prec == "fp64" else 2e-5)
 
@@ -147,7 +158,7 @@ def test_free_stream_and_conservation(dgm, prec):
     scale = 1e-12 if prec == "fp64" else 2e-4
     assert r.abs().max().item() < scale
     cfg, qp, y_or = turb_case(k, n, box)
-    y = to_dev(y_or, s.dtype)
+    y = state_dev(y_or, s.dtype)
     t0 = s.totals(y)
     s.step(y, nsteps=4, dt=0.0)
     t1 = s.totals(y)
@@ -160,7 +171,7 @@ def test_totals_parity_and_determinism(dgm, prec):
     k, n, box = 2, (30, 7, 6), (1.0, 1.0, 1.0)
     cfg, qp, y_or = turb_case(k, n, box)
     s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
-    y = to_dev(y_or, s.dtype)
+    y = state_dev(y_or, s.dtype)
     ref = O.totals(cfg, y_or if prec == "fp64" else y_or.astype(np.float32).astype(np.float64))
     np.testing.assert_allclose(s.totals(y), ref, rtol=1e-13, atol=1e-14)
     ya = y.clone()
@@ -182,7 +193,7 @@ def test_edge_grids(dgm, n):
     qp = qp * (1.0 + 0.05 * rng.standard_normal(qp.shape))
     y_or = O.project(cfg, qp)
     s = dgm.Solver(k, n, box=box, gamma=G, precision="fp64")
-    y = to_dev(y_or, s.dtype)
+    y = state_dev(y_or, s.dtype)
     r = s.rhs(y)
-    err = rhs_err(r.cpu().numpy(), O.rhs(cfg, y_or))
+    err = rhs_err(state_host(r), O.rhs(cfg, y_or))
     assert np.all(err <= 1e-12), err
