@@ -15,7 +15,11 @@ namespace dgmi {
 constexpr int NF = 5;          // conserved fields
 constexpr int BLK = 16;        // cells per MFMA column tile (one x-run)
 constexpr int BLK_INNER = 14;  // cells of a block whose result is kept; columns 0 and 15 are x-halo
-constexpr int MAX_FORCING_MODES = 256;
+constexpr int MAX_FORCING_MODES = 256;  // accepted by dg_set_forcing
+
+// The driving acceleration at the volume points is one more MFMA product over
+// KF contraction slots (the real and imaginary parts of KF/2 Fourier modes).
+inline int forcing_slots(int prec) { return (prec == DG_BF16 || prec == DG_BF16X3) ? 96 : 88; }
 
 inline int nmodes_of(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 
@@ -46,6 +50,8 @@ struct TableLayout {
 };
 
 TableLayout make_layout(int k, int prec);
+size_t forcing_table_bytes(const TableLayout &L);
+std::vector<char> build_forcing_table(const TableLayout &L, const int n[3], int nmodes, const int32_t *nvec);
 
 struct StageArgs {
     const void *yin;
@@ -64,7 +70,7 @@ struct StageArgs {
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
-    const double *fmodes; // device forcing table [nmodes][8]: n.x-phase factors and amplitudes
+    const double *fmodes; // device mode table [KF/2][9]: n_x, n_y, n_z, then Re/Im of ahat_x, ahat_y, ahat_z
     int nfmodes;
     double h[3];          // cell widths
 };
@@ -97,7 +103,8 @@ struct dg_ctx {
     int *flag = nullptr;           // range-check flag
     double *partials = nullptr;    // totals partial sums
     int nparts = 0;
-    double *fmodes = nullptr;      // forcing table
+    double *fmodes = nullptr;      // forcing mode table (zero padded to KF/2 modes)
+    size_t f6_bytes = 0;           // bytes of the forcing point table (after the operator tables)
     int nfmodes = 0;
     bool have_forcing = false;
     int grid = 0;

@@ -307,6 +307,11 @@ struct StageCfg {
     static constexpr int O5 = O4 + RT2 * NC4 * FB2;
     static constexpr int SET = O5 + RT2 * NC2 * FB2;
     static constexpr int NTAB = PREC == DG_BF16X3 ? 2 : 1;
+    // forcing product: KF slots = real and imaginary parts of KF/2 modes
+    static constexpr int KF = KPL == 8 ? 96 : 88;
+    static constexpr int KSF = KF / KSTEP;
+    static constexpr int O6 = SET * NTAB;           // forcing table after the operator tables
+    static constexpr int F6SET = RT1 * KSF * FB1;   // one (hi or lo) set of it
     static constexpr bool QFULL = (Q % 16) == 0;  // no padded volume rows
     static constexpr bool PFULL = P == 16;        // no padded face rows
 };
@@ -345,7 +350,31 @@ struct TabReader {
     __device__ typename PR::AF t3(int f, int s) const { return wide(SC::O3 + (f * SC::KS1 + s) * SC::FB1); }
     __device__ typename PR::AF2 t4(int rt, int c) const { return narrow(SC::O4 + (rt * SC::NC4 + c) * SC::FB2); }
     __device__ typename PR::AF2 t5(int rt, int c) const { return narrow(SC::O5 + (rt * SC::NC2 + c) * SC::FB2); }
+    __device__ typename PR::AF t6(int t, int st) const {
+        const int byte = SC::O6 + (t * SC::KSF + st) * SC::FB1;
+        if constexpr (PREC == DG_BF16X3)
+            return typename PR::AF{*reinterpret_cast<const bf8 *>(lds + byte + off1),
+                                   *reinterpret_cast<const bf8 *>(lds + SC::F6SET + byte + off1)};
+        else
+            return PR::lda(lds + byte + off1);
+    }
 };
+
+// the mode and part (0 = real, 1 = imaginary) fed at slot (K-step st, lane group
+// g, value j) of the forcing product; both parts of a mode sit in one lane
+template <int KPL>
+__device__ inline void forcing_slot(int st, int g, int j, int &m, int &part) {
+    if constexpr (KPL == 8) {
+        m = 16 * st + 4 * g + (j >> 1);
+        part = j & 1;
+    } else {
+        m = 4 * (st >> 1) + g;
+        part = st & 1;
+    }
+}
+
+__device__ inline void sincos_2pi(double ph, float &s, float &c) { sincospif((float)(2.0 * ph), &s, &c); }
+__device__ inline void sincos_2pi(double ph, double &s, double &c) { sincospi(2.0 * ph, &s, &c); }
 
 constexpr int STAGE_THREADS = 256;
 
@@ -391,7 +420,7 @@ __device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
 }
 
-template <int K, int PREC>
+template <int K, int PREC, bool FORCE>
 __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
     using PR = typename SC::PR;
@@ -405,7 +434,7 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
-        constexpr int bytes = SC::SET * SC::NTAB;
+        const int bytes = SC::SET * SC::NTAB + (FORCE ? SC::F6SET * SC::NTAB : 0);
         const int4 *src = reinterpret_cast<const int4 *>(a.tables);
         int4 *dst = reinterpret_cast<int4 *>(lds);
         for (int j = threadIdx.x; j < bytes / 16; j += STAGE_THREADS) dst[j] = src[j];
@@ -599,6 +628,91 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         }
     };
 
+    // driving source of Sec. 3.1: a(x_q) by the forcing product, S = (0, rho a, m.a),
+    // projected with GEMM5 (T5 = -phi w / 8)
+    auto source = [&](const B &b, int ix, int iy, int iz, Acc acc[NF][RT2]) {
+        constexpr int KSF = SC::KSF;
+        Acc af[RT1][3];
+#pragma unroll
+        for (int t = 0; t < RT1; t++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) af[t][c] = Acc{0, 0, 0, 0};
+        const double cx = (ix + 0.5) / nx, cy = (iy + 0.5) / ny, cz = (iz + 0.5) / nz;
+#pragma unroll
+        for (int st = 0; st < KSF; st++) {
+            C gv[3][KPL];
+#pragma unroll
+            for (int j = 0; j < KPL; j += (KPL == 8 ? 2 : 1)) {
+                int m, part;
+                forcing_slot<KPL>(st, g, j, m, part);
+                // G_{m,c} = ahat_{m,c} exp(2 pi i n_m . x_cell / L)
+                const double *md = a.fmodes + 9 * m;
+                double ph = md[0] * cx + md[1] * cy + md[2] * cz;
+                ph -= __builtin_floor(ph);
+                C sn, cs;
+                sincos_2pi(ph, sn, cs);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const C ar = (C)md[3 + 2 * c], ai = (C)md[4 + 2 * c];
+                    const C re = ar * cs - ai * sn, im = ar * sn + ai * cs;
+                    if constexpr (KPL == 8) {
+                        gv[c][j] = re;
+                        gv[c][j + 1] = im;
+                    } else {
+                        gv[c][0] = part ? im : re;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const auto bf = PR::mkb(gv[c]);
+#pragma unroll
+                for (int t = 0; t < RT1; t++) af[t][c] = PR::mma(af[t][c], T.t6(t, st), bf);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RT1; t++) {
+            Acc d[NF];
+#pragma unroll
+            for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS1; s++) {
+                const auto A = T.t1(t, s);
+#pragma unroll
+                for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, b.w[i][s]);
+            }
+            C Sv[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
+                const C rho = (C)d[0][r] + b.qbar[0];
+                const C ax = (C)af[t][0][r], ay = (C)af[t][1][r], az = (C)af[t][2][r];
+                const C mx = (C)d[1][r] + b.qbar[1], my = (C)d[2][r] + b.qbar[2], mz = (C)d[3][r] + b.qbar[3];
+                Sv[0][r] = valid ? rho * ax : C(0);
+                Sv[1][r] = valid ? rho * ay : C(0);
+                Sv[2][r] = valid ? rho * az : C(0);
+                Sv[3][r] = valid ? mx * ax + my * ay + mz * az : C(0);
+            }
+            if constexpr (KPL2 == 1) {
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+#pragma unroll
+                    for (int rt = 0; rt < RT2; rt++) {
+                        const auto A = T.t5(rt, t * 4 + r);
+#pragma unroll
+                        for (int i = 1; i < NF; i++) acc[i][rt] = PR::mma2(acc[i][rt], A, PR::mkb2(&Sv[i - 1][r]));
+                    }
+            } else {
+#pragma unroll
+                for (int i = 1; i < NF; i++) {
+                    const auto bf = PR::mkb2(Sv[i - 1]);
+#pragma unroll
+                    for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t5(rt, t), bf);
+                }
+            }
+        }
+    };
+
     // ---------------- work items: (x-block, y row, z chunk), x-block fastest
     const int nxcd = gridDim.x < 8 ? (int)gridDim.x : 8;
     const int xcd = blockIdx.x % nxcd;
@@ -648,6 +762,7 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 
             lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
             volume(cur, acc);
+            if constexpr (FORCE) source(cur, xc, iy, z, acc);
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
                 C tl[NF][4], Fh[NF][4];
                 {
@@ -741,13 +856,19 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 
 template <int K, int PREC>
 static hipError_t launch_stage_t(const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<K, PREC>), dim3(grid), dim3(STAGE_THREADS), lds_bytes, s, a);
+    if (a.forcing)
+        hipLaunchKernelGGL((stage_kernel<K, PREC, true>), dim3(grid), dim3(STAGE_THREADS), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<K, PREC, false>), dim3(grid), dim3(STAGE_THREADS), lds_bytes, s, a);
     return hipGetLastError();
 }
 
 template <int K, int PREC>
 static hipError_t set_attr_t(int lds_bytes) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_kernel<K, PREC>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_kernel<K, PREC, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_kernel<K, PREC, true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 
@@ -774,7 +895,7 @@ int stage_block_threads() { return STAGE_THREADS; }
 
 template <int K, int PREC>
 static hipError_t occ_t(int lds_bytes, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC>, STAGE_THREADS, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC, true>, STAGE_THREADS, lds_bytes);
 }
 
 }  // namespace dgmi

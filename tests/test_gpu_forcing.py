@@ -1,0 +1,100 @@
+"""GPU parity of the driving source term (Sec. 3.1 of arXiv 1602.09079).
+
+Each side builds its own driving amplitudes from the same seeded OU draws: the
+library with dg_ou_update, the oracle with its own OU update and solenoidal
+projection.  Tolerances as in test_gpu_parity."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_09079_amd import synth
+from tests.layout import from_abi, to_abi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+G = 5.0 / 3.0
+TOL_STATE = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 5e-3}
+TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-3, "bf16": 0.5}
+
+
+@pytest.fixture(scope="module")
+def dgm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_09079_amd import dg
+    dg.lib()
+    return dg
+
+
+def driving(dgm, a0=2.0, f=0.9, seed=1602):
+    nvec = synth.forcing_modes(1.0, 3.0)
+    th = synth.ou_stationary_start(seed, len(nvec))
+    z = synth.ou_normals(seed, len(nvec), 1)[0]
+    _, ah_lib = dgm.ou_update(nvec, th, z, f, 1.0, a0, 1.0, 3.0)
+    _, ah_orc = O.ou_update(nvec, th, z, f, 1.0, a0, 1.0, 3.0)
+    return nvec, ah_lib, O.ForcingTable(nvec, ah_orc)
+
+
+def rhs_err(r, r_ref):
+    r = np.asarray(r).reshape(5, -1)
+    r_ref = np.asarray(r_ref).reshape(5, -1)
+    return np.linalg.norm(r - r_ref, axis=1) / np.linalg.norm(r_ref, axis=1).max()
+
+
+CASES = [(1, (20, 6, 5), (1.0, 0.8, 1.2)), (2, (17, 5, 4), (1.0, 1.0, 0.9)), (3, (16, 6, 5), (1.2, 1.0, 1.0))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("k,n,box", CASES)
+def test_forced_rhs_and_step(dgm, k, n, box, prec):
+    cfg = O.make_cfg(k, n, box=box, gamma=G)
+    x = O.gauss_legendre(k + 1)[0]
+    y_or = O.project(cfg, synth.turbulence(n, x, seed=9079, mach=0.3).numpy())
+    nvec, ah_lib, frc = driving(dgm)
+    s = dgm.Solver(k, n, box=box, gamma=G, precision=prec, forcing=True)
+    s.set_forcing(nvec, ah_lib)
+    y = torch.from_numpy(to_abi(y_or)).to("cuda", s.dtype)
+    r = from_abi(s.rhs(y).cpu().double().numpy())
+    r_or = O.rhs(cfg, y_or if prec == "fp64" else y_or.astype(np.float32).astype(np.float64), frc)
+    err = rhs_err(r, r_or)
+    # the source alone must matter at this amplitude
+    assert np.linalg.norm(r_or - O.rhs(cfg, y_or)) > 1e-3 * np.linalg.norm(r_or)
+    print(f"forced rhs k={k} {prec}: {err}")
+    assert np.all(err <= TOL_RHS[prec]), err
+    h = O.dt(cfg, y_or)
+    s.step(y, nsteps=2, dt=h)
+    y1, _ = O.step(cfg, y_or, h, 2, frc=frc)
+    e2 = O.rel_l2(from_abi(y.cpu().double().numpy()), y1)
+    print(f"forced step k={k} {prec}: {e2}")
+    assert np.all(e2 <= TOL_STATE[prec]), e2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_constant_acceleration_on_gpu(dgm, prec):
+    """The n = 0 mode is a constant acceleration: R_m = -rho a, R_E = -m.a on a uniform gas."""
+    k, n = 2, (15, 4, 3)
+    x = O.gauss_legendre(k + 1)[0]
+    s = dgm.Solver(k, n, gamma=G, precision=prec, forcing=True)
+    vel = (0.2, -0.1, 0.3)
+    y = s.project(torch.from_numpy(synth.uniform_state(n, x, rho=1.5, vel=vel, p=1.0)).to("cuda", s.dtype))
+    a = np.array([0.4, -0.7, 0.25])
+    s.set_forcing(np.zeros((1, 3), dtype=np.int32), np.stack([a, np.zeros(3)], axis=1)[None])
+    r = from_abi(s.rhs(y).cpu().double().numpy())
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for c in range(3):
+        np.testing.assert_allclose(r[1 + c, 0], -1.5 * a[c], atol=tol)
+    np.testing.assert_allclose(r[4, 0], -1.5 * np.dot(vel, a), atol=tol)
+    assert np.abs(r[:, 1:]).max() < tol
+
+
+def test_set_forcing_errors(dgm):
+    s = dgm.Solver(1, 8, precision="fp32")
+    with pytest.raises(dgm.DGError):
+        s.set_forcing(np.zeros((1, 3), dtype=np.int32), np.zeros((1, 3, 2)))  # context without DG_FORCING
+    s2 = dgm.Solver(1, 8, precision="fp32", forcing=True)
+    with pytest.raises(dgm.DGError):
+        s2.set_forcing(np.ones((45, 3), dtype=np.int32), np.zeros((45, 3, 2)))  # more modes than the table holds
+    y = s2.empty_state().zero_()
+    with pytest.raises(dgm.DGError):
+        s2.rhs(y)  # DG_FORCING without a table
