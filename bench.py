@@ -10,7 +10,7 @@ supports it.
 Metric: DOF-updates/s per RK stage = 5 N(k) cells * 3 * steps / elapsed, for
 the FP32-grade tier (value) with the FP64 path and the BF16 tier reported
 beside it.  Roofline of the stage kernel from HIP events around each launch on
-the library's stream; algorithmic bytes per launch as in the design doc.
+the library's stream; algorithmic bytes per launch: stage 1 reads and writes one state, stages 2 and 3 read two and write one.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--k 3]
 """
@@ -40,6 +40,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
     p.add_argument("--quiet", action="store_true")
+    p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
     return p.parse_args()
 
 
@@ -62,8 +63,28 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+# Driving: the solenoidal OU field on 1 <= |n| <= 3 (43 modes and their
+# conjugates), one OU update from the stationary start.  a0 is fixed by the scale
+# estimate a ~ v_rms^2 / L for Mach 0.3 (v_rms = 0.387, rms |a| ~ 5 a0).
+A0 = 0.03
+OU_SEED = 1602
+
+
+def driving_table(dg):
+    from paper_1602_09079_amd import synth
+    nvec = synth.forcing_modes(1.0, 3.0)
+    th = synth.ou_stationary_start(OU_SEED, len(nvec))
+    z = synth.ou_normals(OU_SEED, len(nvec), 1)[0]
+    ts = 0.5 / (0.3 * math.sqrt(5.0 / 3.0))  # t_s = L / (2 M c)
+    _, ahat = dg.ou_update(nvec, th, z, math.exp(-0.1), 1.0, A0, 1.0, 3.0)  # dt_drive = 0.1 t_s
+    return nvec, ahat, ts
+
+
 def measure_tier(args, dg, torch, prec, qp_dev, n, k):
-    s = dg.Solver(k, n, precision=prec, cfl=0.3)
+    s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing)
+    if not args.no_forcing:
+        nvec, ahat, _ = driving_table(dg)
+        s.set_forcing(nvec, ahat)
     y = s.project(qp_dev.to(s.dtype))
     N = s.N
     cells = n ** 3
@@ -150,8 +171,8 @@ def cpu_baseline(args, k):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (see DESIGN.md for how the "
-                                   "path would shard)"}))
+        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1; the domain-decomposed multi-GPU "
+                                   "path is not built"}))
         sys.exit(2)
     import torch
 
@@ -198,9 +219,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"modal DG Euler k={k} ({N} modes, {(k + 1) ** 3} Gauss pts), {n}^3 cells, periodic "
-                               f"unit box, gamma=5/3, turbulence surrogate Mach 0.3, SSP-RK3 with device CFL dt 0.3",
+                               f"unit box, gamma=5/3, turbulence surrogate Mach 0.3"
+                               f"{'' if args.no_forcing else ' with solenoidal OU driving on 1<=|n|<=3'}"
+                               f", SSP-RK3 with device CFL dt 0.3",
                    "k": k, "cells": n ** 3, "dof": 5 * N * n ** 3, "tier": primary,
-                   "forcing": False},
+                   "forcing": not args.no_forcing},
         "roofline": roof,
         "cpu_baseline": cpu,
         "tiers": {p: {"dof_updates_per_s": v["dof_updates_per_s"], "ms_per_step": v["ms_per_step"],

@@ -156,6 +156,16 @@ def rhs(cfg, y, frc=None):
     return r
 
 
+def rhs_cells(cfg, y, cells, frc=None):
+    """R at the listed cells (flat index (z*ny + y)*nx + x); returns [len(cells)][5][N]."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    r = np.zeros((len(cells), NF, nmodes(cfg.k)))
+    lib().orc_rhs_cells(ctypes.byref(cfg), _d(y), _fptr(frc), ctypes.c_int64(len(cells)),
+                        cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _d(r))
+    return r
+
+
 def dt(cfg, y):
     return lib().orc_dt(ctypes.byref(cfg), _d(np.ascontiguousarray(y, dtype=np.float64)))
 

@@ -7,8 +7,9 @@
  * against.  Nothing in the product path may load it.  It shares no code with
  * the GPU library: its quadrature comes from Newton iteration on Legendre
  * polynomials and its basis from the Bonnet recurrence, its operator is the
- * paper's dense per-cell / per-face quadrature sums, with every face flux
- * computed once and handed to both cells.
+ * paper's dense per-cell / per-face quadrature sums.  Each cell evaluates the
+ * numerical flux of its six faces from the two traces, in the +axis
+ * orientation, so both cells of a face use the same value.
  *
  * Readings of the paper used here (where it is silent or garbled):
  *  - basis normalised so that (1/8) int phi_l phi_m dxi = delta_lm, i.e. the
@@ -354,11 +355,13 @@ static void eval_at(const double *y, size_t nc, size_t K, int N, const double *p
     }
 }
 
-void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double *r)
+/* R of one cell K: out[i][l].  The numerical flux of a face is a function of
+ * the two traces only, evaluated in the +axis orientation (left = the cell on
+ * the -axis side), so the two cells sharing a face receive the same value. */
+static void cell_rhs(const orc_cfg *cfg, const tables *t, const double *y, size_t K, const orc_forcing *frc,
+                     double out[NF][NMAX])
 {
-    tables t;
-    tables_init(&t, cfg->k);
-    const int N = t.N, Q = t.Q, P = t.P, n = t.n;
+    const int N = t->N, Q = t->Q, P = t->P, n = t->n;
     const size_t nc = ncells_of(cfg);
     const double g = cfg->gamma;
     double dx[3], s[3];
@@ -366,69 +369,85 @@ void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double
         dx[a] = cfg->box[a] / cfg->n[a];
         s[a] = 1.0 / (4.0 * dx[a]); /* (dx^2/4) / |K| of eqs. dg:eqn:volume_int and dg:eqn:surface_int */
     }
-    /* one numerical flux per unique face: face (axis, K) joins K and its +axis neighbour */
-    double *fh = malloc(sizeof(double) * 3 * nc * P * NF);
-#pragma omp parallel for schedule(static)
-    for (size_t K = 0; K < nc; K++) {
-        long ix = K % cfg->n[0], iy = (K / cfg->n[0]) % cfg->n[1], iz = K / ((size_t)cfg->n[0] * cfg->n[1]);
-        for (int axis = 0; axis < 3; axis++) {
-            size_t Kp = cell_index(cfg, ix + (axis == 0), iy + (axis == 1), iz + (axis == 2));
-            for (int p = 0; p < P; p++) {
-                double qL[5], qR[5];
-                eval_at(y, nc, K, N, t.phi_f + ((axis * 2 + 1) * P + p) * N, qL);
-                eval_at(y, nc, Kp, N, t.phi_f + ((axis * 2 + 0) * P + p) * N, qR);
-                orc_hllc(qL, qR, axis, g, fh + ((axis * nc + K) * P + p) * NF);
-            }
+    long ix = K % cfg->n[0], iy = (K / cfg->n[0]) % cfg->n[1], iz = K / ((size_t)cfg->n[0] * cfg->n[1]);
+    double vol[NF][NMAX], surf[NF][NMAX], src[NF][NMAX];
+    memset(vol, 0, sizeof vol);
+    memset(surf, 0, sizeof surf);
+    memset(src, 0, sizeof src);
+    /* volume integral, eq. dg:eqn:volume_int */
+    for (int q = 0; q < Q; q++) {
+        double qv[5];
+        eval_at(y, nc, K, N, t->phi_v + q * N, qv);
+        for (int al = 0; al < 3; al++) {
+            double F[5];
+            orc_euler_flux(qv, al, g, F);
+            for (int i = 0; i < NF; i++)
+                for (int l = 0; l < N; l++) vol[i][l] += s[al] * F[i] * t->dphi_v[(al * Q + q) * N + l] * t->w_v[q];
+        }
+        if (frc) {
+            /* driving source, Sec. 3.1: (0, rho a, m.a) projected with the volume rule */
+            int a = q % n, b = (q / n) % n, c = q / (n * n);
+            double xq[3] = {(ix + 0.5 * (1.0 + t->xg[a])) * dx[0], (iy + 0.5 * (1.0 + t->xg[b])) * dx[1],
+                            (iz + 0.5 * (1.0 + t->xg[c])) * dx[2]};
+            double acc[3];
+            orc_accel(frc, cfg->box, xq, acc);
+            double S[5] = {0.0, qv[0] * acc[0], qv[0] * acc[1], qv[0] * acc[2],
+                           qv[1] * acc[0] + qv[2] * acc[1] + qv[3] * acc[2]};
+            for (int i = 0; i < NF; i++)
+                for (int l = 0; l < N; l++) src[i][l] += S[i] * t->phi_v[q * N + l] * t->w_v[q] / 8.0;
         }
     }
+    /* surface integral, eq. dg:eqn:surface_int, outward normal */
+    for (int axis = 0; axis < 3; axis++) {
+        size_t Km = cell_index(cfg, ix - (axis == 0), iy - (axis == 1), iz - (axis == 2));
+        size_t Kp = cell_index(cfg, ix + (axis == 0), iy + (axis == 1), iz + (axis == 2));
+        for (int p = 0; p < P; p++) {
+            const double *php = t->phi_f + ((axis * 2 + 1) * P + p) * N;
+            const double *phm = t->phi_f + ((axis * 2 + 0) * P + p) * N;
+            double qa[5], qb[5], Fp[5], Fm[5];
+            eval_at(y, nc, K, N, php, qa);  /* my trace on the + face */
+            eval_at(y, nc, Kp, N, phm, qb); /* right neighbour's trace on its - face */
+            orc_hllc(qa, qb, axis, g, Fp);
+            eval_at(y, nc, Km, N, php, qa); /* left neighbour's trace on its + face */
+            eval_at(y, nc, K, N, phm, qb);  /* my trace on the - face */
+            orc_hllc(qa, qb, axis, g, Fm);
+            for (int i = 0; i < NF; i++)
+                for (int l = 0; l < N; l++) surf[i][l] += s[axis] * (Fp[i] * php[l] - Fm[i] * phm[l]) * t->w_f[p];
+        }
+    }
+    for (int i = 0; i < NF; i++)
+        for (int l = 0; l < N; l++) out[i][l] = surf[i][l] - vol[i][l] - src[i][l];
+}
+
+void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double *r)
+{
+    tables t;
+    tables_init(&t, cfg->k);
+    const size_t nc = ncells_of(cfg);
+    const int N = t.N;
 #pragma omp parallel for schedule(static)
     for (size_t K = 0; K < nc; K++) {
-        long ix = K % cfg->n[0], iy = (K / cfg->n[0]) % cfg->n[1], iz = K / ((size_t)cfg->n[0] * cfg->n[1]);
-        double vol[NF][NMAX], surf[NF][NMAX], src[NF][NMAX];
-        memset(vol, 0, sizeof vol);
-        memset(surf, 0, sizeof surf);
-        memset(src, 0, sizeof src);
-        /* volume integral, eq. dg:eqn:volume_int */
-        for (int q = 0; q < Q; q++) {
-            double qv[5];
-            eval_at(y, nc, K, N, t.phi_v + q * N, qv);
-            for (int al = 0; al < 3; al++) {
-                double F[5];
-                orc_euler_flux(qv, al, g, F);
-                for (int i = 0; i < NF; i++)
-                    for (int l = 0; l < N; l++)
-                        vol[i][l] += s[al] * F[i] * t.dphi_v[(al * Q + q) * N + l] * t.w_v[q];
-            }
-            if (frc) {
-                /* driving source, Sec. 3.1: (0, rho a, m.a) projected with the volume rule */
-                int a = q % n, b = (q / n) % n, c = q / (n * n);
-                double xq[3] = {(ix + 0.5 * (1.0 + t.xg[a])) * dx[0], (iy + 0.5 * (1.0 + t.xg[b])) * dx[1],
-                                (iz + 0.5 * (1.0 + t.xg[c])) * dx[2]};
-                double acc[3];
-                orc_accel(frc, cfg->box, xq, acc);
-                double S[5] = {0.0, qv[0] * acc[0], qv[0] * acc[1], qv[0] * acc[2],
-                               qv[1] * acc[0] + qv[2] * acc[1] + qv[3] * acc[2]};
-                for (int i = 0; i < NF; i++)
-                    for (int l = 0; l < N; l++) src[i][l] += S[i] * t.phi_v[q * N + l] * t.w_v[q] / 8.0;
-            }
-        }
-        /* surface integral, eq. dg:eqn:surface_int, outward normal */
-        for (int axis = 0; axis < 3; axis++) {
-            size_t Km = cell_index(cfg, ix - (axis == 0), iy - (axis == 1), iz - (axis == 2));
-            for (int p = 0; p < P; p++) {
-                const double *Fp = fh + ((axis * nc + K) * P + p) * NF;  /* my +axis face */
-                const double *Fm = fh + ((axis * nc + Km) * P + p) * NF; /* my -axis face */
-                const double *php = t.phi_f + ((axis * 2 + 1) * P + p) * N;
-                const double *phm = t.phi_f + ((axis * 2 + 0) * P + p) * N;
-                for (int i = 0; i < NF; i++)
-                    for (int l = 0; l < N; l++)
-                        surf[i][l] += s[axis] * (Fp[i] * php[l] - Fm[i] * phm[l]) * t.w_f[p];
-            }
-        }
+        double o[NF][NMAX];
+        cell_rhs(cfg, &t, y, K, frc, o);
         for (int i = 0; i < NF; i++)
-            for (int l = 0; l < N; l++) r[((size_t)i * N + l) * nc + K] = surf[i][l] - vol[i][l] - src[i][l];
+            for (int l = 0; l < N; l++) r[((size_t)i * N + l) * nc + K] = o[i][l];
     }
-    free(fh);
+    tables_free(&t);
+}
+
+void orc_rhs_cells(const orc_cfg *cfg, const double *y, const orc_forcing *frc, int64_t ncells_list,
+                   const int64_t *cells, double *r)
+{
+    tables t;
+    tables_init(&t, cfg->k);
+    const int N = t.N;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ncells_list; j++) {
+        double o[NF][NMAX];
+        cell_rhs(cfg, &t, y, (size_t)cells[j], frc, o);
+        for (int i = 0; i < NF; i++)
+            for (int l = 0; l < N; l++) r[((size_t)j * NF + i) * N + l] = o[i][l];
+    }
     tables_free(&t);
 }
 

@@ -8,7 +8,7 @@
  * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
  * no code, header, table or constant with the GPU library.
  *
- * Every array is FP64 on the host.  State layout (also the GPU layout):
+ * Every array is FP64 on the host.  State layout:
  *   y[i][l][z][y][x], x fastest; i = field (rho, m_x, m_y, m_z, E);
  *   l = mode index in the graded order listed by orc_mode_list().
  *
@@ -61,6 +61,9 @@ void orc_euler_flux(const double q[5], int axis, double gamma, double F[5]);
 void orc_hllc(const double qL[5], const double qR[5], int axis, double gamma, double F[5]);
 /* r = R(y) with dy/dt + R(y) = 0 (eq. dg:eqn:time); frc may be NULL */
 void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double *r);
+/* R at listed cells only (cell = (z*ny + y)*nx + x); r: [ncells_list][5][N] */
+void orc_rhs_cells(const orc_cfg *cfg, const double *y, const orc_forcing *frc, int64_t ncells_list,
+                   const int64_t *cells, double *r);
 
 /* ---- Sec. 2.4: time step from cell means, global minimum ---- */
 double orc_dt(const orc_cfg *cfg, const double *y);

@@ -1,0 +1,95 @@
+"""Parity at the benchmark workload (k = 3, 256^3 cells, turbulence surrogate at
+Mach 0.3 with the solenoidal OU driving), on sampled cells.
+
+The oracle cannot step 256^3 on the host, but R is local: the oracle projects
+the generator's point values of each sampled cell and of its six face
+neighbours (projection is cell-local) and evaluates R at the samples.  The GPU
+runs dg_project and dg_rhs on the whole grid, in the launch configuration the
+benchmark times.  Samples include x-block seams, periodic boundaries and random
+cells.  Properties checked at full size: finiteness, mass conservation over a
+step."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_09079_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+G = 5.0 / 3.0
+K, NC = 3, 256
+TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-3, "bf16": 0.5}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_09079_amd import dg
+    dg.lib()
+    x = dg.gauss_nodes(K + 1)
+    qp = synth.turbulence(NC, x, seed=9079, mach=0.3, device="cuda", dtype=torch.float64)
+    nvec = synth.forcing_modes(1.0, 3.0)
+    th = synth.ou_stationary_start(1602, len(nvec))
+    z = synth.ou_normals(1602, len(nvec), 1)[0]
+    _, ah_lib = dg.ou_update(nvec, th, z, math.exp(-0.1), 1.0, 0.03, 1.0, 3.0)
+    _, ah_orc = O.ou_update(nvec, th, z, math.exp(-0.1), 1.0, 0.03, 1.0, 3.0)
+    rng = np.random.default_rng(256)
+    special = [(0, 0, 0), (NC - 1, NC - 1, NC - 1), (13, 5, 7), (14, 5, 7), (27, 200, 31), (28, 200, 31),
+               (NC - 1, 0, 17), (251, 128, 0), (252, 128, NC - 1), (0, NC - 1, 128)]
+    rand = [tuple(int(v) for v in rng.integers(0, NC, 3)) for _ in range(118)]
+    samples = special + rand
+    # oracle input: its own projection of the generator's point values of every needed cell
+    need = set()
+    for (ix, iy, iz) in samples:
+        for d in [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+            need.add(((ix + d[0]) % NC, (iy + d[1]) % NC, (iz + d[2]) % NC))
+    need = sorted(need)
+    xs = torch.tensor([c[0] for c in need], device="cuda")
+    ys = torch.tensor([c[1] for c in need], device="cuda")
+    zs = torch.tensor([c[2] for c in need], device="cuda")
+    pts = qp[:, :, :, :, zs, ys, xs].cpu().numpy()  # [5][n][n][n][M]
+    cfg1 = O.make_cfg(K, (len(need), 1, 1), box=(len(need) / NC, 1.0 / NC, 1.0 / NC), gamma=G)
+    ysub = O.project(cfg1, pts.reshape(5, K + 1, K + 1, K + 1, 1, 1, len(need)))  # cell-local
+    N = O.nmodes(K)
+    y_or = np.zeros((5, N, NC, NC, NC))  # untouched pages stay unallocated
+    for j, (ix, iy, iz) in enumerate(need):
+        y_or[:, :, iz, iy, ix] = ysub[:, :, 0, 0, j]
+    cells = np.array([(iz * NC + iy) * NC + ix for (ix, iy, iz) in samples], dtype=np.int64)
+    return dict(dg=dg, qp=qp, nvec=nvec, ah_lib=ah_lib, frc=O.ForcingTable(nvec, ah_orc), samples=samples,
+                need=need, y_or=y_or, cells=cells)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16"])
+def test_fullsize_rhs_sampled(setup, prec):
+    dg = setup["dg"]
+    s = dg.Solver(K, NC, gamma=G, precision=prec, forcing=True)
+    s.set_forcing(setup["nvec"], setup["ah_lib"])
+    y = s.project(setup["qp"].to(s.dtype))
+    r = s.rhs(y)
+    cfg = O.make_cfg(K, NC, gamma=G)
+    y_in = setup["y_or"]
+    if prec != "fp64":
+        y_in = y_in.astype(np.float32).astype(np.float64)
+    r_or = O.rhs_cells(cfg, y_in, setup["cells"], setup["frc"])  # [S][5][N]
+    xs = torch.tensor([c[0] for c in setup["samples"]], device="cuda")
+    ys = torch.tensor([c[1] for c in setup["samples"]], device="cuda")
+    zs = torch.tensor([c[2] for c in setup["samples"]], device="cuda")
+    r_gpu = r[zs, ys, :, :, xs].double().cpu().numpy()  # [S][5][N]
+    d = (r_gpu - r_or).transpose(1, 0, 2).reshape(5, -1)
+    ref = r_or.transpose(1, 0, 2).reshape(5, -1)
+    err = np.linalg.norm(d, axis=1) / np.linalg.norm(ref, axis=1).max()
+    print(f"full-size rhs {prec}: {err}")
+    assert np.all(np.isfinite(err)) and np.all(err <= TOL_RHS[prec]), err
+    # the projection at the sampled cells matches the oracle's
+    yg = y[zs, ys, :, :, xs].double().cpu().numpy()
+    yo = np.stack([setup["y_or"][:, :, c[2], c[1], c[0]] for c in setup["samples"]])
+    assert np.abs(yg - yo).max() <= (1e-13 if prec == "fp64" else 2e-6) * np.abs(yo).max()
+    # one full step at this size stays finite and conserves mass
+    m0 = s.totals(y)[0]
+    s.step(y, nsteps=1, dt=0.0)
+    assert bool(torch.isfinite(y).all().item())
+    assert s.totals(y)[0] == pytest.approx(m0, rel=1e-13 if prec == "fp64" else 1e-6)
