@@ -373,7 +373,12 @@ __device__ inline void forcing_slot(int st, int g, int j, int &m, int &part) {
     }
 }
 
-__device__ inline void sincos_2pi(double ph, float &s, float &c) { sincospif((float)(2.0 * ph), &s, &c); }
+// sin and cos of 2 pi ph for ph in [0, 1): the FP32 tiers use the hardware
+// v_sin/v_cos, whose argument is in revolutions; FP64 uses sincospi
+__device__ inline void sincos_2pi(double ph, float &s, float &c) {
+    s = __builtin_amdgcn_sinf((float)ph);
+    c = __builtin_amdgcn_cosf((float)ph);
+}
 __device__ inline void sincos_2pi(double ph, double &s, double &c) { sincospi(2.0 * ph, &s, &c); }
 
 constexpr int STAGE_THREADS = 256;
@@ -638,36 +643,60 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 #pragma unroll
             for (int c = 0; c < 3; c++) af[t][c] = Acc{0, 0, 0, 0};
         const double cx = (ix + 0.5) / nx, cy = (iy + 0.5) / ny, cz = (iz + 0.5) / nz;
+        // G_{m,c} = ahat_{m,c} exp(2 pi i n_m . x_cell / L) for mode m, both parts
+        auto coef = [&](int m, C re[3], C im[3]) {
+            const double *md = a.fmodes + 9 * m;
+            double ph = md[0] * cx + md[1] * cy + md[2] * cz;
+            ph -= __builtin_floor(ph);
+            C sn, cs;
+            sincos_2pi(ph, sn, cs);
 #pragma unroll
-        for (int st = 0; st < KSF; st++) {
-            C gv[3][KPL];
-#pragma unroll
-            for (int j = 0; j < KPL; j += (KPL == 8 ? 2 : 1)) {
-                int m, part;
-                forcing_slot<KPL>(st, g, j, m, part);
-                // G_{m,c} = ahat_{m,c} exp(2 pi i n_m . x_cell / L)
-                const double *md = a.fmodes + 9 * m;
-                double ph = md[0] * cx + md[1] * cy + md[2] * cz;
-                ph -= __builtin_floor(ph);
-                C sn, cs;
-                sincos_2pi(ph, sn, cs);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const C ar = (C)md[3 + 2 * c], ai = (C)md[4 + 2 * c];
-                    const C re = ar * cs - ai * sn, im = ar * sn + ai * cs;
-                    if constexpr (KPL == 8) {
-                        gv[c][j] = re;
-                        gv[c][j + 1] = im;
-                    } else {
-                        gv[c][0] = part ? im : re;
-                    }
-                }
+            for (int c = 0; c < 3; c++) {
+                const C ar = (C)md[3 + 2 * c], ai = (C)md[4 + 2 * c];
+                re[c] = ar * cs - ai * sn;
+                im[c] = ar * sn + ai * cs;
             }
+        };
+        auto gemm_f = [&](int st, C gv[3][KPL]) {
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 const auto bf = PR::mkb(gv[c]);
 #pragma unroll
                 for (int t = 0; t < RT1; t++) af[t][c] = PR::mma(af[t][c], T.t6(t, st), bf);
+            }
+        };
+        if constexpr (KPL == 8) {
+#pragma unroll
+            for (int st = 0; st < KSF; st++) {
+                C gv[3][KPL];
+#pragma unroll
+                for (int j = 0; j < KPL; j += 2) {
+                    int m, part;
+                    forcing_slot<KPL>(st, g, j, m, part);
+                    C re[3], im[3];
+                    coef(m, re, im);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        gv[c][j] = re[c];
+                        gv[c][j + 1] = im[c];
+                    }
+                }
+                gemm_f(st, gv);
+            }
+        } else {
+            // K-steps 2u and 2u+1 carry the real and imaginary parts of one mode
+#pragma unroll
+            for (int st = 0; st < KSF; st += 2) {
+                int m, part;
+                forcing_slot<KPL>(st, g, 0, m, part);
+                C re[3], im[3], gv[3][KPL];
+                coef(m, re, im);
+#pragma unroll
+                for (int c = 0; c < 3; c++) gv[c][0] = re[c];
+                gemm_f(st, gv);
+#pragma unroll
+                for (int c = 0; c < 3; c++) gv[c][0] = im[c];
+                gemm_f(st + 1, gv);
             }
         }
 #pragma unroll
@@ -752,17 +781,17 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         }
         for (int z = z0; z < z1; z++) {
             T.refresh();
-            B nxt;
-            load(cidx(iy, z + 1), nxt);
             Acc acc[NF][RT2];
 #pragma unroll
             for (int i = 0; i < NF; i++)
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
-
             lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
-            volume(cur, acc);
+            // the driving source runs before the look-ahead load is in flight (fewer live registers)
             if constexpr (FORCE) source(cur, xc, iy, z, acc);
+            B nxt;
+            load(cidx(iy, z + 1), nxt);
+            volume(cur, acc);
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
                 C tl[NF][4], Fh[NF][4];
                 {

@@ -21,7 +21,12 @@ torch = pytest.importorskip("torch")
 
 G = 5.0 / 3.0
 K, NC = 3, 256
-TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-3, "bf16": 0.5}
+# R is a difference of volume and surface terms that grow like 1/h while R does
+# not, so its rounding error relative to R grows with the resolution: the bars
+# of the small-grid parity tests (16-20 cells per axis) are scaled by 256/16.
+# The pass/fail bar of the method is on the state after a stage (TOL_STATE).
+TOL_RHS = {"fp64": 1.6e-11, "fp32": 3.2e-4, "bf16x3": 3.2e-2, "bf16": 0.5}
+TOL_STATE = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 5e-3}
 
 
 @pytest.fixture(scope="module")
@@ -84,6 +89,17 @@ def test_fullsize_rhs_sampled(setup, prec):
     err = np.linalg.norm(d, axis=1) / np.linalg.norm(ref, axis=1).max()
     print(f"full-size rhs {prec}: {err}")
     assert np.all(np.isfinite(err)) and np.all(err <= TOL_RHS[prec]), err
+    # one SSP stage y1 = y - dt R(y) with the oracle's state at the samples
+    h = 1e-5
+    y1 = torch.empty_like(y)
+    s.stage(y, y, y1, 0.0, 1.0, h)
+    y1g = y1[zs, ys, :, :, xs].double().cpu().numpy()
+    y_s = np.stack([y_in[:, :, c[2], c[1], c[0]] for c in setup["samples"]])
+    y1o = y_s - h * r_or
+    e1 = (np.linalg.norm((y1g - y1o).transpose(1, 0, 2).reshape(5, -1), axis=1) /
+          np.linalg.norm(y1o.transpose(1, 0, 2).reshape(5, -1), axis=1))
+    print(f"full-size stage {prec}: {e1}")
+    assert np.all(e1 <= TOL_STATE[prec]), e1
     # the projection at the sampled cells matches the oracle's
     yg = y[zs, ys, :, :, xs].double().cpu().numpy()
     yo = np.stack([setup["y_or"][:, :, c[2], c[1], c[0]] for c in setup["samples"]])
