@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
+    p.add_argument("--copy-calibration", type=float, default=0.0,
+                   help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
     return p.parse_args()
 
 
@@ -189,6 +191,16 @@ def main():
         results[prec] = measure_tier(args, dg, torch, prec, qp, n, k)
     del qp
     torch.cuda.empty_cache()
+    if args.copy_calibration > 0:
+        nel = int(args.copy_calibration * (1 << 30)) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, f"[bench] copy calibration: 3 copies of {nel * 4} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
     fp32_grade = [p for p in ("bf16x3", "fp32") if p in results]
     primary = args.primary if args.primary != "auto" else max(fp32_grade or list(results),
                                                                key=lambda p: results[p]["dof_updates_per_s"])
