@@ -262,3 +262,41 @@ def rel_l2(a, b):
     b = np.asarray(b, dtype=np.float64).reshape(NF, -1)
     nb = np.linalg.norm(b, axis=1)
     return np.linalg.norm(a - b, axis=1) / np.where(nb > 0, nb, 1.0)
+
+
+class Closure(ctypes.Structure):
+    _fields_ = [("nin", ctypes.c_int32), ("nh1", ctypes.c_int32), ("nh2", ctypes.c_int32), ("nout", ctypes.c_int32),
+                ("params", c_double_p), ("feat_mean", c_double_p), ("feat_std", c_double_p),
+                ("out_scale", c_double_p), ("out_bound", c_double_p)]
+
+
+class ClosureParams:
+    """Keeps the arrays alive behind an orc_closure struct."""
+
+    def __init__(self, params, feat_mean, feat_std, out_scale, out_bound, shape=MLP_SHAPE):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        self.arrays = [f(params), f(feat_mean), f(feat_std), f(out_scale), f(out_bound)]
+        self.s = Closure(*shape, *[_d(a) for a in self.arrays])
+
+    def ptr(self):
+        return ctypes.byref(self.s)
+
+
+def closure_features(cfg, y):
+    """[ncells][7][5][N] features (self, -x, +x, -y, +y, -z, +z)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    N = nmodes(cfg.k)
+    nc = cfg.n[0] * cfg.n[1] * cfg.n[2]
+    out = np.zeros((nc, 7, NF, N))
+    lib().orc_closure_features(ctypes.byref(cfg), _d(y), _d(out))
+    return out
+
+
+def closure_correction(cfg, y, clo):
+    """Returns (corr in state layout, number of cells that fell back)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    corr = np.zeros_like(y)
+    L = lib()
+    L.orc_closure_correction.restype = ctypes.c_int64
+    nfb = L.orc_closure_correction(ctypes.byref(cfg), _d(y), clo.ptr(), _d(corr))
+    return corr, int(nfb)

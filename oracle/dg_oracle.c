@@ -661,3 +661,73 @@ void orc_adam(int nparams, double *params, const double *grad, double *m, double
         params[j] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned closure (not in the paper): features and correction          */
+/* ------------------------------------------------------------------ */
+
+/* the seven cells whose weights form a cell's features: itself, then its
+ * -x, +x, -y, +y, -z, +z neighbours (periodic) */
+static const int nb_off[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+
+void orc_closure_features(const orc_cfg *cfg, const double *y, double *feat)
+{
+    int N = orc_nmodes(cfg->k);
+    size_t nc = ncells_of(cfg);
+    long nx = cfg->n[0], ny = cfg->n[1];
+    int nin = 7 * NF * N;
+#pragma omp parallel for schedule(static)
+    for (size_t K = 0; K < nc; K++) {
+        long ix = K % nx, iy = (K / nx) % ny, iz = K / ((size_t)nx * ny);
+        for (int j = 0; j < 7; j++) {
+            size_t Kn = cell_index(cfg, ix + nb_off[j][0], iy + nb_off[j][1], iz + nb_off[j][2]);
+            for (int i = 0; i < NF; i++)
+                for (int l = 0; l < N; l++)
+                    feat[K * nin + (size_t)(j * NF + i) * N + l] = y[((size_t)i * N + l) * nc + Kn];
+        }
+    }
+}
+
+int64_t orc_closure_correction(const orc_cfg *cfg, const double *y, const orc_closure *clo, double *corr)
+{
+    int N = orc_nmodes(cfg->k);
+    size_t nc = ncells_of(cfg);
+    int nin = clo->nin, nh1 = clo->nh1, nh2 = clo->nh2, nout = clo->nout;
+    double *feat = malloc(sizeof(double) * nc * nin);
+    double *h1 = malloc(sizeof(double) * nc * nh1), *h2 = malloc(sizeof(double) * nc * nh2);
+    double *o = malloc(sizeof(double) * nc * nout);
+    orc_closure_features(cfg, y, feat);
+    /* standardised features, then the network */
+    for (size_t K = 0; K < nc; K++)
+        for (int f = 0; f < nin; f++)
+            feat[K * nin + f] = (feat[K * nin + f] - clo->feat_mean[f]) / clo->feat_std[f];
+    orc_mlp_forward(nin, nh1, nh2, nout, clo->params, (int)nc, feat, h1, h2, o);
+    /* correction = scale * output, or nothing for a cell with any output
+     * non-finite or beyond its bound (the plain operator is kept there) */
+    int64_t fallbacks = 0;
+    for (size_t K = 0; K < nc; K++) {
+        int bad = 0;
+        for (int j = 0; j < nout; j++) {
+            double v = o[K * nout + j];
+            if (!isfinite(v) || fabs(v) > clo->out_bound[j]) bad = 1;
+        }
+        fallbacks += bad;
+        for (int i = 0; i < NF; i++)
+            for (int l = 0; l < N; l++) {
+                int j = i * N + l;
+                corr[((size_t)i * N + l) * nc + K] = bad ? 0.0 : clo->out_scale[j] * o[K * nout + j];
+            }
+    }
+    /* the cell-mean rows are shifted to zero sum per field, so the closure
+     * leaves the conserved totals unchanged */
+    for (int i = 0; i < NF; i++) {
+        double *row = corr + (size_t)i * N * nc;
+        double s = pairwise_sum(row, nc) / (double)nc;
+        for (size_t K = 0; K < nc; K++) row[K] -= s;
+    }
+    free(feat);
+    free(h1);
+    free(h2);
+    free(o);
+    return fallbacks;
+}

@@ -17,6 +17,8 @@
  *   forcing table (OU + Helmholtz projection)               -- pinned (statistics, solenoidality)
  *   restriction                                             -- pinned (exactness, conservation)
  *   MLP forward/backward/Adam                               -- pinned (finite differences, textbook Adam)
+ *   closure features / correction                           -- pinned (neighbour order, closed-form outputs,
+ *                                                              fallback, zero-sum mean rows)
  */
 #ifndef DG_ORACLE_H
 #define DG_ORACLE_H
@@ -100,6 +102,25 @@ double orc_mlp_loss_grad(int nin, int nh1, int nh2, int nout, const double *para
                          int batch, const double *x, const double *target, double *grad);
 void orc_adam(int nparams, double *params, const double *grad, double *m, double *v,
               int step, double lr, double beta1, double beta2, double eps);
+
+/* Per-cell closure.  A cell's features are the weights of itself and of its
+ * -x, +x, -y, +y, -z, +z neighbours: feat[cell][j][i][l], 7*5*N values (140 at
+ * k=1).  The network sees (feat - feat_mean)/feat_std; its output o (nout =
+ * 5N, ordered [i][l]) gives the correction c = out_scale * o, added to the
+ * time derivative: dy/dt = -R(y) + c.  A cell with any o_j non-finite or
+ * |o_j| > out_bound_j gets c = 0 (the plain operator).  Afterwards the l = 0
+ * rows of c are shifted to zero sum over cells per field (totals conserved). */
+typedef struct {
+    int32_t nin, nh1, nh2, nout;
+    const double *params;      /* orc_mlp_* layout */
+    const double *feat_mean;   /* [nin] */
+    const double *feat_std;    /* [nin] */
+    const double *out_scale;   /* [nout] */
+    const double *out_bound;   /* [nout] */
+} orc_closure;
+void orc_closure_features(const orc_cfg *cfg, const double *y, double *feat);   /* [ncells][7*5*N] */
+/* corr: state layout; returns the number of cells that fell back */
+int64_t orc_closure_correction(const orc_cfg *cfg, const double *y, const orc_closure *clo, double *corr);
 
 #ifdef __cplusplus
 }

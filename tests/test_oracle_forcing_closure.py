@@ -172,3 +172,91 @@ def test_adam_first_steps():
     O.adam(p, g, m, v, 1, lr=0.01)
     # first step: m_hat = g, v_hat = g^2, so the move is lr * g / (|g| + eps)
     np.testing.assert_allclose(p, [1.0 - 0.01 * 0.3 / (0.3 + 1e-8), -2.0 + 0.01 * 4.0 / (4.0 + 1e-8), 0.5], rtol=1e-14)
+
+
+# ---------------------------------------------------------------- closure features and correction
+
+def _clo_cfg():
+    return O.make_cfg(1, (5, 4, 3))
+
+
+def test_closure_features_neighbour_order():
+    """Feature j of a cell is the weight block of the neighbour at offset j
+    (self, -x, +x, -y, +y, -z, +z) with periodic wrap: checked against numpy
+    rolls of the state, an independent indexing."""
+    cfg = _clo_cfg()
+    y = np.random.default_rng(1).standard_normal(O.state_shape(cfg))
+    f = O.closure_features(cfg, y)
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    for j, (dx, dy, dz) in enumerate(offs):
+        # value at cell (x, y, z) is y at (x+dx, y+dy, z+dz): roll by the negative offset
+        nb = np.roll(y, shift=(-dz, -dy, -dx), axis=(2, 3, 4))
+        want = nb.reshape(5, 4, -1).transpose(2, 0, 1)
+        np.testing.assert_array_equal(f[:, j], want)
+
+
+def _affine_closure(b3, bound, scale, shape=(140, 16, 16, 20)):
+    """A network whose last layer is zero: its output is b3 for every input."""
+    nin, nh1, nh2, nout = shape
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(O.mlp_nparams(*shape)) * 0.1
+    off = nh1 * nin + nh1 + nh2 * nh1 + nh2
+    p[off:off + nout * nh2] = 0.0
+    p[off + nout * nh2:] = b3
+    return O.ClosureParams(p, np.zeros(nin), np.ones(nin), scale, bound, shape=shape)
+
+
+def test_closure_constant_output_closed_form():
+    """Zero last layer: o = b3 everywhere, so c = scale * b3 for l > 0 and the
+    zero-sum shift removes the (constant) l = 0 rows entirely."""
+    cfg = _clo_cfg()
+    y = np.random.default_rng(3).standard_normal(O.state_shape(cfg))
+    b3 = np.linspace(-0.9, 0.9, 20)
+    scale = np.linspace(0.5, 2.5, 20)
+    clo = _affine_closure(b3, np.ones(20), scale, shape=(140, 16, 16, 20))
+    corr, nfb = O.closure_correction(cfg, y, clo)
+    assert nfb == 0
+    want = (scale * b3).reshape(5, 4)
+    for i in range(5):
+        np.testing.assert_allclose(corr[i, 0], 0.0, atol=1e-15)
+        for l in range(1, 4):
+            np.testing.assert_allclose(corr[i, l], want[i, l], rtol=1e-14)
+
+
+def test_closure_fallback_on_bound_and_nan():
+    cfg = _clo_cfg()
+    y = np.random.default_rng(4).standard_normal(O.state_shape(cfg))
+    b3 = np.full(20, 0.5)
+    b3[7] = 1.5  # one output beyond its bound of 1: every cell falls back
+    corr, nfb = O.closure_correction(cfg, y, _affine_closure(b3, np.ones(20), np.ones(20)))
+    assert nfb == 60 and np.all(corr == 0.0)
+    b3[7] = np.nan
+    corr, nfb = O.closure_correction(cfg, y, _affine_closure(b3, np.ones(20), np.ones(20)))
+    assert nfb == 60 and np.all(corr == 0.0)
+
+
+def test_closure_network_and_zero_sum_means():
+    """A random network: the correction equals scale * MLP(standardised
+    features) on cells within bounds (composition of the pinned pieces), the
+    l = 0 rows sum to zero per field, and cells beyond a bound fall back."""
+    cfg = _clo_cfg()
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(O.state_shape(cfg))
+    shape = (140, 32, 24, 20)
+    p = rng.standard_normal(O.mlp_nparams(*shape)) * 0.2
+    mean = rng.standard_normal(140) * 0.1
+    std = rng.uniform(0.5, 2.0, 140)
+    scale = rng.uniform(0.5, 2.0, 20)
+    feats = (O.closure_features(cfg, y).reshape(60, 140) - mean) / std
+    _, _, o = O.mlp_forward(p, feats, shape=shape)
+    bound = np.quantile(np.abs(o), 0.97, axis=0)  # some cells exceed a bound
+    clo = O.ClosureParams(p, mean, std, scale, bound, shape=shape)
+    corr, nfb = O.closure_correction(cfg, y, clo)
+    bad = np.any(np.abs(o) > bound, axis=1)
+    assert nfb == int(bad.sum()) and 0 < nfb < 60
+    c = np.where(bad[:, None], 0.0, scale * o)  # [cell][i*4+l]
+    c = c.reshape(60, 5, 4).transpose(1, 2, 0)
+    got = corr.reshape(5, 4, 60)
+    np.testing.assert_allclose(got[:, 1:], c[:, 1:], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(got[:, 0], c[:, 0] - c[:, 0].mean(axis=1, keepdims=True), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(got[:, 0].sum(axis=1), 0.0, atol=1e-12)
