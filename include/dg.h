@@ -59,6 +59,7 @@ typedef enum {
 
 enum {
     DG_FORCING = 1u,      /* add the driving source term of Sec. 3.1 (needs dg_set_forcing) */
+    DG_CLOSURE = 2u,      /* k = 1 only: add the learned closure correction (needs dg_set_closure) */
     DG_CHECK_RANGE = 4u   /* dg_step checks cell means for rho>0, p>0, finite after each step */
 };
 
@@ -76,8 +77,8 @@ typedef struct {
  * upload them and allocate the context's small device slots (dt, time,
  * partial sums).  hip_stream: a hipStream_t (NULL = default stream).
  * DG_ERR_ARG and no context for: k < 1, any n < 2, box <= 0, gamma <= 1,
- * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3
- * or a slab (5 N(k) n[0] elements) of 2 GiB or more. */
+ * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3,
+ * DG_CLOSURE with k != 1, or a slab (5 N(k) n[0] elements) of 2 GiB or more. */
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out);
 
 /* Release the context and its device memory.  NULL is accepted. */
@@ -142,6 +143,90 @@ dg_status dg_set_forcing(dg_ctx *ctx, int32_t nmodes, const int32_t *nvec, const
  * ahat: HOST output, same shape. */
 dg_status dg_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const double *z, double f,
                        double sigma, double a0, double kmin, double kmax, double *ahat);
+
+/* ---------------------------------------------------------------------------
+ * Learned closure (an addition to the paper's scheme, for under-resolved k = 1
+ * runs).  A cell's 140 features are the weights of the cell and of its -x,
+ * +x, -y, +y, -z, +z neighbours (periodic), ordered feat[j][i][l] (neighbour j,
+ * field i, mode l).  A 140-128-128-20 network with tanh hidden layers maps
+ * (feat - feat_mean) / feat_std to o (20 values ordered [i][l]); the
+ * correction is c = out_scale * o and the scheme becomes dy/dt = -R(y) + c,
+ * i.e. dg_rhs returns R - c and the stages use it.  A cell with any o_j
+ * non-finite or |o_j| > out_bound_j keeps the plain operator (c = 0 for that
+ * cell, counted as a fallback).  The mode-0 rows of c are then shifted by
+ * their mean over the mesh, per field, so the conserved totals are unchanged.
+ * Inference runs in FP32 (FP32 matrix cores) in every precision tier.
+ * ------------------------------------------------------------------------- */
+
+/* Install the network (DG_CLOSURE contexts only; DG_ERR_STATE otherwise).
+ * HOST arrays, copied: params [dg_mlp_nparams({140,128,128,20})] in the layout
+ * W1[128][140] b1[128] W2[128][128] b2[128] W3[20][128] b3[20]; feat_mean,
+ * feat_std [140] (std > 0); out_scale, out_bound [20] (bound >= 0).  The first
+ * call allocates the correction buffer (one state).  Synchronises. */
+dg_status dg_set_closure(dg_ctx *ctx, const float *params, const float *feat_mean, const float *feat_std,
+                         const float *out_scale, const float *out_bound);
+
+/* Cells that fell back since the previous call (summed over every closure
+ * evaluation, one per R evaluation), then reset.  count: HOST.  Synchronises. */
+dg_status dg_closure_fallbacks(dg_ctx *ctx, int64_t *count);
+
+/* Training data.  feat: DEVICE float [ncells][7][5][N] (raw, unstandardised)
+ * features of state y (any k).  Cells in x-fastest order (z, y, x). */
+dg_status dg_closure_features(dg_ctx *ctx, const void *y, float *feat);
+
+/* target[cell][i][l] = r_coarse - r_fine_restricted (DEVICE float
+ * [ncells][5N]); both inputs are states of ctx's shape, e.g. R_c(P y_f) and
+ * P R_f(y_f), whose difference is the correction a closure should supply. */
+dg_status dg_closure_targets(dg_ctx *ctx, const void *r_coarse, const void *r_fine_restricted, float *target);
+
+/* Exact L2 restriction onto ctx's mesh and degree (the coarse side): yf is a
+ * degree-kf state on the mesh with twice as many cells per axis (cell
+ * (2X+dx, 2Y+dy, 2Z+dz) is a child of coarse cell (X, Y, Z)); yc = the
+ * projection of the piecewise polynomial onto degree ctx.k, computed child by
+ * child with a Gauss rule exact for degree kf + k.  Linear, so it also
+ * restricts time derivatives.  k <= kf <= 3.  yf, yc: DEVICE, storage type of
+ * ctx.  The first call per kf allocates a small table. */
+dg_status dg_restrict(dg_ctx *ctx, int32_t kf, const void *yf, void *yc);
+
+/* ---- Dense tanh networks for the closure's training (no context) --------
+ * shape = {nin, nh1, nh2, nout}; params layout W1[nh1][nin] b1 W2[nh2][nh1] b2
+ * W3[nout][nh2] b3 (row-major), FP32, DEVICE.  All products on the FP32 matrix
+ * cores.  work: DEVICE, dg_mlp_workspace_bytes(shape, batch) bytes.
+ * hip_stream: the stream all work is enqueued on (NULL = default). */
+size_t dg_mlp_nparams(const int32_t shape[4]);
+size_t dg_mlp_workspace_bytes(const int32_t shape[4], int32_t batch);
+
+/* y[s][j] = network(x[rows[s]])_j for s < batch.  x: DEVICE [nsamples][nin];
+ * rows: DEVICE int32 [batch] sample indices, or NULL for rows 0..batch-1;
+ * y: DEVICE [batch][nout]. */
+dg_status dg_mlp_forward(const int32_t shape[4], const float *params, int32_t batch, const float *x,
+                         const int32_t *rows, float *y, void *work, void *hip_stream);
+
+/* Mean-squared error over the batch and the outputs, and its gradient:
+ * loss = mean_{s,j} (y_sj - target[rows[s]][j])^2; grad (DEVICE, params
+ * layout) = d loss / d params, summed over the batch in a fixed order.
+ * loss: DEVICE double, or NULL. */
+dg_status dg_mlp_loss_grad(const int32_t shape[4], const float *params, int32_t batch, const float *x,
+                           const float *target, const int32_t *rows, float *grad, double *loss, void *work,
+                           void *hip_stream);
+
+/* One Adam step (Kingma and Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  All DEVICE
+ * FP32 arrays of nparams entries, updated in place; step >= 1. */
+dg_status dg_adam(int64_t nparams, float *params, const float *grad, float *m, float *v, int32_t step, double lr,
+                  double beta1, double beta2, double eps, void *hip_stream);
+
+/* Column statistics of x (DEVICE float [rows][cols], cols <= 256), in FP64 with
+ * a fixed summation order: mean, standard deviation about the mean, root mean
+ * square about zero, max |x|.  Outputs: DEVICE double [cols] each.  work:
+ * DEVICE, dg_column_stats_workspace_bytes(cols) bytes. */
+size_t dg_column_stats_workspace_bytes(int32_t cols);
+dg_status dg_column_stats(const float *x, int64_t rows, int32_t cols, double *mean, double *stdev, double *rms,
+                          double *maxabs, void *work, void *hip_stream);
+
+/* x[r][c] = (x[r][c] - shift[c]) / scale[c] in place.  shift, scale: DEVICE double [cols]. */
+dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shift, const double *scale,
+                         void *hip_stream);
 
 /* Host-only helpers for callers that sample fields at the Gauss points. */
 int32_t dg_nmodes(int32_t k);                      /* N(k) = (k+1)(k+2)(k+3)/6, Sec. 2.1 */

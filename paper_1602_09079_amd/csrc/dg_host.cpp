@@ -363,8 +363,9 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
-    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CHECK_RANGE)) return DG_ERR_ARG;
+    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE)) return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
+    if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     {
         // the stage kernel addresses one (z, y) slab of 5 N(k) rows of n[0] cells with 32-bit offsets
         const double slab_bytes = 5.0 * nmodes_of(cfg->k) * cfg->n[0] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
@@ -452,6 +453,12 @@ dg_status dg_destroy(dg_ctx *c) {
     if (c->flag) hipFree(c->flag);
     if (c->partials) hipFree(c->partials);
     if (c->fmodes) hipFree(c->fmodes);
+    if (c->clo) hipFree(c->clo);
+    if (c->corr) hipFree(c->corr);
+    if (c->clo_partials) hipFree(c->clo_partials);
+    if (c->clo_fallbacks) hipFree(c->clo_fallbacks);
+    for (int j = 0; j < 4; j++)
+        if (c->restrict_tab[j]) hipFree(c->restrict_tab[j]);
     delete c;
     return DG_OK;
 }
@@ -480,7 +487,32 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
         c->err = "DG_FORCING set but dg_set_forcing was not called";
         return DG_ERR_STATE;
     }
+    if ((c->cfg.flags & DG_CLOSURE) && !c->have_closure) {
+        c->err = "DG_CLOSURE set but dg_set_closure was not called";
+        return DG_ERR_STATE;
+    }
     StageArgs s{};
+    if (c->cfg.flags & DG_CLOSURE) {
+        // the correction of the stage input, then the stage that applies it
+        ClosureArgs ca{};
+        ca.y = yin;
+        ca.corr = c->corr;
+        ca.params = c->clo;
+        ca.fmean = c->clo + CL_NPARAMS;
+        ca.fistd = ca.fmean + CL_NIN;
+        ca.oscale = ca.fistd + CL_NIN;
+        ca.obound = ca.oscale + CL_NOUT;
+        ca.partials = c->clo_partials + NF;
+        ca.fallbacks = c->clo_fallbacks;
+        ca.cmean = c->clo_partials;
+        ca.nx = c->cfg.n[0];
+        ca.ny = c->cfg.n[1];
+        ca.nz = c->cfg.n[2];
+        ca.ncells = c->ncells;
+        HIPCHK(c, launch_closure(c->cfg.precision, ca, c->stream));
+        s.corr = c->corr;
+        s.cmean = c->clo_partials;
+    }
     s.yin = yin;
     s.y0 = y0 ? y0 : yin;
     s.out = out;
@@ -671,6 +703,283 @@ dg_status dg_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const
             ahat[6 * m + 4 + part] = a0 * prof * (vz - n2 * dot);
         }
     }
+    return DG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned closure and its training
+
+extern "C" {
+
+dg_status dg_set_closure(dg_ctx *c, const float *params, const float *feat_mean, const float *feat_std,
+                         const float *out_scale, const float *out_bound) {
+    if (!c) return DG_ERR_ARG;
+    if (!(c->cfg.flags & DG_CLOSURE)) {
+        c->err = "dg_set_closure: the context was created without DG_CLOSURE";
+        return DG_ERR_STATE;
+    }
+    if (!params || !feat_mean || !feat_std || !out_scale || !out_bound) {
+        c->err = "dg_set_closure: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    std::vector<float> blob((size_t)CL_NPARAMS + 2 * CL_NIN + 2 * CL_NOUT);
+    std::memcpy(blob.data(), params, sizeof(float) * CL_NPARAMS);
+    float *fm = blob.data() + CL_NPARAMS, *fi = fm + CL_NIN, *os = fi + CL_NIN, *ob = os + CL_NOUT;
+    for (int f = 0; f < CL_NIN; f++) {
+        if (!(feat_std[f] > 0.0f) || !std::isfinite(feat_std[f]) || !std::isfinite(feat_mean[f])) {
+            c->err = "dg_set_closure: feat_std must be positive and finite, feat_mean finite";
+            return DG_ERR_ARG;
+        }
+        fm[f] = feat_mean[f];
+        fi[f] = 1.0f / feat_std[f];
+    }
+    for (int j = 0; j < CL_NOUT; j++) {
+        if (!std::isfinite(out_scale[j]) || !(out_bound[j] >= 0.0f)) {
+            c->err = "dg_set_closure: out_scale must be finite and out_bound >= 0";
+            return DG_ERR_ARG;
+        }
+        os[j] = out_scale[j];
+        ob[j] = out_bound[j];
+    }
+    if (!c->clo) {
+        const long long nwaves = (c->ncells + 15) / 16;
+        if (hipMalloc(&c->clo, blob.size() * sizeof(float)) != hipSuccess ||
+            hipMalloc(&c->corr, dg_state_count(c) * elem_bytes(c)) != hipSuccess ||
+            hipMalloc(&c->clo_partials, (size_t)(nwaves + 1) * NF * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->clo_fallbacks, sizeof(unsigned long long)) != hipSuccess) {
+            c->err = "dg_set_closure: device allocation failed";
+            return DG_ERR_HIP;
+        }
+        HIPCHK(c, launch_zero_u64(c->clo_fallbacks, c->stream));
+    }
+    // the copy is ordered after the work already enqueued on the stream
+    HIPCHK(c, hipMemcpyAsync(c->clo, blob.data(), blob.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_closure = true;
+    return DG_OK;
+}
+
+dg_status dg_closure_fallbacks(dg_ctx *c, int64_t *count) {
+    if (!c) return DG_ERR_ARG;
+    if (!count) {
+        c->err = "dg_closure_fallbacks: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    if (!c->have_closure) {
+        *count = 0;
+        return DG_OK;
+    }
+    unsigned long long v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->clo_fallbacks, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_zero_u64(c->clo_fallbacks, c->stream));
+    *count = (int64_t)v;
+    return DG_OK;
+}
+
+dg_status dg_closure_features(dg_ctx *c, const void *y, float *feat) {
+    if (!c) return DG_ERR_ARG;
+    if (!y || !feat) {
+        c->err = "dg_closure_features: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    HIPCHK(c, launch_features(c->cfg.precision, y, feat, c->N, c->cfg.n[0], c->cfg.n[1], c->cfg.n[2], c->ncells,
+                              c->stream));
+    return DG_OK;
+}
+
+dg_status dg_closure_targets(dg_ctx *c, const void *r_coarse, const void *r_fine_restricted, float *target) {
+    if (!c) return DG_ERR_ARG;
+    if (!r_coarse || !r_fine_restricted || !target) {
+        c->err = "dg_closure_targets: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    HIPCHK(c, launch_targets(c->cfg.precision, r_coarse, r_fine_restricted, target, c->N, c->cfg.n[0], c->ncells,
+                             c->stream));
+    return DG_OK;
+}
+
+dg_status dg_restrict(dg_ctx *c, int32_t kf, const void *yf, void *yc) {
+    if (!c) return DG_ERR_ARG;
+    if (kf < c->cfg.k || kf > 3) {
+        c->err = "dg_restrict: need k <= kf <= 3";
+        return kf > 3 ? DG_ERR_UNSUPPORTED : DG_ERR_ARG;
+    }
+    if (!yf || !yc || yf == yc) {
+        c->err = "dg_restrict: NULL or aliased pointers";
+        return DG_ERR_ARG;
+    }
+    const int Nf = nmodes_of(kf), Nc = c->N;
+    if (!c->restrict_tab[kf]) {
+        // M[ch][l][m] = (1/64) sum_q phi^f_m(xi_q) phi^c_l(xi^c(xi_q)) w_q over a Gauss rule of the
+        // child exact for degree kf + kc; child ch = (dz dy dx) bits, xi^c = -1/2 + d + xi/2
+        const Basis Bf(kf), Bc(c->cfg.k);
+        const int nq = (kf + c->cfg.k) / 2 + 1;
+        double xg[5], wg[5];
+        gauss_rule(nq, xg, wg);
+        std::vector<double> M((size_t)8 * Nc * Nf, 0.0);
+        for (int ch = 0; ch < 8; ch++) {
+            const int d[3] = {ch & 1, (ch >> 1) & 1, ch >> 2};
+            for (int qc = 0; qc < nq; qc++)
+                for (int qb = 0; qb < nq; qb++)
+                    for (int qa = 0; qa < nq; qa++) {
+                        const double xf[3] = {xg[qa], xg[qb], xg[qc]};
+                        double xcs[3];
+                        for (int a = 0; a < 3; a++) xcs[a] = -0.5 + d[a] + 0.5 * xf[a];
+                        const double w = wg[qa] * wg[qb] * wg[qc] / 64.0;
+                        for (int l = 0; l < Nc; l++) {
+                            const double pc = Bc.phi(l, xcs) * w;
+                            for (int m = 0; m < Nf; m++) M[((size_t)ch * Nc + l) * Nf + m] += pc * Bf.phi(m, xf);
+                        }
+                    }
+        }
+        double *dM = nullptr;
+        HIPCHK(c, hipMalloc(&dM, M.size() * sizeof(double)));
+        c->restrict_tab[kf] = dM;
+        HIPCHK(c, hipMemcpy(dM, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, launch_restrict(c->cfg.precision, yf, yc, c->restrict_tab[kf], Nf, Nc, c->cfg.n[0], c->cfg.n[1],
+                              c->cfg.n[2], c->stream));
+    return DG_OK;
+}
+
+// ---- MLP training (no context): the caller's stream and workspace
+
+static bool mlp_shape_ok(const int32_t *sh) {
+    return sh && sh[0] >= 1 && sh[1] >= 1 && sh[2] >= 1 && sh[3] >= 1 && sh[0] <= 4096 && sh[1] <= 4096 &&
+           sh[2] <= 4096 && sh[3] <= 4096;
+}
+
+size_t dg_mlp_nparams(const int32_t shape[4]) {
+    if (!mlp_shape_ok(shape)) return 0;
+    const size_t a = shape[0], b = shape[1], cc = shape[2], d = shape[3];
+    return b * a + b + cc * b + cc + d * cc + d;
+}
+
+size_t dg_mlp_workspace_bytes(const int32_t shape[4], int32_t batch) {
+    if (!mlp_shape_ok(shape) || batch < 1) return 0;
+    const size_t B = batch;
+    // Xb, H1, H2, Y, Tb, dY, D2, D1 (feature-major) and a loss slot
+    return sizeof(float) * B * ((size_t)shape[0] + 2 * shape[1] + 2 * shape[2] + 3 * shape[3]) + 64;
+}
+
+namespace {
+struct MlpWork {
+    float *Xb, *H1, *H2, *Y, *Tb, *dY, *D2, *D1;
+};
+MlpWork carve(const int32_t *sh, int B, void *work) {
+    float *p = static_cast<float *>(work);
+    MlpWork w;
+    w.Xb = p; p += (size_t)sh[0] * B;
+    w.H1 = p; p += (size_t)sh[1] * B;
+    w.D1 = p; p += (size_t)sh[1] * B;
+    w.H2 = p; p += (size_t)sh[2] * B;
+    w.D2 = p; p += (size_t)sh[2] * B;
+    w.Y = p; p += (size_t)sh[3] * B;
+    w.Tb = p; p += (size_t)sh[3] * B;
+    w.dY = p;
+    return w;
+}
+// C[M][B] = act(W[M][K] X[K][B] + b), feature-major activations
+hipError_t dense(const float *W, const float *b, const float *X, float *C, int M, int K, int B, int ep,
+                 hipStream_t s) {
+    GemmArgs g{};
+    g.A = W; g.B = X; g.C = C; g.bias = b; g.E = nullptr;
+    g.M = M; g.N = B; g.K = K;
+    g.sam = K; g.sak = 1; g.sbk = B; g.sbn = 1; g.scm = B; g.scn = 1;
+    g.ep = ep;
+    return launch_gemm(g, s);
+}
+hipError_t mlp_fwd(const int32_t *sh, const float *P, int B, const MlpWork &w, hipStream_t s) {
+    const int nin = sh[0], h1 = sh[1], h2 = sh[2], no = sh[3];
+    const float *W1 = P, *b1 = W1 + (size_t)h1 * nin, *W2 = b1 + h1, *b2 = W2 + (size_t)h2 * h1;
+    const float *W3 = b2 + h2, *b3 = W3 + (size_t)no * h2;
+    hipError_t e;
+    if ((e = dense(W1, b1, w.Xb, w.H1, h1, nin, B, EP_TANH, s)) != hipSuccess) return e;
+    if ((e = dense(W2, b2, w.H1, w.H2, h2, h1, B, EP_TANH, s)) != hipSuccess) return e;
+    return dense(W3, b3, w.H2, w.Y, no, h2, B, EP_NONE, s);
+}
+}  // namespace
+
+dg_status dg_mlp_forward(const int32_t shape[4], const float *params, int32_t batch, const float *x, const int32_t *rows,
+                         float *y, void *work, void *hip_stream) {
+    if (!mlp_shape_ok(shape) || batch < 1 || !params || !x || !y || !work) return DG_ERR_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const MlpWork w = carve(shape, batch, work);
+    if (launch_gather(x, shape[0], rows, batch, w.Xb, s) != hipSuccess) return DG_ERR_HIP;
+    if (mlp_fwd(shape, params, batch, w, s) != hipSuccess) return DG_ERR_HIP;
+    // y[s][j] = Y[j][s]: the gather kernel with the roles of rows and columns swapped transposes
+    if (launch_gather(w.Y, batch, nullptr, shape[3], y, s) != hipSuccess) return DG_ERR_HIP;
+    return DG_OK;
+}
+
+dg_status dg_mlp_loss_grad(const int32_t shape[4], const float *params, int32_t batch, const float *x,
+                           const float *target, const int32_t *rows, float *grad, double *loss, void *work,
+                           void *hip_stream) {
+    if (!mlp_shape_ok(shape) || batch < 1 || !params || !x || !target || !grad || !work) return DG_ERR_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int nin = shape[0], h1 = shape[1], h2 = shape[2], no = shape[3], B = batch;
+    const MlpWork w = carve(shape, B, work);
+    const float *W2 = params + (size_t)h1 * nin + h1, *W3 = W2 + (size_t)h2 * h1 + h2;
+    float *gW1 = grad, *gb1 = gW1 + (size_t)h1 * nin, *gW2 = gb1 + h1, *gb2 = gW2 + (size_t)h2 * h1;
+    float *gW3 = gb2 + h2, *gb3 = gW3 + (size_t)no * h2;
+    auto ok = [](hipError_t e) { return e == hipSuccess; };
+    if (!ok(launch_gather(x, nin, rows, B, w.Xb, s)) || !ok(launch_gather(target, no, rows, B, w.Tb, s)) ||
+        !ok(mlp_fwd(shape, params, B, w, s)) || !ok(launch_mse(w.Y, w.Tb, w.dY, (long long)no * B, loss, s)))
+        return DG_ERR_HIP;
+    // weight gradients: gW = D A^T (contraction over the batch); bias gradients: row sums of D
+    auto wgrad = [&](const float *D, const float *Aact, float *gW, int M, int K) {
+        GemmArgs g{};
+        g.A = D; g.B = Aact; g.C = gW; g.M = M; g.N = K; g.K = B;
+        g.sam = B; g.sak = 1; g.sbk = 1; g.sbn = B; g.scm = K; g.scn = 1;
+        g.ep = EP_NONE;
+        return launch_gemm(g, s);
+    };
+    // back-propagated signal: D_prev = (W^T D) * (1 - H_prev^2)
+    auto bprop = [&](const float *W, const float *D, const float *Hp, float *Dp, int Mout, int Kin) {
+        GemmArgs g{};
+        g.A = W; g.B = D; g.C = Dp; g.E = Hp; g.M = Kin; g.N = B; g.K = Mout;
+        g.sam = 1; g.sak = Kin; g.sbk = B; g.sbn = 1; g.scm = B; g.scn = 1;
+        g.ep = EP_DTANH;
+        return launch_gemm(g, s);
+    };
+    if (!ok(wgrad(w.dY, w.H2, gW3, no, h2)) || !ok(launch_rowsum(w.dY, no, B, gb3, s)) ||
+        !ok(bprop(W3, w.dY, w.H2, w.D2, no, h2)) || !ok(wgrad(w.D2, w.H1, gW2, h2, h1)) ||
+        !ok(launch_rowsum(w.D2, h2, B, gb2, s)) || !ok(bprop(W2, w.D2, w.H1, w.D1, h2, h1)) ||
+        !ok(wgrad(w.D1, w.Xb, gW1, h1, nin)) || !ok(launch_rowsum(w.D1, h1, B, gb1, s)))
+        return DG_ERR_HIP;
+    return DG_OK;
+}
+
+dg_status dg_adam(int64_t nparams, float *params, const float *grad, float *m, float *v, int32_t step, double lr,
+                  double beta1, double beta2, double eps, void *hip_stream) {
+    if (nparams < 1 || !params || !grad || !m || !v || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+        !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return DG_ERR_ARG;
+    if (launch_adam(params, grad, m, v, nparams, step, lr, beta1, beta2, eps, reinterpret_cast<hipStream_t>(hip_stream)) !=
+        hipSuccess)
+        return DG_ERR_HIP;
+    return DG_OK;
+}
+
+size_t dg_column_stats_workspace_bytes(int32_t cols) { return cols < 1 ? 0 : (size_t)1024 * cols * 3 * sizeof(double); }
+
+dg_status dg_column_stats(const float *x, int64_t rows, int32_t cols, double *mean, double *stdev, double *rms,
+                          double *maxabs, void *work, void *hip_stream) {
+    if (!x || rows < 1 || cols < 1 || cols > 256 || !mean || !stdev || !rms || !maxabs || !work) return DG_ERR_ARG;
+    const int nchunks = (int)std::min<int64_t>(1024, rows);
+    if (launch_colstats(x, rows, cols, static_cast<double *>(work), nchunks, mean, stdev, rms, maxabs,
+                        reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return DG_ERR_HIP;
+    return DG_OK;
+}
+
+dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shift, const double *scale,
+                         void *hip_stream) {
+    if (!x || rows < 1 || cols < 1 || !shift || !scale) return DG_ERR_ARG;
+    if (launch_standardize(x, rows, cols, shift, scale, reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return DG_ERR_HIP;
     return DG_OK;
 }
 

@@ -73,6 +73,8 @@ struct StageArgs {
     const double *fmodes; // device mode table [KF/2][9]: n_x, n_y, n_z, then Re/Im of ahat_x, ahat_y, ahat_z
     int nfmodes;
     double h[3];          // cell widths
+    const void *corr;     // closure correction c (state layout) or nullptr: R <- R - (c - cmean on mode 0)
+    const double *cmean;  // [5] mean of c's mode-0 rows per field
 };
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
@@ -86,6 +88,58 @@ hipError_t launch_cfl(int prec, const void *y, int N, int nx, long long ncells, 
 hipError_t launch_totals(int prec, const void *y, int N, int nx, long long ncells, double vol, double *partials,
                          int nparts, double *out, hipStream_t s);
 hipError_t launch_range_check(int prec, const void *y, int N, int nx, long long ncells, double gamma, int *flag,
+                              hipStream_t s);
+
+// ---- learned closure (k = 1): 140 -> 128 -> 128 -> 20, tanh
+constexpr int CL_ROWS = NF * 4;         // weight rows per cell at k = 1
+constexpr int CL_NIN = 7 * CL_ROWS;     // self and six face neighbours
+constexpr int CL_NH = 128;
+constexpr int CL_NOUT = CL_ROWS;
+constexpr long long CL_NPARAMS = (long long)CL_NH * CL_NIN + CL_NH + CL_NH * CL_NH + CL_NH + CL_NOUT * CL_NH + CL_NOUT;
+
+struct ClosureArgs {
+    const void *y;
+    void *corr;
+    const float *params;   // W1 b1 W2 b2 W3 b3, W row-major [out][in]
+    const float *fmean;    // [CL_NIN]
+    const float *fistd;    // [CL_NIN] 1 / std
+    const float *oscale;   // [CL_NOUT]
+    const float *obound;   // [CL_NOUT]
+    double *partials;      // [waves][5]
+    unsigned long long *fallbacks;
+    double *cmean;         // [5]
+    int nx, ny, nz;
+    long long ncells;
+};
+hipError_t launch_closure(int prec, const ClosureArgs &a, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
+hipError_t launch_features(int prec, const void *y, float *feat, int N, int nx, int ny, int nz, long long nc,
+                           hipStream_t s);
+hipError_t launch_targets(int prec, const void *rc, const void *prf, float *out, int N, int nx, long long nc,
+                          hipStream_t s);
+hipError_t launch_restrict(int prec, const void *yf, void *yc, const double *M, int Nf, int Nc, int NX, int NY, int NZ,
+                           hipStream_t s);
+
+// ---- training kernels
+enum { EP_NONE = 0, EP_TANH = 1, EP_DTANH = 2 };
+struct GemmArgs {
+    const float *A, *B;
+    float *C;
+    const float *bias;  // [M] or nullptr
+    const float *E;     // EP_DTANH: tanh outputs, C's strides
+    int M, N, K;
+    long long sam, sak, sbk, sbn, scm, scn;
+    int ep;
+};
+hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
+hipError_t launch_rowsum(const float *X, int M, int N, float *out, hipStream_t s);
+hipError_t launch_gather(const float *X, int cols, const int *rows, int batch, float *Xb, hipStream_t s);
+hipError_t launch_mse(const float *Y, const float *T, float *dY, long long n, double *loss, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, int step, double lr, double b1,
+                       double b2, double eps, hipStream_t s);
+hipError_t launch_colstats(const float *x, long long rows, int cols, double *part, int nchunks, double *mean,
+                           double *stdv, double *rms, double *maxabs, hipStream_t s);
+hipError_t launch_standardize(float *x, long long rows, int cols, const double *shift, const double *scale,
                               hipStream_t s);
 
 }  // namespace dgmi
@@ -112,5 +166,12 @@ struct dg_ctx {
     int cur_slot = 1;              // slot holding the latest CFL rate
     int lds = 0;
     long long step_count = 0;
+    // closure (DG_CLOSURE)
+    float *clo = nullptr;                 // params, fmean, fistd, oscale, obound
+    void *corr = nullptr;                 // correction, state layout
+    double *clo_partials = nullptr;       // per-wave mean-row sums; then [5] means
+    unsigned long long *clo_fallbacks = nullptr;
+    bool have_closure = false;
+    double *restrict_tab[4] = {nullptr, nullptr, nullptr, nullptr};  // per fine degree: [8][N][Nf]
     std::string err;
 };

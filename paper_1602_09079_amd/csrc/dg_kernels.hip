@@ -865,7 +865,11 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 #pragma unroll
                             for (int i = 0; i < NF; i++) {
                                 const unsigned so = (unsigned)i * fbytes;
-                                const C R = (C)acc[i][rt][r];
+                                C R = (C)acc[i][rt][r];
+                                if (a.corr) {  // learned closure: dy/dt = -R + c
+                                    const auto rcr = slab_rsrc(reinterpret_cast<const S *>(a.corr), slabn, rz);
+                                    R -= (C)bload(S(), rcr, e, so) - (m == 0 ? (C)a.cmean[i] : C(0));
+                                }
                                 if (a.mode == 0) {
                                     bstore((S)R, ro, e + so);
                                 } else {

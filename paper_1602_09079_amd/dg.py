@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libdgmi.so")
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_RANGE, DG_ERR_STATE = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 DG_FORCING = 1
+DG_CLOSURE = 2
 DG_CHECK_RANGE = 4
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
                 5: "DG_ERR_STATE"}
@@ -21,7 +22,9 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR
 # every entry point declared in include/dg.h
 EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_project", "dg_rhs", "dg_stage",
            "dg_dt", "dg_step", "dg_totals", "dg_set_forcing", "dg_ou_update", "dg_nmodes", "dg_gauss_nodes",
-           "dg_error_string"]
+           "dg_error_string", "dg_set_closure", "dg_closure_fallbacks", "dg_closure_features", "dg_closure_targets",
+           "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
+           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize"]
 
 
 class DGError(RuntimeError):
@@ -40,6 +43,7 @@ _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 
 def lib():
@@ -65,6 +69,20 @@ def lib():
             "dg_nmodes": (ctypes.c_int32, [ctypes.c_int32]),
             "dg_gauss_nodes": (ctypes.c_int, [ctypes.c_int32, _dp]),
             "dg_error_string": (ctypes.c_char_p, [_vp]),
+            "dg_set_closure": (ctypes.c_int, [_vp, _fp, _fp, _fp, _fp, _fp]),
+            "dg_closure_fallbacks": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+            "dg_closure_features": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_closure_targets": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+            "dg_restrict": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp]),
+            "dg_mlp_nparams": (ctypes.c_size_t, [_ip]),
+            "dg_mlp_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int32]),
+            "dg_mlp_forward": (ctypes.c_int, [_ip, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]),
+            "dg_mlp_loss_grad": (ctypes.c_int, [_ip, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "dg_adam": (ctypes.c_int, [ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
+            "dg_column_stats_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+            "dg_column_stats": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "dg_standardize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -129,10 +147,12 @@ class Solver:
     """One DG context on the current CUDA (HIP) device and stream."""
 
     def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
-                 forcing=False, check_range=False, stream=None):
+                 forcing=False, check_range=False, closure=False, stream=None):
         import torch
         if forcing:
             flags |= DG_FORCING
+        if closure:
+            flags |= DG_CLOSURE
         if check_range:
             flags |= DG_CHECK_RANGE
         self.cfg = make_config(k, n, box, gamma, cfl, precision, flags)
@@ -240,3 +260,136 @@ class Solver:
         ahat = np.ascontiguousarray(ahat, dtype=np.float64).reshape(-1, 3, 2)
         self._check(lib().dg_set_forcing(self._ctx, len(nvec), nvec.ctypes.data_as(_ip), ahat.ctypes.data_as(_dp)),
                     "dg_set_forcing")
+
+    # ------------------------------------------------------------ closure
+    def set_closure(self, params, feat_mean, feat_std, out_scale, out_bound):
+        """Host arrays (any float dtype), copied as float32."""
+        import numpy as np
+        a = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).astype(np.float32))
+             for v in (params, feat_mean, feat_std, out_scale, out_bound)]
+        self._check(lib().dg_set_closure(self._ctx, *[v.ctypes.data_as(_fp) for v in a]), "dg_set_closure")
+
+    def closure_fallbacks(self):
+        v = ctypes.c_int64()
+        self._check(lib().dg_closure_fallbacks(self._ctx, ctypes.byref(v)), "dg_closure_fallbacks")
+        return v.value
+
+    def closure_features(self, y, out=None):
+        import torch
+        nc = self.n[0] * self.n[1] * self.n[2]
+        f = torch.empty((nc, 7 * 5 * self.N), dtype=torch.float32, device=self.device) if out is None else out
+        self._check(lib().dg_closure_features(self._ctx, self._ptr(y, self.state_shape()), _vp(f.data_ptr())),
+                    "dg_closure_features")
+        return f
+
+    def closure_targets(self, r_coarse, r_fine_restricted, out=None):
+        import torch
+        nc = self.n[0] * self.n[1] * self.n[2]
+        t = torch.empty((nc, 5 * self.N), dtype=torch.float32, device=self.device) if out is None else out
+        self._check(lib().dg_closure_targets(self._ctx, self._ptr(r_coarse, self.state_shape()),
+                                             self._ptr(r_fine_restricted, self.state_shape()), _vp(t.data_ptr())),
+                    "dg_closure_targets")
+        return t
+
+    def restrict(self, kf, yf, out=None):
+        """yf: a degree-kf state on the mesh with twice the cells per axis (same storage type)."""
+        yc = self.empty_state() if out is None else out
+        fshape = (2 * self.n[2], 2 * self.n[1], 5, nmodes(kf), 2 * self.n[0])
+        self._check(lib().dg_restrict(self._ctx, kf, self._ptr(yf, fshape), self._ptr(yc, self.state_shape())),
+                    "dg_restrict")
+        return yc
+
+
+# ---------------------------------------------------------------- dense networks (closure training)
+
+def _f32ptr(t):
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return _vp(t.data_ptr())
+
+
+def _shape_arr(shape):
+    return (ctypes.c_int32 * 4)(*shape)
+
+
+def mlp_nparams(shape):
+    return lib().dg_mlp_nparams(_shape_arr(shape))
+
+
+class MLP:
+    """Device-side tanh network of the closure: forward, loss gradient, Adam."""
+
+    def __init__(self, shape, batch, stream=None):
+        import torch
+        self.shape = tuple(shape)
+        self.batch = batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nb = lib().dg_mlp_workspace_bytes(_shape_arr(shape), batch)
+        if nb == 0:
+            raise ValueError("invalid network shape or batch")
+        self.work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        self.nparams = mlp_nparams(shape)
+
+    def _s(self):
+        return _vp(self.stream.cuda_stream)
+
+    def forward(self, params, x, rows=None, batch=None):
+        import torch
+        B = batch or (len(rows) if rows is not None else x.shape[0])
+        if B > self.batch:
+            raise ValueError("batch larger than the workspace")
+        y = torch.empty((B, self.shape[3]), dtype=torch.float32, device="cuda")
+        rp = _vp(rows.data_ptr()) if rows is not None else _vp()
+        st = lib().dg_mlp_forward(_shape_arr(self.shape), _f32ptr(params), B, _f32ptr(x), rp, _f32ptr(y),
+                                  _vp(self.work.data_ptr()), self._s())
+        if st != DG_OK:
+            raise DGError(st, "dg_mlp_forward")
+        return y
+
+    def loss_grad(self, params, x, target, rows=None, grad=None, loss=None, batch=None):
+        """Returns (grad, loss) device tensors; loss is a float64 scalar tensor."""
+        import torch
+        B = batch or (len(rows) if rows is not None else x.shape[0])
+        if B > self.batch:
+            raise ValueError("batch larger than the workspace")
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda") if grad is None else grad
+        lo = torch.empty((), dtype=torch.float64, device="cuda") if loss is None else loss
+        rp = _vp(rows.data_ptr()) if rows is not None else _vp()
+        st = lib().dg_mlp_loss_grad(_shape_arr(self.shape), _f32ptr(params), B, _f32ptr(x), _f32ptr(target), rp,
+                                    _f32ptr(g), _vp(lo.data_ptr()), _vp(self.work.data_ptr()), self._s())
+        if st != DG_OK:
+            raise DGError(st, "dg_mlp_loss_grad")
+        return g, lo
+
+    def adam(self, params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        st = lib().dg_adam(self.nparams, _f32ptr(params), _f32ptr(grad), _f32ptr(m), _f32ptr(v), step, lr, beta1,
+                           beta2, eps, self._s())
+        if st != DG_OK:
+            raise DGError(st, "dg_adam")
+
+
+def column_stats(x, stream=None):
+    """(mean, std, rms, maxabs) float64 device tensors of the columns of a float32 [rows][cols] tensor."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rows, cols = x.shape
+    out = [torch.empty(cols, dtype=torch.float64, device="cuda") for _ in range(4)]
+    work = torch.empty(lib().dg_column_stats_workspace_bytes(cols), dtype=torch.uint8, device="cuda")
+    st = lib().dg_column_stats(_f32ptr(x), rows, cols, *[_vp(o.data_ptr()) for o in out], _vp(work.data_ptr()),
+                               _vp(s.cuda_stream))
+    if st != DG_OK:
+        raise DGError(st, "dg_column_stats")
+    return tuple(out)
+
+
+def standardize(x, shift, scale, stream=None):
+    """x = (x - shift) / scale in place, per column (shift, scale: float64 device tensors)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rows, cols = x.shape
+    st = lib().dg_standardize(_f32ptr(x), rows, cols, _vp(shift.data_ptr()), _vp(scale.data_ptr()),
+                              _vp(s.cuda_stream))
+    if st != DG_OK:
+        raise DGError(st, "dg_standardize")
+    return x

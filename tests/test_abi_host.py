@@ -74,7 +74,18 @@ def test_ou_update_matches_oracle():
     (dict(k=1, n=8, cfl=0.0), dg.DG_ERR_ARG),
     (dict(k=1, n=8, cfl=1.5), dg.DG_ERR_ARG),
     (dict(k=1, n=8, precision=7), dg.DG_ERR_ARG),
-    (dict(k=1, n=8, flags=2), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, flags=8), dg.DG_ERR_ARG),
+    (dict(k=2, n=8, flags=dg.DG_CLOSURE), dg.DG_ERR_UNSUPPORTED),
 ])
 def test_config_validation(kw, status):
     assert dg.init_status(dg.make_config(**kw)) == status
+
+
+def test_mlp_host_helpers():
+    shape = (140, 128, 128, 20)
+    assert dg.mlp_nparams(shape) == O.mlp_nparams(*shape) == 37140
+    assert dg.lib().dg_mlp_workspace_bytes(dg._shape_arr(shape), 4096) >= 4 * 4096 * (140 + 4 * 128 + 3 * 20)
+    assert dg.mlp_nparams((0, 1, 1, 1)) == 0
+    # invalid arguments are rejected before any device work
+    assert dg.lib().dg_adam(10, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == dg.DG_ERR_ARG
+    assert dg.lib().dg_column_stats(None, 10, 3, None, None, None, None, None, None) == dg.DG_ERR_ARG
