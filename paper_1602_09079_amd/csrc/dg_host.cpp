@@ -156,13 +156,22 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
         return out_row(L.prec, g, j);
     };
     double xi[3];
+    // mode of B-operand value (K-step st, lane group g, value j) of GEMM1/GEMM3
+    auto in_mode = [&](int st, int g, int j) {
+        return L.kpl == 1 ? slot_mode(N, g, st) : (st == 0 ? slot_mode(N, g, j) : N);
+    };
+    // mode of result row rho of GEMM2/4/5: the row lands in lane group g, register r of tile rho/16
+    auto row_mode = [&](int rho) {
+        const int rr = rho % 16;
+        const int g = L.prec == DG_FP64 ? rr % 4 : rr / 4, r = L.prec == DG_FP64 ? rr / 4 : rr % 4;
+        return slot_mode(N, g, 4 * (rho / 16) + r);
+    };
     for (int lane = 0; lane < 64; lane++) {
         const int row = lane % 16, g = lane / 16;
         for (int j = 0; j < L.kpl; j++) {
-            const int kk = g * L.kpl + j;
             for (int t = 0; t < L.rt1; t++)  // T1: Phi[q][m]
                 for (int st = 0; st < L.ks1; st++) {
-                    const int q = 16 * t + row, m = st * L.kstep + kk;
+                    const int q = 16 * t + row, m = in_mode(st, g, j);
                     if (q < Q && m >= 1 && m < N) {  // mode 0 (the mean) is added apart
                         B.point(q, xi);
                         t1[(((size_t)t * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
@@ -170,7 +179,7 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                 }
             for (int f = 0; f < 6; f++)  // T3: Phi[face point][m]
                 for (int st = 0; st < L.ks1; st++) {
-                    const int p = row, m = st * L.kstep + kk;
+                    const int p = row, m = in_mode(st, g, j);
                     if (p < P && m >= 1 && m < N) {  // mode 0 (the mean) is added apart
                         B.face_point(f, p, xi);
                         t3[(((size_t)f * L.ks1 + st) * 64 + lane) * L.kpl + j] = B.phi(m, xi);
@@ -182,7 +191,7 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                 for (int c = 0; c < L.nc4; c++) {
                     int f;
                     const int p = face_slot(c, g, j, f);
-                    const int m = 16 * rt + row;
+                    const int m = row_mode(16 * rt + row);
                     if (p < P && m < N) {
                         B.face_point(f, p, xi);
                         const double sg = (f & 1) ? 1.0 : -1.0;
@@ -191,7 +200,7 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
                 }
             for (int rt = 0; rt < L.rt2; rt++)
                 for (int c = 0; c < L.nc2; c++) {
-                    const int m = 16 * rt + row, q = vol_point(c, g, j);
+                    const int m = row_mode(16 * rt + row), q = vol_point(c, g, j);
                     if (q < Q && m < N) {
                         B.point(q, xi);
                         for (int a = 0; a < 3; a++)  // T2: -s_a dPhi_a[m][q] w_q
@@ -416,12 +425,20 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipMemset(c->slots, 0, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->flag, sizeof(int)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
-    c->lds = (int)(c->lay.bytes() + c->f6_bytes);
     {
         int dev0 = 0, maxlds = 0;
         if (hipGetDevice(&dev0) != hipSuccess ||
             hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev0) != hipSuccess)
             return fail(DG_ERR_HIP);
+        // separate y-face trace and flux regions when both fit, else one shared region
+        const int exb = (int)stage_exchange_bytes(cfg->precision);
+        c->ex_off = (int)(c->lay.bytes() + c->f6_bytes);
+        c->ex_off2 = c->ex_off + exb;
+        c->lds = c->ex_off + 2 * exb;
+        if (c->lds > maxlds) {
+            c->ex_off2 = c->ex_off;
+            c->lds = c->ex_off + exb;
+        }
         if (c->lds > maxlds) return fail(DG_ERR_UNSUPPORTED);
     }
     if (set_stage_attributes(cfg->k, cfg->precision, c->lds) != hipSuccess) return fail(DG_ERR_HIP);
@@ -429,16 +446,18 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipGetDevice(&dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-    // z chunk length: long sweeps, but at least ~3 work items per resident wave
+    // z chunk length: long sweeps, but at least ~3 work items per resident item slot
     const long long nbx = (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
-    const int waves_per_wg = stage_block_threads() / 64;
-    const long long resident = (long long)per_cu * ncu * waves_per_wg;
-    long long zl = (nbx * cfg->n[1] * cfg->n[2]) / std::max(1LL, 3 * resident);
+    const int rows = stage_rows_per_item(cfg->precision);
+    const int items_per_wg = rows == 1 ? stage_block_threads(cfg->precision) / 64 : 1;  // one item per wave or per workgroup
+    const long long nyg = (cfg->n[1] + rows - 1) / rows;
+    const long long resident = (long long)per_cu * ncu * items_per_wg;
+    long long zl = (nbx * nyg * cfg->n[2]) / std::max(1LL, 3 * resident);
     zl = std::max(1LL, std::min(32LL, std::min(zl, (long long)cfg->n[2])));
     c->zlen = (int)zl;
-    const long long nitems = nbx * cfg->n[1] * ((cfg->n[2] + zl - 1) / zl);
+    const long long nitems = nbx * nyg * ((cfg->n[2] + zl - 1) / zl);
     long long grid = (long long)per_cu * ncu;
-    grid = std::min(grid, (nitems + waves_per_wg - 1) / waves_per_wg);
+    grid = std::min(grid, (nitems + items_per_wg - 1) / items_per_wg);
     if (grid >= 8) grid -= grid % 8;
     c->grid = (int)std::max(1LL, grid);
     *out = c;
@@ -529,7 +548,13 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.nz = c->cfg.n[2];
     s.nbx = (c->cfg.n[0] + BLK_INNER - 1) / BLK_INNER;
     s.zlen = c->zlen;
-    s.nitems = (long long)s.nbx * s.ny * ((s.nz + c->zlen - 1) / c->zlen);
+    {
+        const int rows = stage_rows_per_item(c->cfg.precision);
+        s.nitems = (long long)s.nbx * ((s.ny + rows - 1) / rows) * ((s.nz + c->zlen - 1) / c->zlen);
+    }
+    s.ex_off = c->ex_off;
+    s.ex_off2 = c->ex_off2;
+    s.ex_single = c->ex_off2 == c->ex_off ? 1 : 0;
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;

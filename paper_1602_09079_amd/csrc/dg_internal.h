@@ -27,6 +27,26 @@ inline int nmodes_of(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 // register r.  FP32/BF16 accumulators: 4g + r.  FP64 (16x16x4f64): g + 4r.
 inline int out_row(int prec, int g, int r) { return prec == DG_FP64 ? g + 4 * r : 4 * g + r; }
 
+// Mode assignment shared by every product: lane group g owns the modes
+// g*spl .. g*spl + spl - 1 (spl = ceil(N/4)), mode slot s = 0..spl-1.  Slot s is
+// the K-step s (FP32/FP64) or value s (BF16) of the B operands of GEMM1/GEMM3,
+// and the result register r of row tile rt with s = 4 rt + r of GEMM2/4/5, so
+// the weights a lane loads as product inputs are the modes of the result rows
+// it receives.  Returns N for an unused slot.
+__host__ __device__ constexpr int mode_slots(int N) { return (N + 3) / 4; }
+__host__ __device__ constexpr int slot_mode(int N, int g, int s) {
+    return (s < mode_slots(N) && g * mode_slots(N) + s < N) ? g * mode_slots(N) + s : N;
+}
+
+// Stage kernel launch shape.  FP32-storage tiers: workgroups of 8 waves that own
+// 8 consecutive y rows of one x-block and sweep z together, sharing y-face traces
+// and fluxes through LDS.  FP64: workgroups of 4 independent waves.
+constexpr int YROWS = 8;
+inline int stage_block_threads(int prec) { return prec == DG_FP64 ? 256 : 64 * YROWS; }
+inline int stage_rows_per_item(int prec) { return prec == DG_FP64 ? 1 : YROWS; }
+// LDS bytes of one y-face exchange region: a slot of 5 fields x 4 values x 64 lanes per wave
+inline size_t stage_exchange_bytes(int prec) { return prec == DG_FP64 ? 0 : (size_t)YROWS * NF * 4 * 64 * 4; }
+
 // Geometry of the MFMA operand tables for one (k, precision).  A "fragment" is
 // what the 64 lanes feed to one MFMA as its A operand.  GEMM1/3/4 use the wide
 // MFMA (K = 4 for FP32/FP64, K = 32 for BF16: kpl values per lane); GEMM2/5
@@ -66,7 +86,10 @@ struct StageArgs {
     int nx, ny, nz;
     int nbx;              // x-blocks per row
     int zlen;             // cells per z chunk swept by one wave
-    long long nitems;     // work items: nbx * ny * ceil(nz / zlen)
+    long long nitems;     // work items: nbx * ceil(ny / rows per item) * ceil(nz / zlen)
+    int ex_off;           // LDS byte offset of the y-face trace slots
+    int ex_off2;          // LDS byte offset of the y-face flux slots (== ex_off: shared, ex_single = 1)
+    int ex_single;
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
@@ -79,7 +102,6 @@ struct StageArgs {
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
 hipError_t set_stage_attributes(int k, int prec, int lds_bytes);
-int stage_block_threads();
 
 hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long ncells, int nx,
                           hipStream_t s);
@@ -163,6 +185,8 @@ struct dg_ctx {
     bool have_forcing = false;
     int grid = 0;
     int zlen = 1;                  // z chunk length of the stage sweep
+    int ex_off = 0;                // LDS offsets of the y-face trace and flux regions (after the tables)
+    int ex_off2 = 0;
     int cur_slot = 1;              // slot holding the latest CFL rate
     int lds = 0;
     long long step_count = 0;

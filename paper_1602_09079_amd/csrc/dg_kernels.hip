@@ -381,7 +381,9 @@ __device__ inline void sincos_2pi(double ph, float &s, float &c) {
 }
 __device__ inline void sincos_2pi(double ph, double &s, double &c) { sincospi(2.0 * ph, &s, &c); }
 
-constexpr int STAGE_THREADS = 256;
+// Workgroup size: 8 waves sharing y faces (FP32-storage tiers), 4 independent waves (FP64).
+template <int PREC>
+constexpr int stage_threads() { return PREC == DG_FP64 ? 256 : 64 * YROWS; }
 
 // Waves per SIMD the stage kernel is compiled for (register budget 512 / this):
 // two for the FP32-storage tiers, one for FP64, whose doubles need the full file.
@@ -426,7 +428,7 @@ __device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff)
 }
 
 template <int K, int PREC, bool FORCE>
-__global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
+__global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
     using PR = typename SC::PR;
     using C = typename PR::C;
@@ -436,13 +438,18 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     constexpr int N = SC::N, Q = SC::Q, P = SC::P;
     constexpr int KPL = SC::KPL, KPL2 = SC::KPL2, KSTEP = SC::KSTEP, KS1 = SC::KS1;
     constexpr int RT1 = SC::RT1, RT2 = SC::RT2;
+    constexpr int SPL = mode_slots(N);               // mode slots per lane group
+    constexpr int THREADS = stage_threads<PREC>();
+    constexpr bool YSH = PREC != DG_FP64;             // workgroup rows share y faces through LDS
+    static_assert(KPL == 1 ? KS1 == SPL : (KS1 == 1 && SPL <= KPL), "mode slots must fit the B operands");
+    static_assert(4 * RT2 >= SPL, "mode slots must fit the result rows");
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
         const int bytes = SC::SET * SC::NTAB + (FORCE ? SC::F6SET * SC::NTAB : 0);
         const int4 *src = reinterpret_cast<const int4 *>(a.tables);
         int4 *dst = reinterpret_cast<int4 *>(lds);
-        for (int j = threadIdx.x; j < bytes / 16; j += STAGE_THREADS) dst[j] = src[j];
+        for (int j = threadIdx.x; j < bytes / 16; j += THREADS) dst[j] = src[j];
         __syncthreads();
     }
     const int lane = threadIdx.x & 63;
@@ -466,9 +473,10 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
     // ---------------- building blocks
-    // Per-lane byte offsets of the rows this lane feeds to the B operand
-    // (mode m = s*KSTEP + g*KPL + j; rows past the last mode are clamped to it,
-    // their table entries are zero, and so are mode 0's: the mean enters apart).
+    // Per-lane byte offsets of the rows this lane feeds to the B operand: the
+    // modes of its slots (slot_mode); unused slots are clamped to the last mode
+    // and meet zero table entries, as does mode 0 (the mean enters apart).
+    // The same rows are the ones this lane's results belong to.
     unsigned boff[KS1][KPL];
     unsigned xoff = 0;
     const unsigned esz = (unsigned)sizeof(S);
@@ -479,7 +487,7 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         for (int s = 0; s < KS1; s++)
 #pragma unroll
             for (int j = 0; j < KPL; j++) {
-                const int m = s * KSTEP + g * KPL + j;
+                const int m = KPL == 1 ? slot_mode(N, g, s) : slot_mode(N, g, j);
                 boff[s][j] = (unsigned)(m < N ? m : N - 1) * nxu * esz + xoff;
             }
     };
@@ -742,19 +750,45 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
         }
     };
 
-    // ---------------- work items: (x-block, y row, z chunk), x-block fastest
+    // y-face exchange in LDS (after the tables): a trace region and a flux region of one slot per
+    // wave (5 x 4 values per lane).  When the two regions do not both fit, they coincide and two
+    // more barriers order the reuse (a.ex_single).
+    C *ex_t = reinterpret_cast<C *>(lds + a.ex_off);
+    C *ex_f = reinterpret_cast<C *>(lds + a.ex_off2);
+    auto ex_put = [&](C *ex, int slot, const C v[NF][4]) {
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) ex[((slot * NF + i) * 4 + r) * 64 + lane] = v[i][r];
+    };
+    auto ex_get = [&](const C *ex, int slot, C v[NF][4]) {
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) v[i][r] = ex[((slot * NF + i) * 4 + r) * 64 + lane];
+    };
+
+    // ---------------- work items: (x-block, y row or group of YROWS rows, z chunk), x-block fastest.
+    // YSH: one item per workgroup, wave w takes row iy0 + w; otherwise one item per wave.
+    constexpr int ROWS = YSH ? YROWS : 1;
+    constexpr int IPW = YSH ? 1 : THREADS / 64;  // items a workgroup holds at once
+    const int nyg = (ny + ROWS - 1) / ROWS;
     const int nxcd = gridDim.x < 8 ? (int)gridDim.x : 8;
     const int xcd = blockIdx.x % nxcd;
     const int wgs_x = (gridDim.x - xcd + nxcd - 1) / nxcd;
-    const long long wid = (long long)(blockIdx.x / nxcd) * (STAGE_THREADS / 64) + wave;
-    const long long wcount = (long long)wgs_x * (STAGE_THREADS / 64);
+    const long long wid = (long long)(blockIdx.x / nxcd) * IPW + (YSH ? 0 : wave);
+    const long long wcount = (long long)wgs_x * IPW;
     const long long i_lo = a.nitems * xcd / nxcd, i_hi = a.nitems * (xcd + 1) / nxcd;
 
     for (long long item = i_lo + wid; item < i_hi; item += wcount) {
         const int bx = (int)(item % a.nbx);
         const long long rest = item / a.nbx;
-        const int iy = (int)(rest % ny);
-        const int zc = (int)(rest / ny);
+        const int iy0 = (int)(rest % nyg) * ROWS;
+        const int zc = (int)(rest / nyg);
+        const int nact = ny - iy0 < ROWS ? ny - iy0 : ROWS;  // rows of this item (the last group may be short)
+        const int wrow = YSH ? wave : 0;
+        const bool act = wrow < nact;                          // inactive waves compute a valid row, store nothing
+        const int iy = act ? iy0 + wrow : iy0;
         const int z0 = zc * a.zlen;
         const int z1 = z0 + a.zlen < nz ? z0 + a.zlen : nz;
         const int xraw = BLK_INNER * bx - 1 + col;  // -1 .. : periodic wrap
@@ -815,7 +849,54 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
                     for (int r = 0; r < 4; r++) Fh[i][r] = dpp_shl1(Fh[i][r]);
                 lift(1, cur, Fh, acc);
             }
-            {  // y faces: neighbour rows' traces from their weights
+            if constexpr (YSH) {
+                // y faces shared by the rows of the workgroup: each face flux is solved once, by the
+                // row below it; the faces at the group's ends use the neighbour rows' weights
+                {
+                    C tm[NF][4];
+                    trace(cur, 2, tm);
+                    if (a.ex_single) __syncthreads();  // the previous step's flux reads are done
+                    ex_put(ex_t, wrow, tm);
+                    if (wrow == 0) {
+                        C Fm[NF][4];
+                        {
+                            C tb[NF][4];
+                            {
+                                B nb;
+                                load(cidx(iy0 - 1, z), nb);
+                                trace(nb, 3, tb);
+                            }
+                            riemann(std::integral_constant<int, 1>{}, tb, tm, Fm);
+                        }
+                        lift(2, cur, Fm, acc);
+                    }
+                }
+                __syncthreads();
+                {
+                    C Fp[NF][4];
+                    {
+                        C tp[NF][4], ta[NF][4];
+                        trace(cur, 3, tp);
+                        if (wrow == nact - 1) {
+                            B nb;
+                            load(cidx(iy0 + nact, z), nb);
+                            trace(nb, 2, ta);
+                        } else {
+                            ex_get(ex_t, wrow + 1 < ROWS ? wrow + 1 : wrow, ta);
+                        }
+                        riemann(std::integral_constant<int, 1>{}, tp, ta, Fp);
+                    }
+                    lift(3, cur, Fp, acc);
+                    if (a.ex_single) __syncthreads();  // every trace has been read
+                    ex_put(ex_f, wrow, Fp);
+                }
+                __syncthreads();
+                if (wrow > 0) {
+                    C Fm[NF][4];
+                    ex_get(ex_f, wrow - 1, Fm);
+                    lift(2, cur, Fm, acc);
+                }
+            } else {  // y faces: neighbour rows' traces from their weights
                 C Fh[NF][4];
                 {
                     C tn[NF][4];
@@ -849,19 +930,19 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
                 riemann(std::integral_constant<int, 2>{}, tp, tm, Fz);
                 lift(5, cur, Fz, acc);
             }
-            // combine and store the interior columns
-            if (keep) {
+            // combine and store the interior columns; result slot s = 4 rt + r is mode slot_mode(N, g, s),
+            // the mode this lane loaded in slot s, so the FP32/FP64 stage input is still in registers
+            if (keep && act) {
                 const long long rz = cidx(iy, z);
                 const auto ro = slab_rsrc(out, slabn, rz);
                 const auto ri = slab_rsrc(yin, slabn, rz);
                 const auto r0 = slab_rsrc(y0, slabn, rz);
 #pragma unroll
-                for (int rt = 0; rt < RT2; rt++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int m = 16 * rt + PR::orow(g, r);
-                        if (m < N) {
-                            const unsigned e = (unsigned)m * nxu * esz + xoff;
+                for (int sl = 0; sl < SPL; sl++) {
+                    const int rt = sl / 4, r = sl % 4;
+                    const int m = slot_mode(N, g, sl);
+                    if (m < N) {
+                            const unsigned e = KPL == 1 ? boff[sl][0] : boff[0][sl];
 #pragma unroll
                             for (int i = 0; i < NF; i++) {
                                 const unsigned so = (unsigned)i * fbytes;
@@ -873,7 +954,11 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
                                 if (a.mode == 0) {
                                     bstore((S)R, ro, e + so);
                                 } else {
-                                    const C yv = (C)bload(S(), ri, e, so);
+                                    C yv;
+                                    if constexpr (KPL == 1)
+                                        yv = m == 0 ? cur.qbar[i] : (C)cur.w[i][sl].v;
+                                    else
+                                        yv = (C)bload(S(), ri, e, so);
                                     const C base = (C)a.b * (yv - dt * R);
                                     const C res = a.a != 0.0 ? (C)a.a * (C)bload(S(), r0, e, so) + base : base;
                                     bstore((S)res, ro, e + so);
@@ -889,10 +974,11 @@ __global__ __launch_bounds__(STAGE_THREADS) __attribute__((amdgpu_waves_per_eu(s
 
 template <int K, int PREC>
 static hipError_t launch_stage_t(const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
+    constexpr int T = stage_threads<PREC>();
     if (a.forcing)
-        hipLaunchKernelGGL((stage_kernel<K, PREC, true>), dim3(grid), dim3(STAGE_THREADS), lds_bytes, s, a);
+        hipLaunchKernelGGL((stage_kernel<K, PREC, true>), dim3(grid), dim3(T), lds_bytes, s, a);
     else
-        hipLaunchKernelGGL((stage_kernel<K, PREC, false>), dim3(grid), dim3(STAGE_THREADS), lds_bytes, s, a);
+        hipLaunchKernelGGL((stage_kernel<K, PREC, false>), dim3(grid), dim3(T), lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -924,11 +1010,10 @@ hipError_t set_stage_attributes(int k, int prec, int lds_bytes) {
     DG_DISPATCH(k, prec, set_attr_t, (lds_bytes))
 }
 
-int stage_block_threads() { return STAGE_THREADS; }
-
 template <int K, int PREC>
 static hipError_t occ_t(int lds_bytes, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC, true>, STAGE_THREADS, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC, true>, stage_threads<PREC>(),
+                                                        lds_bytes);
 }
 
 }  // namespace dgmi
