@@ -205,10 +205,13 @@ dg_status dg_mlp_forward(const int32_t shape[4], const float *params, int32_t ba
 /* Mean-squared error over the batch and the outputs, and its gradient:
  * loss = mean_{s,j} (y_sj - target[rows[s]][j])^2; grad (DEVICE, params
  * layout) = d loss / d params, summed over the batch in a fixed order.
- * loss: DEVICE double, or NULL. */
+ * noise_std > 0 adds noise_std * N(0,1) to every input of the batch (input
+ * noise for robustness), drawn from a counter-based generator keyed by seed
+ * and the element's position in the batch, so a (seed, rows) pair always
+ * draws the same noise.  loss: DEVICE double, or NULL. */
 dg_status dg_mlp_loss_grad(const int32_t shape[4], const float *params, int32_t batch, const float *x,
-                           const float *target, const int32_t *rows, float *grad, double *loss, void *work,
-                           void *hip_stream);
+                           const float *target, const int32_t *rows, float noise_std, uint64_t seed, float *grad,
+                           double *loss, void *work, void *hip_stream);
 
 /* One Adam step (Kingma and Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  All DEVICE

@@ -27,7 +27,8 @@ class Config:
     """Workload of the closure experiment (defaults: k=2 128^3 -> k=1 64^3)."""
 
     def __init__(self, nc=64, mach=0.3, ic_seed=9079, forcing=True, precision="fp32", t_spin=0.05, dt_snap=0.02,
-                 nsnap=16, t_gap=0.1, horizon=0.2, batch=4096, iters=3000, lr=1e-3, init_seed=4, batch_seed=17):
+                 nsnap=16, t_gap=0.1, horizon=0.1, batch=4096, iters=3000, lr=1e-3, init_seed=4, batch_seed=17,
+                 noise=0.1, noise_seed=29, alphas=(1.0, 0.5, 0.25)):
         self.nc = nc
         self.nf = 2 * nc
         self.mach = mach
@@ -37,13 +38,16 @@ class Config:
         self.t_spin = t_spin       # time run before the first training snapshot
         self.dt_snap = dt_snap     # time between snapshots
         self.nsnap = nsnap         # training snapshots
-        self.t_gap = t_gap         # time between the last training snapshot and the held-out start
+        self.t_gap = t_gap         # time before each held-out window
         self.horizon = horizon     # length of the held-out comparison runs
         self.batch = batch
         self.iters = iters
         self.lr = lr
         self.init_seed = init_seed
         self.batch_seed = batch_seed
+        self.noise = noise         # std of the input noise during training (standardised units)
+        self.noise_seed = noise_seed
+        self.alphas = alphas       # correction scales tried on the validation window
 
 
 def driving(a0=0.03, seed=1602):
@@ -145,7 +149,8 @@ class Experiment:
                 pos = 0
             rows = torch.from_numpy(perm[pos:pos + cfg.batch].astype(np.int32)).to("cuda", non_blocking=True)
             pos += cfg.batch
-            net.loss_grad(params, self.X, self.T, rows=rows, grad=grad, loss=loss)
+            net.loss_grad(params, self.X, self.T, rows=rows, grad=grad, loss=loss, noise=cfg.noise,
+                          seed=cfg.noise_seed * 1000003 + it)
             net.adam(params, grad, m, v, it, lr=cfg.lr)
             if it == 1 or it % 250 == 0 or it == cfg.iters:
                 hist.append((it, float(loss.item())))
@@ -155,57 +160,61 @@ class Experiment:
         self.loss_history = hist
         self.log(f"[closure] trained {cfg.iters} Adam steps in {time.perf_counter() - t0:.1f} s, "
                  f"loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
-        self.coarse_cl.set_closure(params.cpu().numpy(), **self.norm)
         return hist
 
+    def install(self, alpha):
+        """The trained network with its correction scaled by alpha."""
+        n = dict(self.norm)
+        n["out_scale"] = n["out_scale"] * alpha
+        self.coarse_cl.set_closure(self.params.cpu().numpy(), **n)
+
     # ------------------------------------------------------------ evaluation
-    def evaluate(self):
-        """Held-out comparison: start both coarse runs from P y_f(t0) at a later
-        time, run for the horizon, compare with P y_f(t0 + horizon)."""
-        torch = self.torch
+    def window(self, alphas):
+        """A held-out window at a later time: both coarse runs start from P y_f(t0)
+        and run for the horizon; the errors are relative to P y_f(t0 + horizon).
+        Returns the a-priori operator errors and, per correction scale, the error
+        of the evolution (y(T) - y(0) against the restricted fine evolution)."""
         cfg = self.cfg
+        c, cl = self.coarse, self.coarse_cl
         self.t = _advance(self.fine, self.yf, cfg.t_gap, self.t)
-        c = self.coarse
-        # instantaneous: how much of the coarse operator's error the closure removes
-        fx, tx = self.sample()
-        yc0 = c.restrict(2, self.yf)
-        rf = self.fine.rhs(self.yf)
-        prf = c.restrict(2, rf)
-        r_plain = c.rhs(yc0)
-        r_clos = self.coarse_cl.rhs(yc0)
-        self.coarse_cl.closure_fallbacks()
-        e_rhs_plain = _rel_l2(r_plain, prf)
-        e_rhs_clos = _rel_l2(r_clos, prf)
-        # integrated over the horizon
-        y_plain = yc0.clone()
-        y_clos = yc0.clone()
         t0 = self.t
-        h = min(c.dt(y_plain), self.coarse_cl.dt(y_clos))
-        n = max(1, int(math.ceil(cfg.horizon / h)))
-        c.step(y_plain, n, cfg.horizon / n)
-        self.coarse_cl.closure_fallbacks()
-        self.coarse_cl.step(y_clos, n, cfg.horizon / n)
-        fb = self.coarse_cl.closure_fallbacks()
+        yc0 = c.restrict(2, self.yf)
+        prf = c.restrict(2, self.fine.rhs(self.yf))
         self.t = _advance(self.fine, self.yf, cfg.horizon, self.t)
         ref = c.restrict(2, self.yf)
-        e_plain = _rel_l2(y_plain, ref)
-        e_clos = _rel_l2(y_clos, ref)
-        # the deviation from the start isolates the evolution the schemes must capture
         d_ref = ref - yc0
-        e_plain_dev = _rel_l2(y_plain - yc0, d_ref)
-        e_clos_dev = _rel_l2(y_clos - yc0, d_ref)
-        ncells = cfg.nc ** 3
-        out = dict(t0=t0, horizon=cfg.horizon, coarse_steps=n,
-                   rhs_err_plain=e_rhs_plain.tolist(), rhs_err_closure=e_rhs_clos.tolist(),
-                   err_plain=e_plain.tolist(), err_closure=e_clos.tolist(),
-                   dev_err_plain=e_plain_dev.tolist(), dev_err_closure=e_clos_dev.tolist(),
-                   fallback_rate=fb / float(ncells * 3 * n),
-                   totals_plain=c.totals(y_plain).tolist(), totals_closure=c.totals(y_clos).tolist(),
-                   totals_start=c.totals(yc0).tolist())
-        self.log(f"[closure] held-out RHS error plain {np.round(e_rhs_plain, 4)} closure {np.round(e_rhs_clos, 4)}")
-        self.log(f"[closure] after {cfg.horizon} ({n} steps): evolution error plain {np.round(e_plain_dev, 4)} "
-                 f"closure {np.round(e_clos_dev, 4)}; fallback rate {out['fallback_rate']:.2e}")
+        h = c.dt(yc0)
+        n = max(1, int(math.ceil(cfg.horizon / h)))
+        out = dict(t0=t0, horizon=cfg.horizon, coarse_steps=n)
+        y = yc0.clone()
+        c.step(y, n, cfg.horizon / n)
+        out["plain"] = dict(rhs_err=_rel_l2(c.rhs(yc0), prf).tolist(), err=_rel_l2(y - yc0, d_ref).tolist())
+        for a in alphas:
+            self.install(a)
+            cl.closure_fallbacks()
+            r = _rel_l2(cl.rhs(yc0), prf).tolist()
+            cl.closure_fallbacks()
+            y = yc0.clone()
+            cl.step(y, n, cfg.horizon / n)
+            fb = cl.closure_fallbacks()
+            out[f"alpha={a}"] = dict(alpha=a, rhs_err=r, err=_rel_l2(y - yc0, d_ref).tolist(),
+                                     fallback_rate=fb / float(cfg.nc ** 3 * 3 * n),
+                                     totals_drift=(np.abs(c.totals(y) - c.totals(yc0))).tolist())
         return out
+
+    def evaluate(self):
+        """Choose the correction scale on a validation window, then compare with
+        the plain scheme on a later test window."""
+        val = self.window(self.cfg.alphas)
+        best = min(self.cfg.alphas, key=lambda a: float(np.mean(val[f"alpha={a}"]["err"])))
+        test = self.window([best])
+        res = dict(validation=val, alpha=best, test=test)
+        p, cl = test["plain"], test[f"alpha={best}"]
+        self.log(f"[closure] alpha={best}; test window t0={test['t0']:.3f}, {test['coarse_steps']} steps")
+        self.log(f"[closure] operator error plain {np.round(p['rhs_err'], 3)} closure {np.round(cl['rhs_err'], 3)}")
+        self.log(f"[closure] evolution error plain {np.round(p['err'], 3)} closure {np.round(cl['err'], 3)}; "
+                 f"fallback rate {cl['fallback_rate']:.2e}")
+        return res
 
 
 def _rel_l2(a, b):

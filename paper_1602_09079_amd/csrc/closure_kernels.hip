@@ -366,19 +366,36 @@ hipError_t launch_rowsum(const float *X, int M, int N, float *out, hipStream_t s
     return hipGetLastError();
 }
 
-// Xb[k][s] = X[rows[s]][k] (feature-major batch), rows == nullptr: row s
-__global__ void gather_kernel(const float *X, int cols, const int *rows, int batch, float *Xb) {
+// Counter-based standard normal draw for element `idx` of stream `seed`: the
+// SplitMix64 output function (Steele, Lea and Flood, 2014) of the counter gives
+// two 32-bit uniforms, the Box-Muller transform a normal deviate.
+__device__ inline float normal_draw(unsigned long long seed, unsigned long long idx) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (idx + 1ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float u1 = ((float)(unsigned)(z >> 40) + 1.0f) * (1.0f / 16777216.0f);  // (0, 1]
+    const float u2 = (float)(unsigned)(z & 0xffffffull) * (1.0f / 16777216.0f);   // [0, 1)
+    return sqrtf(-2.0f * logf(u1)) * __builtin_amdgcn_cosf(u2);  // cos(2 pi u2): argument in revolutions
+}
+
+// Xb[k][s] = X[rows[s]][k] (+ noise * N(0,1)) (feature-major batch), rows == nullptr: row s
+__global__ void gather_kernel(const float *X, int cols, const int *rows, int batch, float *Xb, float noise,
+                              unsigned long long seed) {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long long)cols * batch) return;
     const int s = (int)(id % batch);
     const int k = (int)(id / batch);
     const long long r = rows ? rows[s] : s;
-    Xb[id] = X[r * cols + k];
+    float v = X[r * cols + k];
+    if (noise != 0.0f) v += noise * normal_draw(seed, (unsigned long long)id);
+    Xb[id] = v;
 }
 
-hipError_t launch_gather(const float *X, int cols, const int *rows, int batch, float *Xb, hipStream_t s) {
+hipError_t launch_gather(const float *X, int cols, const int *rows, int batch, float *Xb, hipStream_t s, float noise,
+                         unsigned long long seed) {
     const long long n = (long long)cols * batch;
-    hipLaunchKernelGGL(gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, X, cols, rows, batch, Xb);
+    hipLaunchKernelGGL(gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, X, cols, rows, batch, Xb, noise, seed);
     return hipGetLastError();
 }
 

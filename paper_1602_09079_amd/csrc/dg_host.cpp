@@ -940,9 +940,10 @@ dg_status dg_mlp_forward(const int32_t shape[4], const float *params, int32_t ba
 }
 
 dg_status dg_mlp_loss_grad(const int32_t shape[4], const float *params, int32_t batch, const float *x,
-                           const float *target, const int32_t *rows, float *grad, double *loss, void *work,
-                           void *hip_stream) {
-    if (!mlp_shape_ok(shape) || batch < 1 || !params || !x || !target || !grad || !work) return DG_ERR_ARG;
+                           const float *target, const int32_t *rows, float noise_std, uint64_t seed, float *grad,
+                           double *loss, void *work, void *hip_stream) {
+    if (!mlp_shape_ok(shape) || batch < 1 || !params || !x || !target || !grad || !work || !(noise_std >= 0.0f))
+        return DG_ERR_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int nin = shape[0], h1 = shape[1], h2 = shape[2], no = shape[3], B = batch;
     const MlpWork w = carve(shape, B, work);
@@ -950,7 +951,8 @@ dg_status dg_mlp_loss_grad(const int32_t shape[4], const float *params, int32_t 
     float *gW1 = grad, *gb1 = gW1 + (size_t)h1 * nin, *gW2 = gb1 + h1, *gb2 = gW2 + (size_t)h2 * h1;
     float *gW3 = gb2 + h2, *gb3 = gW3 + (size_t)no * h2;
     auto ok = [](hipError_t e) { return e == hipSuccess; };
-    if (!ok(launch_gather(x, nin, rows, B, w.Xb, s)) || !ok(launch_gather(target, no, rows, B, w.Tb, s)) ||
+    if (!ok(launch_gather(x, nin, rows, B, w.Xb, s, noise_std, (unsigned long long)seed)) ||
+        !ok(launch_gather(target, no, rows, B, w.Tb, s)) ||
         !ok(mlp_fwd(shape, params, B, w, s)) || !ok(launch_mse(w.Y, w.Tb, w.dY, (long long)no * B, loss, s)))
         return DG_ERR_HIP;
     // weight gradients: gW = D A^T (contraction over the batch); bias gradients: row sums of D

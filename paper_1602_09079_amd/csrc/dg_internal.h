@@ -155,7 +155,8 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
 hipError_t launch_rowsum(const float *X, int M, int N, float *out, hipStream_t s);
-hipError_t launch_gather(const float *X, int cols, const int *rows, int batch, float *Xb, hipStream_t s);
+hipError_t launch_gather(const float *X, int cols, const int *rows, int batch, float *Xb, hipStream_t s,
+                         float noise = 0.0f, unsigned long long seed = 0);
 hipError_t launch_mse(const float *Y, const float *T, float *dY, long long n, double *loss, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, int step, double lr, double b1,
                        double b2, double eps, hipStream_t s);

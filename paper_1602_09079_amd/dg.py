@@ -77,7 +77,8 @@ def lib():
             "dg_mlp_nparams": (ctypes.c_size_t, [_ip]),
             "dg_mlp_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int32]),
             "dg_mlp_forward": (ctypes.c_int, [_ip, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]),
-            "dg_mlp_loss_grad": (ctypes.c_int, [_ip, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "dg_mlp_loss_grad": (ctypes.c_int, [_ip, _vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_float,
+                                                ctypes.c_uint64, _vp, _vp, _vp, _vp]),
             "dg_adam": (ctypes.c_int, [ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
             "dg_column_stats_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
@@ -347,8 +348,9 @@ class MLP:
             raise DGError(st, "dg_mlp_forward")
         return y
 
-    def loss_grad(self, params, x, target, rows=None, grad=None, loss=None, batch=None):
-        """Returns (grad, loss) device tensors; loss is a float64 scalar tensor."""
+    def loss_grad(self, params, x, target, rows=None, grad=None, loss=None, batch=None, noise=0.0, seed=0):
+        """Returns (grad, loss) device tensors; loss is a float64 scalar tensor.  noise > 0 perturbs
+        the batch inputs with noise * N(0,1) drawn from the counter-based generator keyed by seed."""
         import torch
         B = batch or (len(rows) if rows is not None else x.shape[0])
         if B > self.batch:
@@ -357,7 +359,8 @@ class MLP:
         lo = torch.empty((), dtype=torch.float64, device="cuda") if loss is None else loss
         rp = _vp(rows.data_ptr()) if rows is not None else _vp()
         st = lib().dg_mlp_loss_grad(_shape_arr(self.shape), _f32ptr(params), B, _f32ptr(x), _f32ptr(target), rp,
-                                    _f32ptr(g), _vp(lo.data_ptr()), _vp(self.work.data_ptr()), self._s())
+                                    noise, seed, _f32ptr(g), _vp(lo.data_ptr()), _vp(self.work.data_ptr()),
+                                    self._s())
         if st != DG_OK:
             raise DGError(st, "dg_mlp_loss_grad")
         return g, lo

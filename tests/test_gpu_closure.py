@@ -253,3 +253,19 @@ def test_column_stats_and_standardize(dgm):
     m, s, _, _ = dgm.column_stats(xd)
     dgm.standardize(xd, m, s)
     np.testing.assert_allclose(xd.cpu().numpy(), (xx - mean) / std, rtol=1e-5, atol=1e-5)
+
+
+def test_training_noise_is_seeded(dgm):
+    rng = np.random.default_rng(14)
+    p = dev(synth.xavier_params(SHAPE, seed=4))
+    x = dev(rng.standard_normal((512, 140)))
+    t = dev(rng.standard_normal((512, 20)))
+    net = dgm.MLP(SHAPE, 512)
+    g0, l0 = net.loss_grad(p, x, t)
+    g1, l1 = net.loss_grad(p, x, t, noise=0.3, seed=5)
+    g1 = g1.clone()
+    l1 = l1.item()
+    g2, l2 = net.loss_grad(p, x, t, noise=0.3, seed=5)
+    g3, l3 = net.loss_grad(p, x, t, noise=0.3, seed=6)
+    assert l1 == l2.item() and torch.equal(g1, g2)
+    assert l1 != l0.item() and l3.item() != l1
