@@ -70,7 +70,7 @@ typedef struct {
     double gamma;       /* adiabatic index, > 1 */
     double cfl;         /* Courant factor C of Sec. 2.4, in (0, 1] */
     int32_t precision;  /* a dg_precision value */
-    uint32_t flags;     /* DG_FORCING | DG_CHECK_RANGE */
+    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE */
 } dg_config;
 
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
@@ -131,7 +131,11 @@ dg_status dg_totals(dg_ctx *ctx, const void *y, double out[5]);
 /* Driving acceleration of Sec. 3.1 as a Fourier sum:
  *   a_c(x) = sum_m Re( ahat[m][c] * exp(2 pi i sum_a nvec[m][a] x_a / box[a]) ).
  * nvec: HOST [nmodes][3]; ahat: HOST [nmodes][3][2] (re, im); copied.
- * 0 <= nmodes <= 256.  Takes effect for the calls enqueued after it. */
+ * 0 <= nmodes <= 256.  The field is constant until the next call (the driving
+ * is piecewise constant in time), so it is evaluated here once, in FP64, at
+ * every volume Gauss point of every cell, and cached on the device in the
+ * storage type (3 (k+1)^3 values per cell; the first call allocates the
+ * cache).  The stages read the cache.  Synchronises. */
 dg_status dg_set_forcing(dg_ctx *ctx, int32_t nmodes, const int32_t *nvec, const double *ahat);
 
 /* Host-only helper (no ctx, no device): one Ornstein-Uhlenbeck update of the

@@ -287,63 +287,6 @@ TableLayout make_layout(int k, int prec) {
     return L;
 }
 
-// Slot (K-step st, lane group g, value j) of the forcing product holds the real
-// (part 0) or imaginary (part 1) part of mode m; both parts of a mode sit in one lane.
-static void forcing_slot(const TableLayout &L, int st, int g, int j, int &m, int &part) {
-    if (L.kpl == 8) {
-        m = 16 * st + 4 * g + (j >> 1);
-        part = j & 1;
-    } else {
-        m = 4 * (st >> 1) + g;
-        part = st & 1;
-    }
-}
-
-size_t forcing_table_bytes(const TableLayout &L) {
-    const int ksf = forcing_slots(L.prec) / L.kstep;
-    return (size_t)L.rt1 * ksf * L.fb1 * L.ntab;
-}
-
-// A operand of the forcing product: [volume point q][slot] = cos(theta_m(dq)) for
-// part 0 and -sin(theta_m(dq)) for part 1, where dq is the offset of point q from
-// the cell centre and theta_m(d) = 2 pi sum_a n_a d_a / box_a = pi sum_a n_a xi_a / n_a.
-std::vector<char> build_forcing_table(const TableLayout &L, const int n[3], int nmodes, const int32_t *nvec) {
-    const Basis B(L.k);
-    const int ksf = forcing_slots(L.prec) / L.kstep;
-    const size_t set = (size_t)L.rt1 * ksf * L.fb1;
-    std::vector<double> v((size_t)L.rt1 * ksf * 64 * L.kpl, 0.0);
-    double xi[3];
-    for (int t = 0; t < L.rt1; t++)
-        for (int st = 0; st < ksf; st++)
-            for (int lane = 0; lane < 64; lane++)
-                for (int j = 0; j < L.kpl; j++) {
-                    const int q = 16 * t + lane % 16;
-                    int m, part;
-                    forcing_slot(L, st, lane / 16, j, m, part);
-                    if (q >= L.Q || m >= nmodes) continue;
-                    B.point(q, xi);
-                    double th = 0.0;
-                    for (int a = 0; a < 3; a++) th += M_PI * nvec[3 * m + a] * xi[a] / n[a];
-                    v[(((size_t)t * ksf + st) * 64 + lane) * L.kpl + j] = part ? -std::sin(th) : std::cos(th);
-                }
-    std::vector<char> blob(set * L.ntab, 0);
-    if (L.prec == DG_FP64) {
-        std::memcpy(blob.data(), v.data(), v.size() * 8);
-    } else if (L.prec == DG_FP32) {
-        float *o = reinterpret_cast<float *>(blob.data());
-        for (size_t i = 0; i < v.size(); i++) o[i] = (float)v[i];
-    } else {
-        uint16_t *hi = reinterpret_cast<uint16_t *>(blob.data());
-        uint16_t *lo = reinterpret_cast<uint16_t *>(blob.data() + set);
-        for (size_t i = 0; i < v.size(); i++) {
-            const uint16_t h = bf16_rne((float)v[i]);
-            hi[i] = h;
-            if (L.ntab == 2) lo[i] = bf16_rne((float)(v[i] - (double)bf16_to_float(h)));
-        }
-    }
-    return blob;
-}
-
 }  // namespace dgmi
 
 hipError_t stage_occupancy(int k, int prec, int lds_bytes, int *blocks_per_cu);
@@ -403,11 +346,8 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         return st;
     };
     const std::vector<char> blob = build_tables(c->lay, s);
-    c->f6_bytes = (cfg->flags & DG_FORCING) ? forcing_table_bytes(c->lay) : 0;
-    if (hipMalloc(&c->tables, blob.size() + c->f6_bytes) != hipSuccess) return fail(DG_ERR_HIP);
+    if (hipMalloc(&c->tables, blob.size()) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMemcpy(c->tables, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
-    if (c->f6_bytes && hipMemset(static_cast<char *>(c->tables) + blob.size(), 0, c->f6_bytes) != hipSuccess)
-        return fail(DG_ERR_HIP);
     // projection table: phi_l(xi_q) w_q / 8
     {
         const Basis B(cfg->k);
@@ -432,7 +372,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             return fail(DG_ERR_HIP);
         // separate y-face trace and flux regions when both fit, else one shared region
         const int exb = (int)stage_exchange_bytes(cfg->precision);
-        c->ex_off = (int)(c->lay.bytes() + c->f6_bytes);
+        c->ex_off = (int)c->lay.bytes();
         c->ex_off2 = c->ex_off + exb;
         c->lds = c->ex_off + 2 * exb;
         if (c->lds > maxlds) {
@@ -472,6 +412,7 @@ dg_status dg_destroy(dg_ctx *c) {
     if (c->flag) hipFree(c->flag);
     if (c->partials) hipFree(c->partials);
     if (c->fmodes) hipFree(c->fmodes);
+    if (c->acache) hipFree(c->acache);
     if (c->clo) hipFree(c->clo);
     if (c->corr) hipFree(c->corr);
     if (c->clo_partials) hipFree(c->clo_partials);
@@ -558,8 +499,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;
-    s.fmodes = c->fmodes;
-    s.nfmodes = c->nfmodes;
+    s.acache = c->acache;
     for (int i = 0; i < 3; i++) s.h[i] = c->h[i];
     HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
     return DG_OK;
@@ -678,26 +618,26 @@ dg_status dg_set_forcing(dg_ctx *c, int32_t nmodes, const int32_t *nvec, const d
         c->err = "dg_set_forcing: bad mode count or NULL table";
         return DG_ERR_ARG;
     }
-    const int kf2 = forcing_slots(c->cfg.precision) / 2;
-    if (nmodes > kf2) {
-        c->err = "dg_set_forcing: at most " + std::to_string(kf2) + " modes in this precision";
-        return DG_ERR_UNSUPPORTED;
-    }
     if (!(c->cfg.flags & DG_FORCING)) {
         c->err = "dg_set_forcing: context was created without DG_FORCING";
         return DG_ERR_STATE;
     }
     // device mode table per mode: n_x, n_y, n_z (as doubles), then Re/Im of the three components
-    std::vector<double> t((size_t)kf2 * 9, 0.0);
+    std::vector<double> t((size_t)MAX_FORCING_MODES * 9, 0.0);
     for (int m = 0; m < nmodes; m++) {
         for (int a = 0; a < 3; a++) t[9 * m + a] = (double)nvec[3 * m + a];
         for (int j = 0; j < 6; j++) t[9 * m + 3 + j] = ahat[6 * m + j];
     }
     if (!c->fmodes) HIPCHK(c, hipMalloc(&c->fmodes, t.size() * sizeof(double)));
-    const std::vector<char> f6 = build_forcing_table(c->lay, c->cfg.n, nmodes, nvec);
+    if (!c->acache)
+        HIPCHK(c, hipMalloc(&c->acache, (size_t)accel_slab_elems(c->cfg.k, c->cfg.n[0]) * c->cfg.n[1] * c->cfg.n[2] *
+                                            elem_bytes(c)));
     HIPCHK(c, hipMemcpyAsync(c->fmodes, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(static_cast<char *>(c->tables) + c->lay.bytes(), f6.data(), f6.size(),
-                             hipMemcpyHostToDevice, c->stream));
+    GaussNodes xg{};
+    double wg[5];
+    gauss_rule(c->n, xg.x, wg);
+    HIPCHK(c, launch_accel_cache(c->cfg.k, c->cfg.precision, c->fmodes, nmodes, c->cfg.n[0], c->cfg.n[1], c->cfg.n[2],
+                                 c->ncells, xg, c->acache, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->nfmodes = nmodes;
     c->have_forcing = true;

@@ -17,9 +17,6 @@ constexpr int BLK = 16;        // cells per MFMA column tile (one x-run)
 constexpr int BLK_INNER = 14;  // cells of a block whose result is kept; columns 0 and 15 are x-halo
 constexpr int MAX_FORCING_MODES = 256;  // accepted by dg_set_forcing
 
-// The driving acceleration at the volume points is one more MFMA product over
-// KF contraction slots (the real and imaginary parts of KF/2 Fourier modes).
-inline int forcing_slots(int prec) { return (prec == DG_BF16 || prec == DG_BF16X3) ? 96 : 88; }
 
 inline int nmodes_of(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 
@@ -70,8 +67,16 @@ struct TableLayout {
 };
 
 TableLayout make_layout(int k, int prec);
-size_t forcing_table_bytes(const TableLayout &L);
-std::vector<char> build_forcing_table(const TableLayout &L, const int n[3], int nmodes, const int32_t *nvec);
+struct GaussNodes {
+    double x[5];
+};
+// elements of the driving acceleration cache per (z, y) row of cells: 3 components x 16 ceil(Q/16) points x nx
+inline long long accel_slab_elems(int k, int nx) {
+    const int Q = (k + 1) * (k + 1) * (k + 1);
+    return (long long)((Q + 15) / 16) * 16 * 3 * nx;
+}
+hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
+                              const GaussNodes &xg, void *out, hipStream_t s);
 
 struct StageArgs {
     const void *yin;
@@ -93,8 +98,7 @@ struct StageArgs {
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
-    const double *fmodes; // device mode table [KF/2][9]: n_x, n_y, n_z, then Re/Im of ahat_x, ahat_y, ahat_z
-    int nfmodes;
+    const void *acache;   // driving acceleration at the volume points (layout of accel_load)
     double h[3];          // cell widths
     const void *corr;     // closure correction c (state layout) or nullptr: R <- R - (c - cmean on mode 0)
     const double *cmean;  // [5] mean of c's mode-0 rows per field
@@ -180,8 +184,8 @@ struct dg_ctx {
     int *flag = nullptr;           // range-check flag
     double *partials = nullptr;    // totals partial sums
     int nparts = 0;
-    double *fmodes = nullptr;      // forcing mode table (zero padded to KF/2 modes)
-    size_t f6_bytes = 0;           // bytes of the forcing point table (after the operator tables)
+    double *fmodes = nullptr;      // forcing mode table [MAX_FORCING_MODES][9]
+    void *acache = nullptr;        // driving acceleration at the volume points (storage type)
     int nfmodes = 0;
     bool have_forcing = false;
     int grid = 0;

@@ -307,11 +307,6 @@ struct StageCfg {
     static constexpr int O5 = O4 + RT2 * NC4 * FB2;
     static constexpr int SET = O5 + RT2 * NC2 * FB2;
     static constexpr int NTAB = PREC == DG_BF16X3 ? 2 : 1;
-    // forcing product: KF slots = real and imaginary parts of KF/2 modes
-    static constexpr int KF = KPL == 8 ? 96 : 88;
-    static constexpr int KSF = KF / KSTEP;
-    static constexpr int O6 = SET * NTAB;           // forcing table after the operator tables
-    static constexpr int F6SET = RT1 * KSF * FB1;   // one (hi or lo) set of it
     static constexpr bool QFULL = (Q % 16) == 0;  // no padded volume rows
     static constexpr bool PFULL = P == 16;        // no padded face rows
 };
@@ -350,36 +345,7 @@ struct TabReader {
     __device__ typename PR::AF t3(int f, int s) const { return wide(SC::O3 + (f * SC::KS1 + s) * SC::FB1); }
     __device__ typename PR::AF2 t4(int rt, int c) const { return narrow(SC::O4 + (rt * SC::NC4 + c) * SC::FB2); }
     __device__ typename PR::AF2 t5(int rt, int c) const { return narrow(SC::O5 + (rt * SC::NC2 + c) * SC::FB2); }
-    __device__ typename PR::AF t6(int t, int st) const {
-        const int byte = SC::O6 + (t * SC::KSF + st) * SC::FB1;
-        if constexpr (PREC == DG_BF16X3)
-            return typename PR::AF{*reinterpret_cast<const bf8 *>(lds + byte + off1),
-                                   *reinterpret_cast<const bf8 *>(lds + SC::F6SET + byte + off1)};
-        else
-            return PR::lda(lds + byte + off1);
-    }
 };
-
-// the mode and part (0 = real, 1 = imaginary) fed at slot (K-step st, lane group
-// g, value j) of the forcing product; both parts of a mode sit in one lane
-template <int KPL>
-__device__ inline void forcing_slot(int st, int g, int j, int &m, int &part) {
-    if constexpr (KPL == 8) {
-        m = 16 * st + 4 * g + (j >> 1);
-        part = j & 1;
-    } else {
-        m = 4 * (st >> 1) + g;
-        part = st & 1;
-    }
-}
-
-// sin and cos of 2 pi ph for ph in [0, 1): the FP32 tiers use the hardware
-// v_sin/v_cos, whose argument is in revolutions; FP64 uses sincospi
-__device__ inline void sincos_2pi(double ph, float &s, float &c) {
-    s = __builtin_amdgcn_sinf((float)ph);
-    c = __builtin_amdgcn_cosf((float)ph);
-}
-__device__ inline void sincos_2pi(double ph, double &s, double &c) { sincospi(2.0 * ph, &s, &c); }
 
 // Workgroup size: 8 waves sharing y faces (FP32-storage tiers), 4 independent waves (FP64).
 template <int PREC>
@@ -427,6 +393,25 @@ __device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
 }
 
+// Acceleration cache: per slab [tile t][component c][lane group g][x][r] holds a_c at volume
+// point 16 t + orow(g, r) of cell x, so a lane reads its 4 values of a tile with one 16-byte load.
+__device__ inline void accel_load(__amdgpu_buffer_rsrc_t r, unsigned off, float v[4]) {
+    // the whole 16-byte vector is reinterpreted at once (casting its elements one by one lets the
+    // compiler narrow the load to one dword)
+    const f4 w = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = w[j];
+}
+__device__ inline void accel_load(__amdgpu_buffer_rsrc_t r, unsigned off, double v[4]) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const dv2 w0 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const dv2 w1 = __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    v[0] = w0[0];
+    v[1] = w0[1];
+    v[2] = w1[0];
+    v[3] = w1[1];
+}
+
 template <int K, int PREC, bool FORCE>
 __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
@@ -446,7 +431,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
-        const int bytes = SC::SET * SC::NTAB + (FORCE ? SC::F6SET * SC::NTAB : 0);
+        const int bytes = SC::SET * SC::NTAB;
         const int4 *src = reinterpret_cast<const int4 *>(a.tables);
         int4 *dst = reinterpret_cast<int4 *>(lds);
         for (int j = threadIdx.x; j < bytes / 16; j += THREADS) dst[j] = src[j];
@@ -469,6 +454,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     S *out = reinterpret_cast<S *>(a.out);
     const long long nc = a.ncells;
     const long long slabn = (long long)NF * N * a.nx;  // elements per (z, y) slab
+    const long long aslab = (long long)RT1 * 16 * 3 * a.nx;  // elements per slab of the acceleration cache
     const unsigned nxu = (unsigned)a.nx;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
 
@@ -575,12 +561,22 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             }
         }
     };
-    // volume integral: GEMM1 -> flux deviation -> GEMM2, one 16-point tile at a time
-    auto volume = [&](const B &b, Acc acc[NF][RT2]) {
+    // volume integral: GEMM1 -> flux deviation -> GEMM2, one 16-point tile at a time; with the
+    // driving (Sec. 3.1) the source S = (0, rho a, m.a) at the same points is projected by GEMM5
+    // (T5 = -phi w / 8), a(x_q) read from the acceleration cache of the row (slab ar)
+    auto volume = [&](const B &b, Acc acc[NF][RT2], __amdgpu_buffer_rsrc_t ar) {
         C Fb[3][5];
         euler_flux3<PR>(b.qbar, g1, Fb);
 #pragma unroll
         for (int t = 0; t < RT1; t++) {
+            C av[3][4];  // this lane's 4 points of the tile: a_c at point 16 t + orow(g, r)
+            if constexpr (FORCE) {
+                // the offset passes an empty asm so the loads are issued here, not hoisted for all tiles
+                unsigned ao = ((t * 3) * 4 + g) * nxu * 4 * esz + xoff * 4;
+                asm volatile("" : "+v"(ao));
+#pragma unroll
+                for (int c = 0; c < 3; c++) accel_load(ar, ao + c * 4 * nxu * 4 * esz, av[c]);
+            }
             Acc d[NF];
 #pragma unroll
             for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
@@ -591,7 +587,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                 for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, b.w[i][s]);
             }
             // primitive quantities at this lane's 4 points of the tile
-            C mx[4], my[4], mz[4], ep[4], vel[3][4], p[4];
+            C mx[4], my[4], mz[4], ep[4], vel[3][4], p[4], rho_pt[4];
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
@@ -599,10 +595,41 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 #pragma unroll
                 for (int i = 0; i < 5; i++) q[i] = valid ? (C)d[i][r] + b.qbar[i] : b.qbar[i];
                 const C inv = PR::rcp(q[0]);
+                rho_pt[r] = q[0];
                 mx[r] = q[1]; my[r] = q[2]; mz[r] = q[3];
                 vel[0][r] = q[1] * inv; vel[1][r] = q[2] * inv; vel[2][r] = q[3] * inv;
                 p[r] = g1 * (q[4] - C(0.5) * (q[1] * vel[0][r] + q[2] * vel[1][r] + q[3] * vel[2][r]));
                 ep[r] = q[4] + p[r];
+            }
+            if constexpr (FORCE) {
+                C Sv[4][4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
+                    const C rho = rho_pt[r];
+                    Sv[0][r] = valid ? rho * av[0][r] : C(0);
+                    Sv[1][r] = valid ? rho * av[1][r] : C(0);
+                    Sv[2][r] = valid ? rho * av[2][r] : C(0);
+                    Sv[3][r] = valid ? mx[r] * av[0][r] + my[r] * av[1][r] + mz[r] * av[2][r] : C(0);
+                }
+                if constexpr (KPL2 == 1) {
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int rt = 0; rt < RT2; rt++) {
+                            const auto A = T.t5(rt, t * 4 + r);
+#pragma unroll
+                            for (int i = 1; i < NF; i++)
+                                acc[i][rt] = PR::mma2(acc[i][rt], A, PR::mkb2(&Sv[i - 1][r]));
+                        }
+                } else {
+#pragma unroll
+                    for (int i = 1; i < NF; i++) {
+                        const auto bf = PR::mkb2(Sv[i - 1]);
+#pragma unroll
+                        for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t5(rt, t), bf);
+                    }
+                }
             }
 #pragma unroll
             for (int al = 0; al < 3; al++) {
@@ -636,115 +663,6 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 #pragma unroll
                         for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t2(rt, al, t), bf);
                     }
-                }
-            }
-        }
-    };
-
-    // driving source of Sec. 3.1: a(x_q) by the forcing product, S = (0, rho a, m.a),
-    // projected with GEMM5 (T5 = -phi w / 8)
-    auto source = [&](const B &b, int ix, int iy, int iz, Acc acc[NF][RT2]) {
-        constexpr int KSF = SC::KSF;
-        Acc af[RT1][3];
-#pragma unroll
-        for (int t = 0; t < RT1; t++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) af[t][c] = Acc{0, 0, 0, 0};
-        const double cx = (ix + 0.5) / nx, cy = (iy + 0.5) / ny, cz = (iz + 0.5) / nz;
-        // G_{m,c} = ahat_{m,c} exp(2 pi i n_m . x_cell / L) for mode m, both parts
-        auto coef = [&](int m, C re[3], C im[3]) {
-            const double *md = a.fmodes + 9 * m;
-            double ph = md[0] * cx + md[1] * cy + md[2] * cz;
-            ph -= __builtin_floor(ph);
-            C sn, cs;
-            sincos_2pi(ph, sn, cs);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const C ar = (C)md[3 + 2 * c], ai = (C)md[4 + 2 * c];
-                re[c] = ar * cs - ai * sn;
-                im[c] = ar * sn + ai * cs;
-            }
-        };
-        auto gemm_f = [&](int st, C gv[3][KPL]) {
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const auto bf = PR::mkb(gv[c]);
-#pragma unroll
-                for (int t = 0; t < RT1; t++) af[t][c] = PR::mma(af[t][c], T.t6(t, st), bf);
-            }
-        };
-        if constexpr (KPL == 8) {
-#pragma unroll
-            for (int st = 0; st < KSF; st++) {
-                C gv[3][KPL];
-#pragma unroll
-                for (int j = 0; j < KPL; j += 2) {
-                    int m, part;
-                    forcing_slot<KPL>(st, g, j, m, part);
-                    C re[3], im[3];
-                    coef(m, re, im);
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        gv[c][j] = re[c];
-                        gv[c][j + 1] = im[c];
-                    }
-                }
-                gemm_f(st, gv);
-            }
-        } else {
-            // K-steps 2u and 2u+1 carry the real and imaginary parts of one mode
-#pragma unroll
-            for (int st = 0; st < KSF; st += 2) {
-                int m, part;
-                forcing_slot<KPL>(st, g, 0, m, part);
-                C re[3], im[3], gv[3][KPL];
-                coef(m, re, im);
-#pragma unroll
-                for (int c = 0; c < 3; c++) gv[c][0] = re[c];
-                gemm_f(st, gv);
-#pragma unroll
-                for (int c = 0; c < 3; c++) gv[c][0] = im[c];
-                gemm_f(st + 1, gv);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < RT1; t++) {
-            Acc d[NF];
-#pragma unroll
-            for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < KS1; s++) {
-                const auto A = T.t1(t, s);
-#pragma unroll
-                for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, b.w[i][s]);
-            }
-            C Sv[4][4];
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const bool valid = SC::QFULL || 16 * t + PR::orow(g, r) < Q;
-                const C rho = (C)d[0][r] + b.qbar[0];
-                const C ax = (C)af[t][0][r], ay = (C)af[t][1][r], az = (C)af[t][2][r];
-                const C mx = (C)d[1][r] + b.qbar[1], my = (C)d[2][r] + b.qbar[2], mz = (C)d[3][r] + b.qbar[3];
-                Sv[0][r] = valid ? rho * ax : C(0);
-                Sv[1][r] = valid ? rho * ay : C(0);
-                Sv[2][r] = valid ? rho * az : C(0);
-                Sv[3][r] = valid ? mx * ax + my * ay + mz * az : C(0);
-            }
-            if constexpr (KPL2 == 1) {
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-#pragma unroll
-                    for (int rt = 0; rt < RT2; rt++) {
-                        const auto A = T.t5(rt, t * 4 + r);
-#pragma unroll
-                        for (int i = 1; i < NF; i++) acc[i][rt] = PR::mma2(acc[i][rt], A, PR::mkb2(&Sv[i - 1][r]));
-                    }
-            } else {
-#pragma unroll
-                for (int i = 1; i < NF; i++) {
-                    const auto bf = PR::mkb2(Sv[i - 1]);
-#pragma unroll
-                    for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t5(rt, t), bf);
                 }
             }
         }
@@ -821,11 +739,9 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
             lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
-            // the driving source runs before the look-ahead load is in flight (fewer live registers)
-            if constexpr (FORCE) source(cur, xc, iy, z, acc);
             B nxt;
             load(cidx(iy, z + 1), nxt);
-            volume(cur, acc);
+            volume(cur, acc, slab_rsrc(reinterpret_cast<const S *>(a.acache), aslab, cidx(iy, z)));
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
                 C tl[NF][4], Fh[NF][4];
                 {
@@ -1069,6 +985,69 @@ hipError_t launch_project(int k, int prec, const void *qp, void *y, const double
         case 1: return launch_project_k<1>(prec, qp, y, ptab, nc, nx, s);
         case 2: return launch_project_k<2>(prec, qp, y, ptab, nc, nx, s);
         case 3: return launch_project_k<3>(prec, qp, y, ptab, nc, nx, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ driving acceleration cache (Sec. 3.1)
+
+// a_c(x_q) = sum_m Re(ahat_{m,c} exp(2 pi i n_m . x_q / L)) at every volume point of every
+// cell, in the layout the stage kernel reads (see accel_load); the phase is reduced to one
+// turn in FP64 and its sine and cosine taken in FP64.  Rows past the last point are zero.
+template <int K, class S>
+__global__ void accel_cache_kernel(const double *__restrict__ modes, int nmodes, int nx, int ny, int nz, long long nc,
+                                   GaussNodes xg, S *__restrict__ out) {
+    constexpr int n = K + 1, Q = n * n * n, RT1 = (Q + 15) / 16;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nc * RT1 * 16) return;
+    const long long cell = id / (RT1 * 16);
+    const int rho = (int)(id - cell * (RT1 * 16));
+    const int t = rho / 16, rr = rho % 16;
+    constexpr bool F64 = sizeof(S) == 8;
+    const int g = F64 ? rr % 4 : rr / 4, r = F64 ? rr / 4 : rr % 4;  // result lane group and register of the row
+    const int ix = (int)(cell % nx);
+    const long long slab = cell / nx;
+    const int iy = (int)(slab % ny), iz = (int)(slab / ny);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (rho < Q) {
+        const int qa = rho % n, qb = (rho / n) % n, qc = rho / (n * n);
+        const double X = (ix + 0.5 * (1.0 + xg.x[qa])) / nx, Y = (iy + 0.5 * (1.0 + xg.x[qb])) / ny,
+                     Z = (iz + 0.5 * (1.0 + xg.x[qc])) / nz;
+        for (int m = 0; m < nmodes; m++) {
+            const double *md = modes + 9 * m;
+            double ph = md[0] * X + md[1] * Y + md[2] * Z;
+            ph -= floor(ph);
+            double sn, cs;
+            sincospi(2.0 * ph, &sn, &cs);
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[c] += md[3 + 2 * c] * cs - md[4 + 2 * c] * sn;
+        }
+    }
+    const long long aslab = (long long)RT1 * 16 * 3 * nx;
+#pragma unroll
+    for (int c = 0; c < 3; c++) out[slab * aslab + (((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r] = (S)acc[c];
+}
+
+template <int K>
+static hipError_t launch_accel_k(int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
+                                 const GaussNodes &xg, void *out, hipStream_t s) {
+    constexpr int Q = (K + 1) * (K + 1) * (K + 1), RT1 = (Q + 15) / 16;
+    const long long nb = (nc * RT1 * 16 + 255) / 256;
+    if (prec == DG_FP64)
+        hipLaunchKernelGGL((accel_cache_kernel<K, double>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL((accel_cache_kernel<K, float>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
+                           (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
+                              const GaussNodes &xg, void *out, hipStream_t s) {
+    switch (k) {
+        case 1: return launch_accel_k<1>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
+        case 2: return launch_accel_k<2>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
+        case 3: return launch_accel_k<3>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -94,7 +94,7 @@ def test_set_forcing_errors(dgm):
         s.set_forcing(np.zeros((1, 3), dtype=np.int32), np.zeros((1, 3, 2)))  # context without DG_FORCING
     s2 = dgm.Solver(1, 8, precision="fp32", forcing=True)
     with pytest.raises(dgm.DGError):
-        s2.set_forcing(np.ones((45, 3), dtype=np.int32), np.zeros((45, 3, 2)))  # more modes than the table holds
+        s2.set_forcing(np.ones((257, 3), dtype=np.int32), np.zeros((257, 3, 2)))  # more than 256 modes
     y = s2.empty_state().zero_()
     with pytest.raises(dgm.DGError):
         s2.rhs(y)  # DG_FORCING without a table
