@@ -135,7 +135,8 @@ def measure_tier(args, dg, torch, prec, qp_dev, n, k):
     out = dict(prec=prec, ms_per_step=ms_step, wall_s=wall, dof_updates_per_s=rate, stage_ms=avg_stage_ms,
                stage_ms_each=[sum(t[i] for t in durs) / len(durs) for i in range(3)],
                achieved_GBs=achieved, bytes_per_stage_avg=sum(sb) / 3, finite=finite)
-    log(args, f"[bench] {prec}: {ms_step:.3f} ms/step, {rate:.3e} DOF-updates/s/stage, stage {avg_stage_ms:.3f} ms, "
+    log(args, f"[bench] {prec}: {ms_step:.3f} ms/step, {rate:.3e} DOF-updates/s/stage, stage {avg_stage_ms:.3f} ms "
+              f"({', '.join(f'{v:.2f}' for v in out['stage_ms_each'])}), "
               f"{achieved:.0f} GB/s algorithmic, finite={finite}")
     del s, y
     torch.cuda.empty_cache()

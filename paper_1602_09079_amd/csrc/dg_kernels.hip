@@ -564,19 +564,21 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     // volume integral: GEMM1 -> flux deviation -> GEMM2, one 16-point tile at a time; with the
     // driving (Sec. 3.1) the source S = (0, rho a, m.a) at the same points is projected by GEMM5
     // (T5 = -phi w / 8), a(x_q) read from the acceleration cache of the row (slab ar)
-    auto volume = [&](const B &b, Acc acc[NF][RT2], __amdgpu_buffer_rsrc_t ar) {
+    // this lane's 4 points of tile t: a_c at point 16 t + orow(g, r); the offset passes an empty asm
+    // so the loads are issued where this is called, not hoisted for every tile
+    auto accel_tile = [&](__amdgpu_buffer_rsrc_t ar, int t, C av[3][4]) {
+        unsigned ao = ((t * 3) * 4 + g) * nxu * 4 * esz + xoff * 4;
+        asm volatile("" : "+v"(ao));
+#pragma unroll
+        for (int c = 0; c < 3; c++) accel_load(ar, ao + c * 4 * nxu * 4 * esz, av[c]);
+    };
+    // av holds tile 0 on entry (loaded early by the caller); tile t + 1 is requested once tile t's
+    // source is done, so its latency hides behind tile t's fluxes
+    auto volume = [&](const B &b, Acc acc[NF][RT2], __amdgpu_buffer_rsrc_t ar, C av[3][4]) {
         C Fb[3][5];
         euler_flux3<PR>(b.qbar, g1, Fb);
 #pragma unroll
         for (int t = 0; t < RT1; t++) {
-            C av[3][4];  // this lane's 4 points of the tile: a_c at point 16 t + orow(g, r)
-            if constexpr (FORCE) {
-                // the offset passes an empty asm so the loads are issued here, not hoisted for all tiles
-                unsigned ao = ((t * 3) * 4 + g) * nxu * 4 * esz + xoff * 4;
-                asm volatile("" : "+v"(ao));
-#pragma unroll
-                for (int c = 0; c < 3; c++) accel_load(ar, ao + c * 4 * nxu * 4 * esz, av[c]);
-            }
             Acc d[NF];
 #pragma unroll
             for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
@@ -630,6 +632,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                         for (int rt = 0; rt < RT2; rt++) acc[i][rt] = PR::mma2(acc[i][rt], T.t5(rt, t), bf);
                     }
                 }
+                if (t + 1 < RT1) accel_tile(ar, t + 1, av);
             }
 #pragma unroll
             for (int al = 0; al < 3; al++) {
@@ -738,10 +741,13 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             for (int i = 0; i < NF; i++)
 #pragma unroll
                 for (int rt = 0; rt < RT2; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
+            C av[3][4];  // driving acceleration of the current tile (FORCE)
+            const auto ar = slab_rsrc(reinterpret_cast<const S *>(a.acache), aslab, cidx(iy, z));
+            if constexpr (FORCE) accel_tile(ar, 0, av);
             lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
             B nxt;
             load(cidx(iy, z + 1), nxt);
-            volume(cur, acc, slab_rsrc(reinterpret_cast<const S *>(a.acache), aslab, cidx(iy, z)));
+            volume(cur, acc, ar, av);
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
                 C tl[NF][4], Fh[NF][4];
                 {
