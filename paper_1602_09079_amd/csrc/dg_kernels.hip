@@ -853,41 +853,82 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                 lift(5, cur, Fz, acc);
             }
             // combine and store the interior columns; result slot s = 4 rt + r is mode slot_mode(N, g, s),
-            // the mode this lane loaded in slot s, so the FP32/FP64 stage input is still in registers
+            // the mode this lane loaded in slot s, so the FP32/FP64 stage input is still in registers.
+            // The slots go in groups whose loads are all issued before the group's first store:
+            // vector stores count in the same wait counter as loads, so a load placed after a store
+            // waits for it, and interleaving them one by one would serialise the round trips.
             if (keep && act) {
                 const long long rz = cidx(iy, z);
                 const auto ro = slab_rsrc(out, slabn, rz);
-                const auto ri = slab_rsrc(yin, slabn, rz);
-                const auto r0 = slab_rsrc(y0, slabn, rz);
+                const bool comb = a.mode != 0;
+                const bool with0 = comb && a.a != 0.0;
+                constexpr bool CLO = K == 1;  // the closure exists for k = 1 only
+                constexpr int EG = (KPL == 1 && PREC != DG_FP64) ? SPL : 2;  // slots per group
 #pragma unroll
-                for (int sl = 0; sl < SPL; sl++) {
-                    const int rt = sl / 4, r = sl % 4;
-                    const int m = slot_mode(N, g, sl);
-                    if (m < N) {
-                            const unsigned e = KPL == 1 ? boff[sl][0] : boff[0][sl];
+                for (int s0 = 0; s0 < SPL; s0 += EG) {
+                    // the row offsets pass an empty asm here so the group's loads are not hoisted
+                    unsigned eo[EG];
+#pragma unroll
+                    for (int u = 0; u < EG; u++) {
+                        const int sl = s0 + u < SPL ? s0 + u : SPL - 1;
+                        eo[u] = KPL == 1 ? boff[sl][0] : boff[0][sl];
+                        asm volatile("" : "+v"(eo[u]));
+                    }
+                    C yv[NF][EG], y0v[NF][EG], cv[NF][EG];
+                    if constexpr (KPL != 1) {  // BF16 tiers: the products consumed a converted copy
+                        if (comb) {
+                            const auto ri = slab_rsrc(yin, slabn, rz);
+#pragma unroll
+                            for (int u = 0; u < EG; u++)
+#pragma unroll
+                                for (int i = 0; i < NF; i++) yv[i][u] = (C)bload(S(), ri, eo[u], (unsigned)i * fbytes);
+                        }
+                    }
+                    if (with0) {
+                        const auto r0 = slab_rsrc(y0, slabn, rz);
+#pragma unroll
+                        for (int u = 0; u < EG; u++)
+#pragma unroll
+                            for (int i = 0; i < NF; i++) y0v[i][u] = (C)bload(S(), r0, eo[u], (unsigned)i * fbytes);
+                    }
+                    if constexpr (CLO) {
+                        if (a.corr) {  // learned closure: dy/dt = -R + c
+                            const auto rcr = slab_rsrc(reinterpret_cast<const S *>(a.corr), slabn, rz);
+#pragma unroll
+                            for (int u = 0; u < EG; u++)
+#pragma unroll
+                                for (int i = 0; i < NF; i++) cv[i][u] = (C)bload(S(), rcr, eo[u], (unsigned)i * fbytes);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < EG; u++) {
+                        const int sl = s0 + u;
+                        if (sl >= SPL) break;
+                        const int rt = sl / 4, r = sl % 4;
+                        const int m = slot_mode(N, g, sl);
+                        if (m < N) {
 #pragma unroll
                             for (int i = 0; i < NF; i++) {
                                 const unsigned so = (unsigned)i * fbytes;
                                 C R = (C)acc[i][rt][r];
-                                if (a.corr) {  // learned closure: dy/dt = -R + c
-                                    const auto rcr = slab_rsrc(reinterpret_cast<const S *>(a.corr), slabn, rz);
-                                    R -= (C)bload(S(), rcr, e, so) - (m == 0 ? (C)a.cmean[i] : C(0));
-                                }
-                                if (a.mode == 0) {
-                                    bstore((S)R, ro, e + so);
+                                if constexpr (CLO)
+                                    if (a.corr) R -= cv[i][u] - (m == 0 ? (C)a.cmean[i] : C(0));
+                                if (!comb) {
+                                    bstore((S)R, ro, eo[u] + so);
                                 } else {
-                                    C yv;
+                                    C y1;
                                     if constexpr (KPL == 1)
-                                        yv = m == 0 ? cur.qbar[i] : (C)cur.w[i][sl].v;
+                                        y1 = m == 0 ? cur.qbar[i] : (C)cur.w[i][sl].v;
                                     else
-                                        yv = (C)bload(S(), ri, e, so);
-                                    const C base = (C)a.b * (yv - dt * R);
-                                    const C res = a.a != 0.0 ? (C)a.a * (C)bload(S(), r0, e, so) + base : base;
-                                    bstore((S)res, ro, e + so);
+                                        y1 = yv[i][u];
+                                    const C base = (C)a.b * (y1 - dt * R);
+                                    const C res = with0 ? (C)a.a * y0v[i][u] + base : base;
+                                    bstore((S)res, ro, eo[u] + so);
                                 }
                             }
                         }
                     }
+                }
             }
             cur = nxt;
         }
