@@ -360,7 +360,12 @@ constexpr int stage_waves_per_eu() { return PREC == DG_FP64 ? 1 : 2; }
 // plus the cell means in full precision.
 template <int K, int PREC>
 struct Blk {
-    typename Prec<PREC>::BF w[NF][StageCfg<K, PREC>::KS1];
+    // FP32/FP64: the B operands are the weights themselves.  BF16 tiers: the raw weights of the
+    // lane's mode slots; the (split) BF16 operands are formed where they are used, which keeps
+    // fewer registers live than holding the converted copy, and keeps the FP32 values for the combine.
+    static constexpr bool RAW = Prec<PREC>::KPL != 1;
+    typename Prec<PREC>::BF w[NF][RAW ? 1 : StageCfg<K, PREC>::KS1];
+    typename Prec<PREC>::C v[NF][RAW ? mode_slots(Dims<K>::N) : 1];
     typename Prec<PREC>::C qbar[NF];
 };
 
@@ -484,13 +489,34 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
         for (int i = 0; i < NF; i++) {
             const unsigned so = (unsigned)i * fbytes;
             b.qbar[i] = (C)bload(S(), rs, xoff, so);
+            if constexpr (B::RAW) {
 #pragma unroll
-            for (int s = 0; s < KS1; s++) {
-                C v[KPL];
+                for (int s = 0; s < SPL; s++) b.v[i][s] = (C)bload(S(), rs, boff[0][s], so);
+            } else {
 #pragma unroll
-                for (int j = 0; j < KPL; j++) v[j] = (C)bload(S(), rs, boff[s][j], so);
-                b.w[i][s] = PR::mkb(v);
+                for (int s = 0; s < KS1; s++) {
+                    C v[KPL];
+#pragma unroll
+                    for (int j = 0; j < KPL; j++) v[j] = (C)bload(S(), rs, boff[s][j], so);
+                    b.w[i][s] = PR::mkb(v);
+                }
             }
+        }
+    };
+    // B operand of field i, K-step s of a block (converted here for the BF16 tiers)
+    auto bop = [&](const B &b, int i, int s) -> typename PR::BF {
+        if constexpr (B::RAW) {
+            // an empty asm on the copies keeps each use's conversion from being merged with the
+            // others (which would hold the converted copy live across the whole step)
+            C v[KPL];
+#pragma unroll
+            for (int j = 0; j < KPL; j++) {
+                v[j] = j < SPL ? b.v[i][j] : C(0);
+                if (j < SPL) asm volatile("" : "+v"(v[j]));
+            }
+            return PR::mkb(v);
+        } else {
+            return b.w[i][s];
         }
     };
     auto trace = [&](const B &b, int face, C tr[NF][4]) {
@@ -501,7 +527,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
         for (int s = 0; s < KS1; s++) {
             const auto A = T.t3(face, s);
 #pragma unroll
-            for (int i = 0; i < NF; i++) t[i] = PR::mma(t[i], A, b.w[i][s]);
+            for (int i = 0; i < NF; i++) t[i] = PR::mma(t[i], A, bop(b, i, s));
         }
 #pragma unroll
         for (int i = 0; i < NF; i++)
@@ -586,7 +612,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             for (int s = 0; s < KS1; s++) {
                 const auto A = T.t1(t, s);
 #pragma unroll
-                for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, b.w[i][s]);
+                for (int i = 0; i < NF; i++) d[i] = PR::mma(d[i], A, bop(b, i, s));
             }
             // primitive quantities at this lane's 4 points of the tile
             C mx[4], my[4], mz[4], ep[4], vel[3][4], p[4], rho_pt[4];
@@ -863,7 +889,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                 const bool comb = a.mode != 0;
                 const bool with0 = comb && a.a != 0.0;
                 constexpr bool CLO = K == 1;  // the closure exists for k = 1 only
-                constexpr int EG = (KPL == 1 && PREC != DG_FP64) ? SPL : 2;  // slots per group
+                constexpr int EG = PREC != DG_FP64 ? SPL : 2;  // slots per group
 #pragma unroll
                 for (int s0 = 0; s0 < SPL; s0 += EG) {
                     // the row offsets pass an empty asm here so the group's loads are not hoisted
@@ -874,16 +900,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                         eo[u] = KPL == 1 ? boff[sl][0] : boff[0][sl];
                         asm volatile("" : "+v"(eo[u]));
                     }
-                    C yv[NF][EG], y0v[NF][EG], cv[NF][EG];
-                    if constexpr (KPL != 1) {  // BF16 tiers: the products consumed a converted copy
-                        if (comb) {
-                            const auto ri = slab_rsrc(yin, slabn, rz);
-#pragma unroll
-                            for (int u = 0; u < EG; u++)
-#pragma unroll
-                                for (int i = 0; i < NF; i++) yv[i][u] = (C)bload(S(), ri, eo[u], (unsigned)i * fbytes);
-                        }
-                    }
+                    C y0v[NF][EG], cv[NF][EG];
                     if (with0) {
                         const auto r0 = slab_rsrc(y0, slabn, rz);
 #pragma unroll
@@ -920,7 +937,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                                     if constexpr (KPL == 1)
                                         y1 = m == 0 ? cur.qbar[i] : (C)cur.w[i][sl].v;
                                     else
-                                        y1 = yv[i][u];
+                                        y1 = m == 0 ? cur.qbar[i] : cur.v[i][sl];
                                     const C base = (C)a.b * (y1 - dt * R);
                                     const C res = with0 ? (C)a.a * y0v[i][u] + base : base;
                                     bstore((S)res, ro, eo[u] + so);
