@@ -300,3 +300,41 @@ def closure_correction(cfg, y, clo):
     L.orc_closure_correction.restype = ctypes.c_int64
     nfb = L.orc_closure_correction(ctypes.byref(cfg), _d(y), clo.ptr(), _d(corr))
     return corr, int(nfb)
+
+
+LIMIT_EPS = 1e-13
+
+
+def gll(m):
+    x = np.zeros(m)
+    w = np.zeros(m)
+    lib().orc_gll(m, _d(x), _d(w))
+    return x, w
+
+
+def limiter_points(k):
+    pts = np.zeros((3 * 3 * (k + 1) ** 2, 3))
+    n = lib().orc_limiter_points(k, _d(pts))
+    return pts[:n]
+
+
+def limit(cfg, y, eps=LIMIT_EPS):
+    """Returns (limited copy of y, theta [cells][2])."""
+    y = np.array(y, dtype=np.float64, copy=True, order="C")
+    th = np.zeros((cfg.n[0] * cfg.n[1] * cfg.n[2], 2))
+    lib().orc_limit(ctypes.byref(cfg), _d(y), ctypes.c_double(eps), _d(th))
+    return y, th
+
+
+def dt_limited(cfg, y):
+    L = lib()
+    L.orc_dt_limited.restype = ctypes.c_double
+    return L.orc_dt_limited(ctypes.byref(cfg), _d(np.ascontiguousarray(y, dtype=np.float64)))
+
+
+def step_limited(cfg, y, h=0.0, nsteps=1, t=0.0, frc=None, eps=LIMIT_EPS):
+    y = np.array(y, dtype=np.float64, copy=True, order="C")
+    tt = ctypes.c_double(t)
+    lib().orc_step_limited(ctypes.byref(cfg), _d(y), ctypes.c_double(h), nsteps, ctypes.byref(tt), _fptr(frc),
+                           ctypes.c_double(eps))
+    return y, tt.value

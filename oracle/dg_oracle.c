@@ -731,3 +731,137 @@ int64_t orc_closure_correction(const orc_cfg *cfg, const double *y, const orc_cl
     free(o);
     return fallbacks;
 }
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.5: positivity limiter                                         */
+/* ------------------------------------------------------------------ */
+
+int orc_limiter_m(int k) { return k <= 1 ? 2 : 3; }
+
+void orc_gll(int m, double *x, double *w)
+{
+    /* Gauss-Lobatto-Legendre rules with 2 and 3 points on [-1, 1] (closed forms) */
+    if (m == 2) {
+        x[0] = -1.0; x[1] = 1.0;
+        w[0] = 1.0; w[1] = 1.0;
+    } else {
+        x[0] = -1.0; x[1] = 0.0; x[2] = 1.0;
+        w[0] = 1.0 / 3.0; w[1] = 4.0 / 3.0; w[2] = 1.0 / 3.0;
+    }
+}
+
+/* the points of S = S_x u S_y u S_z: along one axis the m GLL nodes, along the
+ * other two the k+1 Gauss nodes; returns the count, fills pts[count][3] */
+int orc_limiter_points(int k, double *pts)
+{
+    int n = k + 1, m = orc_limiter_m(k), c = 0;
+    double xg[GMAX], wg[GMAX], xl[3], wl[3];
+    orc_gauss_legendre(n, xg, wg);
+    orc_gll(m, xl, wl);
+    for (int a = 0; a < 3; a++)
+        for (int r = 0; r < m; r++)
+            for (int s = 0; s < n; s++)
+                for (int t = 0; t < n; t++) {
+                    double *p = pts + 3 * c++;
+                    int o1 = a == 0 ? 1 : 0, o2 = a == 2 ? 1 : 2;
+                    p[a] = xl[r];
+                    p[o1] = xg[s];
+                    p[o2] = xg[t];
+                }
+    return c;
+}
+
+/* the unique root in (0, 1) of P(qbar + tau (q - qbar)) = eps, where P is concave
+ * along the segment, positive above eps at tau = 0 and below it at tau = 1;
+ * bisection to the end of double precision.  A mean already at or below eps
+ * gives 0. */
+static double tau_root(const double qbar[5], const double q[5], double gamma, double eps)
+{
+    double lo = 0.0, hi = 1.0, s[5];
+    if (!(pressure(qbar, gamma) > eps)) return 0.0;
+    for (int it = 0; it < 200; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        for (int i = 0; i < NF; i++) s[i] = qbar[i] + mid * (q[i] - qbar[i]);
+        if (s[0] > 0.0 && pressure(s, gamma) >= eps) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+void orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta)
+{
+    int k = cfg->k, N = orc_nmodes(k);
+    size_t nc = ncells_of(cfg);
+    double pts[3 * 3 * 3 * GMAX * GMAX];
+    int np = orc_limiter_points(k, pts);
+    double *phi = malloc(sizeof(double) * np * N);
+    for (int p = 0; p < np; p++) orc_basis(k, pts + 3 * p, phi + (size_t)p * N);
+#pragma omp parallel for schedule(static)
+    for (size_t K = 0; K < nc; K++) {
+        double w[NF][NMAX];
+        for (int i = 0; i < NF; i++)
+            for (int l = 0; l < N; l++) w[i][l] = y[((size_t)i * N + l) * nc + K];
+        /* density: theta_1 from the minimum over S */
+        double rmin = w[0][0];
+        for (int p = 0; p < np; p++) {
+            double r = 0.0;
+            for (int l = 0; l < N; l++) r += w[0][l] * phi[(size_t)p * N + l];
+            if (r < rmin) rmin = r;
+        }
+        double rbar = w[0][0];
+        double th1 = rbar == rmin ? 1.0 : fmin(fabs((rbar - eps) / (rbar - rmin)), 1.0);
+        for (int l = 1; l < N; l++) w[0][l] *= th1;
+        /* pressure: theta_2 = min over S of tau */
+        double qbar[5], th2 = 1.0;
+        for (int i = 0; i < NF; i++) qbar[i] = w[i][0];
+        for (int p = 0; p < np; p++) {
+            double q[5];
+            for (int i = 0; i < NF; i++) {
+                double s = 0.0;
+                for (int l = 0; l < N; l++) s += w[i][l] * phi[(size_t)p * N + l];
+                q[i] = s;
+            }
+            if (!(q[0] > 0.0 && pressure(q, cfg->gamma) >= eps)) {
+                double t = tau_root(qbar, q, cfg->gamma, eps);
+                if (t < th2) th2 = t;
+            }
+        }
+        for (int i = 0; i < NF; i++)
+            for (int l = 1; l < N; l++) w[i][l] *= th2;
+        for (int i = 0; i < NF; i++)
+            for (int l = 0; l < N; l++) y[((size_t)i * N + l) * nc + K] = w[i][l];
+        if (theta) {
+            theta[2 * K] = th1;
+            theta[2 * K + 1] = th2;
+        }
+    }
+    free(phi);
+}
+
+double orc_dt_limited(const orc_cfg *cfg, const double *y)
+{
+    double xl[3], wl[3];
+    orc_gll(orc_limiter_m(cfg->k), xl, wl);
+    double f = fmin(1.0 / (2.0 * cfg->k + 1.0), 0.5 * wl[0]);
+    return orc_dt(cfg, y) * (2.0 * cfg->k + 1.0) * f;
+}
+
+void orc_step_limited(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t, const orc_forcing *frc,
+                      double eps)
+{
+    size_t ns = (size_t)NF * orc_nmodes(cfg->k) * ncells_of(cfg);
+    double *y1 = malloc(sizeof(double) * ns), *y2 = malloc(sizeof(double) * ns);
+    for (int it = 0; it < nsteps; it++) {
+        orc_limit(cfg, y, eps, NULL);  /* the stage input of stage 1 is y^n itself */
+        double h = dt > 0.0 ? dt : orc_dt_limited(cfg, y);
+        orc_stage(cfg, y, y, 0.0, 1.0, h, frc, y1);
+        orc_limit(cfg, y1, eps, NULL);
+        orc_stage(cfg, y, y1, 0.75, 0.25, h, frc, y2);
+        orc_limit(cfg, y2, eps, NULL);
+        orc_stage(cfg, y, y2, 1.0 / 3.0, 2.0 / 3.0, h, frc, y);
+        if (t) *t += h;
+    }
+    free(y1);
+    free(y2);
+}

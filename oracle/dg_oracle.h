@@ -17,6 +17,7 @@
  *   forcing table (OU + Helmholtz projection)               -- pinned (statistics, solenoidality)
  *   restriction                                             -- pinned (exactness, conservation)
  *   MLP forward/backward/Adam                               -- pinned (finite differences, textbook Adam)
+ *   positivity limiter, GLL rules, limited dt               -- pinned (closed-form cases, invariants)
  *   closure features / correction                           -- pinned (neighbour order, closed-form outputs,
  *                                                              fallback, zero-sum mean rows)
  */
@@ -91,6 +92,24 @@ void orc_accel(const orc_forcing *frc, const double box[3], const double x[3], d
  * amplitude; kmin/kmax: band in units of 2 pi / L.  ahat out: [nmodes][3][2]. */
 void orc_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const double *z,
                    double f, double sigma, double a0, double kmin, double kmax, double *ahat);
+
+/* ---- Sec. 2.5: positivity limiter (Zhang and Shu) ----
+ * Points S = S_x u S_y u S_z: the m GLL nodes along one axis (m = 2 for k <= 1,
+ * 3 for k >= 2) times the k+1 Gauss nodes along the other two.  Per cell:
+ * theta_1 = min(|(rhobar - eps)/(rhobar - rho_min)|, 1) over S scales the
+ * density's modes l >= 1; then theta_2 = min over S of tau, tau = 1 where
+ * P >= eps, else the root of P(qbar + tau (q - qbar)) = eps (the garbled
+ * printed form read as Zhang-Shu's), scales every field's modes l >= 1.
+ * y is limited in place; theta (may be NULL) receives [cell][2] = (th1, th2). */
+int    orc_limiter_m(int k);
+void   orc_gll(int m, double *x, double *w);
+int    orc_limiter_points(int k, double *pts);
+void   orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta);
+/* dt of the limited scheme: C min(1/(2k+1), w_hat_1/2) / max rate */
+double orc_dt_limited(const orc_cfg *cfg, const double *y);
+/* SSP-RK3 with the limiter applied to each stage's input (y^n in place for stage 1) */
+void   orc_step_limited(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t, const orc_forcing *frc,
+                        double eps);
 
 /* ---- closure support (not in the paper) ---- */
 /* exact L2 restriction of a degree-kf state on (2n)^3 cells onto degree-kc on n^3 cells */

@@ -1,0 +1,138 @@
+"""Pins of the oracle's positivity limiter (arXiv 1602.09079, Sec. 2.5)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_09079_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+G = 5.0 / 3.0
+EPS = O.LIMIT_EPS
+
+
+def test_gll_rules_against_paper_and_exactness():
+    gold = json.load(open(os.path.join(HERE, "golden", "gll.json")))
+    for m in (2, 3):
+        x, w = O.gll(m)
+        np.testing.assert_allclose(x, gold[f"m{m}"]["nodes"], rtol=0, atol=1e-16)
+        np.testing.assert_allclose(w, gold[f"m{m}"]["weights"], rtol=1e-15)
+        # exact for degree 2m - 3
+        for d in range(2 * m - 2):
+            exact = 0.0 if d % 2 else 2.0 / (d + 1)
+            assert abs(np.dot(w, x ** d) - exact) < 1e-15
+    for k, order in ((1, "2"), (2, "3"), (3, "4")):
+        _, w = O.gll(2 if k <= 1 else 3)
+        assert w[0] == pytest.approx(gold["first_weight_by_order"][order], rel=1e-15)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter_points(k):
+    pts = O.limiter_points(k)
+    m = 2 if k <= 1 else 3
+    assert pts.shape == (3 * m * (k + 1) ** 2, 3)
+    xg, _ = O.gauss_legendre(k + 1)
+    for a in range(3):
+        block = pts[a * m * (k + 1) ** 2:(a + 1) * m * (k + 1) ** 2]
+        assert set(np.round(block[:, a], 15)) == set(np.round(O.gll(m)[0], 15))
+        for o in range(3):
+            if o != a:
+                assert set(np.round(block[:, o], 12)) == set(np.round(xg, 12))
+
+
+def _values_at(k, w, pts):
+    phi = np.array([O.basis(k, p) for p in pts])
+    return phi @ w
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter_identity_on_positive_states(k):
+    cfg = O.make_cfg(k, 6, gamma=G)
+    x = O.gauss_legendre(k + 1)[0]
+    y = O.project(cfg, synth.turbulence(6, x, seed=9079, mach=0.3).numpy())
+    yl, th = O.limit(cfg, y)
+    np.testing.assert_array_equal(yl, y)
+    assert np.all(th == 1.0)
+
+
+def _one_cell_state(k, n=2):
+    cfg = O.make_cfg(k, n, gamma=G)
+    y = np.zeros(O.state_shape(cfg))
+    y[0, 0] = 1.0    # rho = 1
+    y[4, 0] = 10.0   # E = 10, at rest: P = (gamma - 1) E
+    return cfg, y
+
+
+def test_density_theta_closed_form():
+    cfg, y = _one_cell_state(1)
+    a = 2.0
+    y[0, 1, 0, 0, 0] = a  # mode (100) of cell 0: rho = 1 + a sqrt(3) xi_x
+    rmin = 1.0 - a * math.sqrt(3.0)
+    yl, th = O.limit(cfg, y)
+    want = (1.0 - EPS) / (1.0 - rmin)
+    assert th[0, 0] == pytest.approx(want, rel=1e-14)
+    assert yl[0, 1, 0, 0, 0] == pytest.approx(a * want, rel=1e-14)
+    pts = O.limiter_points(1)
+    r = _values_at(1, yl[0, :, 0, 0, 0], pts)
+    assert r.min() == pytest.approx(EPS, abs=1e-15)
+    np.testing.assert_array_equal(yl[:, 0], y[:, 0])  # means untouched
+    assert np.all(th[1:] == 1.0)
+
+
+def test_pressure_theta_closed_form():
+    cfg, y = _one_cell_state(1)
+    Ebar, b = 1.0, 1.0
+    y[4, 0, 0, 0, 0] = Ebar
+    y[4, 3, 0, 0, 0] = b  # mode (001): E = 1 + b sqrt(3) xi_z, at rest P = (gamma - 1) E
+    emin = Ebar - b * math.sqrt(3.0)
+    yl, th = O.limit(cfg, y)
+    tau = (EPS / (G - 1.0) - Ebar) / (emin - Ebar)  # P(Ebar + tau (Emin - Ebar)) = eps
+    assert th[0, 0] == 1.0
+    assert th[0, 1] == pytest.approx(tau, rel=1e-12)
+    assert yl[4, 3, 0, 0, 0] == pytest.approx(b * tau, rel=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter_invariants_on_violated_states(k):
+    cfg = O.make_cfg(k, (4, 3, 3), gamma=G)
+    rng = np.random.default_rng(31 + k)
+    y = rng.standard_normal(O.state_shape(cfg)) * 0.6
+    y[0, 0] = 1.0 + 0.2 * rng.random(y[0, 0].shape)
+    y[1:4, 0] = 0.3 * rng.standard_normal(y[1:4, 0].shape)
+    y[4, 0] = 2.0 + rng.random(y[4, 0].shape)
+    yl, th = O.limit(cfg, y)
+    assert np.any(th < 1.0) and np.all((th >= 0.0) & (th <= 1.0))
+    np.testing.assert_array_equal(yl[:, 0], y[:, 0])
+    pts = O.limiter_points(k)
+    N = O.nmodes(k)
+    w = yl.reshape(5, N, -1)
+    phi = np.array([O.basis(k, p) for p in pts])
+    q = np.einsum("pl,ilc->ipc", phi, w)
+    assert q[0].min() >= EPS * (1 - 1e-9) - 1e-14
+    p = (G - 1.0) * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0])
+    assert p.min() >= -1e-12
+    # limiting a limited state changes (almost) nothing
+    y2, th2 = O.limit(cfg, yl)
+    assert np.all(th2 >= 1.0 - 1e-9)
+
+
+def test_limited_dt_factor():
+    cfg = O.make_cfg(1, 4, gamma=G)
+    for k, ratio in ((1, 1.0), (2, (1 / 6) / (1 / 5)), (3, 1.0)):
+        cfg = O.make_cfg(k, 4, gamma=G)
+        x = O.gauss_legendre(k + 1)[0]
+        y = O.project(cfg, synth.turbulence(4, x, seed=1, mach=0.3).numpy())
+        assert O.dt_limited(cfg, y) == pytest.approx(O.dt(cfg, y) * ratio, rel=1e-14)
+
+
+def test_limited_step_equals_plain_on_positive_states():
+    cfg = O.make_cfg(2, 5, gamma=G)
+    x = O.gauss_legendre(3)[0]
+    y = O.project(cfg, synth.turbulence(5, x, seed=2, mach=0.3).numpy())
+    h = O.dt(cfg, y)
+    a, _ = O.step(cfg, y, h, 2)
+    b, _ = O.step_limited(cfg, y, h, 2)
+    np.testing.assert_array_equal(a, b)
