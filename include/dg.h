@@ -60,7 +60,8 @@ typedef enum {
 enum {
     DG_FORCING = 1u,      /* add the driving source term of Sec. 3.1 (needs dg_set_forcing) */
     DG_CLOSURE = 2u,      /* k = 1 only: add the learned closure correction (needs dg_set_closure) */
-    DG_CHECK_RANGE = 4u   /* dg_step checks cell means for rho>0, p>0, finite after each step */
+    DG_CHECK_RANGE = 4u,  /* dg_step checks cell means for rho>0, p>0, finite after each step */
+    DG_LIMIT = 8u         /* positivity limiter of Sec. 2.5 on every stage input (see dg_limiter_stats) */
 };
 
 typedef struct {
@@ -70,7 +71,7 @@ typedef struct {
     double gamma;       /* adiabatic index, > 1 */
     double cfl;         /* Courant factor C of Sec. 2.4, in (0, 1] */
     int32_t precision;  /* a dg_precision value */
-    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE */
+    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT */
 } dg_config;
 
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
@@ -234,6 +235,29 @@ dg_status dg_column_stats(const float *x, int64_t rows, int32_t cols, double *me
 /* x[r][c] = (x[r][c] - shift[c]) / scale[c] in place.  shift, scale: DEVICE double [cols]. */
 dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shift, const double *scale,
                          void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Positivity limiter (Sec. 2.5, Zhang and Shu), enabled by DG_LIMIT.
+ * Applied to the input of every stage (dg_rhs, dg_stage, each stage of
+ * dg_step), IN PLACE: the caller's y / yin is replaced by its limited value
+ * (for dg_step: y^n before the time step is computed, then y^(1), y^(2)).
+ * Points S: along one axis the m GLL nodes (m = 2 for k = 1, m = 3 for
+ * k = 2, 3: -1, 0, 1), along the other two the k+1 Gauss nodes, for each axis.
+ * Per cell, eps = 1e-13: theta_1 = min(|(rhobar - eps)/(rhobar - rho_min)|, 1)
+ * scales the density's modes l >= 1; then theta_2 = min over S of tau, tau = 1
+ * where P >= eps (and rho > 0), else the root in (0, 1) of
+ * P(qbar + tau (q - qbar)) = eps found by Newton-Raphson, scales the modes
+ * l >= 1 of every field.  Cell means are never changed.  FP32-storage tiers
+ * raise the targets per cell to max(eps, 2^-20 rhobar) for the density and
+ * max(eps, 2^-20 (gamma-1) Ebar) for the pressure, above the rounding of the
+ * stored weights, which would otherwise undo the limiting.  With DG_LIMIT the CFL
+ * step becomes C min(1/(2k+1), w_hat_1/2) / max rate, w_hat_1 the first GLL
+ * weight (1 for k = 1, 1/3 for k = 2, 3).  Computed in the storage
+ * precision (FP32 for the FP32-storage tiers).
+ *
+ * Cells changed by the limiter since the previous call, then reset.
+ * count: HOST.  Synchronises.  0 without DG_LIMIT. */
+dg_status dg_limiter_stats(dg_ctx *ctx, int64_t *count);
 
 /* Host-only helpers for callers that sample fields at the Gauss points. */
 int32_t dg_nmodes(int32_t k);                      /* N(k) = (k+1)(k+2)(k+3)/6, Sec. 2.1 */

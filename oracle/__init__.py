@@ -318,11 +318,14 @@ def limiter_points(k):
     return pts[:n]
 
 
-def limit(cfg, y, eps=LIMIT_EPS):
-    """Returns (limited copy of y, theta [cells][2])."""
+LIMIT_REL_FP32 = 2.0 ** -20
+
+
+def limit(cfg, y, eps=LIMIT_EPS, rel=0.0):
+    """Returns (limited copy of y, theta [cells][2]).  rel: see orc_limit (2^-20 for FP32 storage)."""
     y = np.array(y, dtype=np.float64, copy=True, order="C")
     th = np.zeros((cfg.n[0] * cfg.n[1] * cfg.n[2], 2))
-    lib().orc_limit(ctypes.byref(cfg), _d(y), ctypes.c_double(eps), _d(th))
+    lib().orc_limit(ctypes.byref(cfg), _d(y), ctypes.c_double(eps), ctypes.c_double(rel), _d(th))
     return y, th
 
 

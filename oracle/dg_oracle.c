@@ -789,7 +789,7 @@ static double tau_root(const double qbar[5], const double q[5], double gamma, do
     return lo;
 }
 
-void orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta)
+void orc_limit(const orc_cfg *cfg, double *y, double eps, double rel, double *theta)
 {
     int k = cfg->k, N = orc_nmodes(k);
     size_t nc = ncells_of(cfg);
@@ -810,7 +810,10 @@ void orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta)
             if (r < rmin) rmin = r;
         }
         double rbar = w[0][0];
-        double th1 = rbar == rmin ? 1.0 : fmin(fabs((rbar - eps) / (rbar - rmin)), 1.0);
+        /* targets: eps, raised to rel times the cell's mean density / (gamma-1) times its mean
+         * energy for storage whose rounding would otherwise undo the limiting */
+        double eps_r = fmax(eps, rel * rbar), eps_p = fmax(eps, rel * (cfg->gamma - 1.0) * w[4][0]);
+        double th1 = rbar == rmin ? 1.0 : fmin(fabs((rbar - eps_r) / (rbar - rmin)), 1.0);
         for (int l = 1; l < N; l++) w[0][l] *= th1;
         /* pressure: theta_2 = min over S of tau */
         double qbar[5], th2 = 1.0;
@@ -822,8 +825,8 @@ void orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta)
                 for (int l = 0; l < N; l++) s += w[i][l] * phi[(size_t)p * N + l];
                 q[i] = s;
             }
-            if (!(q[0] > 0.0 && pressure(q, cfg->gamma) >= eps)) {
-                double t = tau_root(qbar, q, cfg->gamma, eps);
+            if (!(q[0] > 0.0 && pressure(q, cfg->gamma) >= eps_p)) {
+                double t = tau_root(qbar, q, cfg->gamma, eps_p);
                 if (t < th2) th2 = t;
             }
         }
@@ -853,12 +856,12 @@ void orc_step_limited(const orc_cfg *cfg, double *y, double dt, int nsteps, doub
     size_t ns = (size_t)NF * orc_nmodes(cfg->k) * ncells_of(cfg);
     double *y1 = malloc(sizeof(double) * ns), *y2 = malloc(sizeof(double) * ns);
     for (int it = 0; it < nsteps; it++) {
-        orc_limit(cfg, y, eps, NULL);  /* the stage input of stage 1 is y^n itself */
+        orc_limit(cfg, y, eps, 0.0, NULL);  /* the stage input of stage 1 is y^n itself */
         double h = dt > 0.0 ? dt : orc_dt_limited(cfg, y);
         orc_stage(cfg, y, y, 0.0, 1.0, h, frc, y1);
-        orc_limit(cfg, y1, eps, NULL);
+        orc_limit(cfg, y1, eps, 0.0, NULL);
         orc_stage(cfg, y, y1, 0.75, 0.25, h, frc, y2);
-        orc_limit(cfg, y2, eps, NULL);
+        orc_limit(cfg, y2, eps, 0.0, NULL);
         orc_stage(cfg, y, y2, 1.0 / 3.0, 2.0 / 3.0, h, frc, y);
         if (t) *t += h;
     }

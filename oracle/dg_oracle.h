@@ -104,7 +104,9 @@ void orc_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const dou
 int    orc_limiter_m(int k);
 void   orc_gll(int m, double *x, double *w);
 int    orc_limiter_points(int k, double *pts);
-void   orc_limit(const orc_cfg *cfg, double *y, double eps, double *theta);
+/* rel > 0 raises the targets to max(eps, rel rhobar) and max(eps, rel (gamma-1) Ebar) per cell
+ * (single-precision storage); rel = 0 is the plain limiter */
+void   orc_limit(const orc_cfg *cfg, double *y, double eps, double rel, double *theta);
 /* dt of the limited scheme: C min(1/(2k+1), w_hat_1/2) / max rate */
 double orc_dt_limited(const orc_cfg *cfg, const double *y);
 /* SSP-RK3 with the limiter applied to each stage's input (y^n in place for stage 1) */

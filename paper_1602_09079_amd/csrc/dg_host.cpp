@@ -253,6 +253,13 @@ dg_status hip_fail(dg_ctx *c, hipError_t e, const char *what) {
 
 size_t elem_bytes(const dg_ctx *c) { return c->cfg.precision == DG_FP64 ? 8 : 4; }
 
+// C / (2k+1) (Sec. 2.4); with the positivity limiter C min(1/(2k+1), w_hat_1/2) (Sec. 2.5)
+double dt_factor(const dg_ctx *c) {
+    double f = 1.0 / (2.0 * c->cfg.k + 1.0);
+    if (c->cfg.flags & DG_LIMIT) f = std::min(f, 0.5 * (c->cfg.k <= 1 ? 1.0 : 1.0 / 3.0));
+    return c->cfg.cfl * f;
+}
+
 }  // namespace
 
 namespace dgmi {
@@ -315,7 +322,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
-    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE)) return DG_ERR_ARG;
+    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT)) return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     {
@@ -359,6 +366,30 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         }
         if (hipMalloc(&c->ptab, pt.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
         if (hipMemcpy(c->ptab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+    }
+    if (cfg->flags & DG_LIMIT) {
+        // phi_l at the limiter points: GLL nodes along one axis, Gauss nodes along the others
+        const Basis B(cfg->k);
+        const int m = cfg->k <= 1 ? 2 : 3;
+        const double xl[3] = {-1.0, m == 2 ? 1.0 : 0.0, 1.0};
+        std::vector<double> lt;
+        for (int a = 0; a < 3; a++)
+            for (int r = 0; r < m; r++)
+                for (int s2 = 0; s2 < c->n; s2++)
+                    for (int t = 0; t < c->n; t++) {
+                        double xi[3];
+                        const int o1 = a == 0 ? 1 : 0, o2 = a == 2 ? 1 : 2;
+                        xi[a] = xl[r];
+                        xi[o1] = B.xg[s2];
+                        xi[o2] = B.xg[t];
+                        for (int l = 0; l < c->N; l++) lt.push_back(B.phi(l, xi));
+                    }
+        c->limnp = 3 * m * c->n * c->n;
+        if (hipMalloc(&c->limtab, lt.size() * sizeof(double)) != hipSuccess ||
+            hipMemcpy(c->limtab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMalloc(&c->limcount, sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(c->limcount, 0, sizeof(unsigned long long)) != hipSuccess)
+            return fail(DG_ERR_HIP);
     }
     c->nparts = 1024;
     if (hipMalloc(&c->slots, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
@@ -413,6 +444,8 @@ dg_status dg_destroy(dg_ctx *c) {
     if (c->partials) hipFree(c->partials);
     if (c->fmodes) hipFree(c->fmodes);
     if (c->acache) hipFree(c->acache);
+    if (c->limtab) hipFree(c->limtab);
+    if (c->limcount) hipFree(c->limcount);
     if (c->clo) hipFree(c->clo);
     if (c->corr) hipFree(c->corr);
     if (c->clo_partials) hipFree(c->clo_partials);
@@ -442,7 +475,7 @@ dg_status dg_project(dg_ctx *c, const void *qp, void *y) {
 namespace {
 
 dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, double a, double b, double dt, int mode,
-                    bool advance_time) {
+                    bool advance_time, bool limit_input = true) {
     if ((c->cfg.flags & DG_FORCING) && !c->have_forcing) {
         c->err = "DG_FORCING set but dg_set_forcing was not called";
         return DG_ERR_STATE;
@@ -452,6 +485,9 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
         return DG_ERR_STATE;
     }
     StageArgs s{};
+    if ((c->cfg.flags & DG_LIMIT) && limit_input)  // Sec. 2.5: the stage input is limited in place
+        HIPCHK(c, launch_limit(c->cfg.k, c->cfg.precision, const_cast<void *>(yin), c->limtab, c->limnp, c->ncells,
+                               c->cfg.n[0], c->cfg.gamma, LIMIT_EPS, c->limcount, c->stream));
     if (c->cfg.flags & DG_CLOSURE) {
         // the correction of the stage input, then the stage that applies it
         ClosureArgs ca{};
@@ -482,7 +518,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.dt = dt;
     s.a = a;
     s.b = b;
-    s.dtfac = c->cfg.cfl / (2.0 * c->cfg.k + 1.0);
+    s.dtfac = dt_factor(c);
     s.gamma = c->cfg.gamma;
     s.nx = c->cfg.n[0];
     s.ny = c->cfg.n[1];
@@ -547,7 +583,7 @@ dg_status dg_dt(dg_ctx *c, const void *y, double *dt) {
     double rate = 0.0;
     HIPCHK(c, hipMemcpyAsync(&rate, c->slots + c->cur_slot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    *dt = c->cfg.cfl / (2.0 * c->cfg.k + 1.0) / rate;
+    *dt = dt_factor(c) / rate;
     return DG_OK;
 }
 
@@ -568,8 +604,12 @@ dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, dou
     const bool check = (c->cfg.flags & DG_CHECK_RANGE) != 0;
     for (int it = 0; it < nsteps; it++) {
         dg_status st;
+        const bool lim = (c->cfg.flags & DG_LIMIT) != 0;
+        if (lim)  // y^n is limited before its time step is taken (it is the first stage's input)
+            HIPCHK(c, launch_limit(c->cfg.k, c->cfg.precision, y, c->limtab, c->limnp, c->ncells, c->cfg.n[0],
+                                   c->cfg.gamma, LIMIT_EPS, c->limcount, c->stream));
         if (dev_dt && (st = run_cfl(c, y)) != DG_OK) return st;
-        if ((st = run_stage(c, y, y, w1, 0.0, 1.0, dt, 1, false)) != DG_OK) return st;
+        if ((st = run_stage(c, y, y, w1, 0.0, 1.0, dt, 1, false, false)) != DG_OK) return st;
         if ((st = run_stage(c, y, w1, w2, 0.75, 0.25, dt, 1, false)) != DG_OK) return st;
         if ((st = run_stage(c, y, w2, y, 1.0 / 3.0, 2.0 / 3.0, dt, 1, dev_dt && t_inout)) != DG_OK) return st;
         if (check) {
@@ -951,3 +991,19 @@ dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shi
 }
 
 }  // extern "C"
+
+extern "C" dg_status dg_limiter_stats(dg_ctx *c, int64_t *count) {
+    if (!c) return DG_ERR_ARG;
+    if (!count) {
+        c->err = "dg_limiter_stats: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    *count = 0;
+    if (!c->limcount) return DG_OK;
+    unsigned long long v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->limcount, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_zero_u64(c->limcount, c->stream));
+    *count = (int64_t)v;
+    return DG_OK;
+}

@@ -75,6 +75,11 @@ inline long long accel_slab_elems(int k, int nx) {
     const int Q = (k + 1) * (k + 1) * (k + 1);
     return (long long)((Q + 15) / 16) * 16 * 3 * nx;
 }
+constexpr double LIMIT_EPS = 1e-13;  // minimum density and pressure of the positivity limiter
+// FP32 storage: the targets are raised to 2^-20 times the cell's mean density / (gamma-1) x mean energy
+constexpr double LIMIT_REL_FP32 = 1.0 / 1048576.0;
+hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, long long nc, int nx, double gamma,
+                        double eps, unsigned long long *count, hipStream_t s);
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
                               const GaussNodes &xg, void *out, hipStream_t s);
 
@@ -202,5 +207,9 @@ struct dg_ctx {
     unsigned long long *clo_fallbacks = nullptr;
     bool have_closure = false;
     double *restrict_tab[4] = {nullptr, nullptr, nullptr, nullptr};  // per fine degree: [8][N][Nf]
+    // positivity limiter (DG_LIMIT)
+    double *limtab = nullptr;              // phi_l at the limiter points [np][N]
+    int limnp = 0;
+    unsigned long long *limcount = nullptr;  // cells changed by the limiter since the last query
     std::string err;
 };

@@ -1116,6 +1116,130 @@ hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, 
     }
 }
 
+// ------------------------------------------------------------------ positivity limiter (Sec. 2.5)
+
+// One thread per cell, in the storage precision.  The state is read once; it is
+// written back only for the cells the limiter changes.  tab[p][l] = phi_l at the
+// limiter points (the m GLL nodes along one axis times the k+1 Gauss nodes along
+// the other two, for each axis).
+template <int K, class S>
+__global__ __launch_bounds__(256) void limit_kernel(S *__restrict__ y, const double *__restrict__ tab, int np,
+                                                    long long nc, int nx, double gamma, double eps, double rel,
+                                                    unsigned long long *count) {
+    constexpr int N = Dims<K>::N;
+    using C = S;
+    extern __shared__ __attribute__((aligned(16))) char lsm[];
+    C *lt = reinterpret_cast<C *>(lsm);
+    for (int j = threadIdx.x; j < np * N; j += blockDim.x) lt[j] = (C)tab[j];
+    __syncthreads();
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= nc) return;
+    const long long r = cell / nx;
+    const long long base = r * (long long)NF * N * nx + (cell - r * nx);
+    C w[NF][N];
+#pragma unroll
+    for (int i = 0; i < NF; i++)
+#pragma unroll
+        for (int l = 0; l < N; l++) w[i][l] = y[base + (long long)(i * N + l) * nx];
+    const C g1 = (C)(gamma - 1.0), ep = (C)eps;
+    // density: theta_1 from the minimum over the points
+    C rmin = w[0][0];
+    for (int p = 0; p < np; p++) {
+        C v = 0;
+#pragma unroll
+        for (int l = 0; l < N; l++) v += w[0][l] * lt[p * N + l];
+        rmin = v < rmin ? v : rmin;
+    }
+    const C rbar = w[0][0];
+    // targets raised to rel x the cell's mean density / (gamma-1) x its mean energy where the
+    // storage's rounding (FP32) would otherwise undo the limiting
+    const C ep_r = (C)rel * rbar > ep ? (C)rel * rbar : ep;
+    const C ep_p = (C)rel * g1 * w[4][0] > ep ? (C)rel * g1 * w[4][0] : ep;
+    C th1 = C(1);
+    if (rbar != rmin) {
+        const C t = __builtin_fabs((rbar - ep_r) / (rbar - rmin));
+        th1 = t < C(1) ? t : C(1);
+    }
+#pragma unroll
+    for (int l = 1; l < N; l++) w[0][l] *= th1;
+    // pressure: theta_2 = min over the points of tau, the root of P(qbar + tau (q - qbar)) = eps
+    // (Newton-Raphson on rho P - eps rho, a quadratic in tau, kept inside its bracket)
+    const C qb[5] = {w[0][0], w[1][0], w[2][0], w[3][0], w[4][0]};
+    auto gfun = [&](const C d[5], C t, C &dg) {
+        const C rr = qb[0] + t * d[0], mx = qb[1] + t * d[1], my = qb[2] + t * d[2], mz = qb[3] + t * d[3],
+                ee = qb[4] + t * d[4];
+        dg = g1 * (d[0] * ee + rr * d[4] - (mx * d[1] + my * d[2] + mz * d[3])) - ep_p * d[0];
+        return g1 * (rr * ee - C(0.5) * (mx * mx + my * my + mz * mz)) - ep_p * rr;
+    };
+    C th2 = C(1);
+    for (int p = 0; p < np; p++) {
+        C q[5];
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            C v = 0;
+#pragma unroll
+            for (int l = 0; l < N; l++) v += w[i][l] * lt[p * N + l];
+            q[i] = v;
+        }
+        const C pr = g1 * (q[4] - C(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+        if (q[0] > C(0) && pr >= ep_p) continue;
+        C d[5];
+#pragma unroll
+        for (int i = 0; i < 5; i++) d[i] = q[i] - qb[i];
+        C dg0, dg1;
+        const C g0 = gfun(d, C(0), dg0);
+        C tau = C(0);
+        if (g0 > C(0)) {
+            const C gone = gfun(d, C(1), dg1);
+            C lo = C(0), hi = C(1);
+            C t = gone < C(0) ? g0 / (g0 - gone) : C(1);
+            for (int it = 0; it < 60; it++) {
+                C dv;
+                const C v = gfun(d, t, dv);
+                if (v >= C(0)) lo = t;
+                else hi = t;
+                C tn = dv != C(0) ? t - v / dv : C(0.5) * (lo + hi);
+                if (!(tn > lo && tn < hi)) tn = C(0.5) * (lo + hi);
+                if (tn == t || hi - lo <= C(4) * __builtin_fabs(t) * (sizeof(C) == 8 ? C(2.3e-16) : C(1.2e-7))) break;
+                t = tn;
+            }
+            tau = lo;
+        }
+        th2 = tau < th2 ? tau : th2;
+    }
+    if (th1 < C(1) || th2 < C(1)) {
+#pragma unroll
+        for (int i = 0; i < NF; i++)
+#pragma unroll
+            for (int l = 1; l < N; l++) y[base + (long long)(i * N + l) * nx] = w[i][l] * th2;
+        atomicAdd(count, 1ull);
+    }
+}
+
+template <int K>
+static hipError_t launch_limit_k(int prec, void *y, const double *tab, int np, long long nc, int nx, double gamma,
+                                 double eps, unsigned long long *count, hipStream_t s) {
+    const long long nb = (nc + 255) / 256;
+    const int N = Dims<K>::N;
+    if (prec == DG_FP64)
+        hipLaunchKernelGGL((limit_kernel<K, double>), dim3(nb), dim3(256), np * N * 8, s, (double *)y, tab, np, nc, nx,
+                           gamma, eps, 0.0, count);
+    else
+        hipLaunchKernelGGL((limit_kernel<K, float>), dim3(nb), dim3(256), np * N * 4, s, (float *)y, tab, np, nc, nx,
+                           gamma, eps, LIMIT_REL_FP32, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, long long nc, int nx, double gamma,
+                        double eps, unsigned long long *count, hipStream_t s) {
+    switch (k) {
+        case 1: return launch_limit_k<1>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
+        case 2: return launch_limit_k<2>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
+        case 3: return launch_limit_k<3>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // ------------------------------------------------------------------ CFL reduction (Sec. 2.4)
 
 __device__ inline double wave_max(double v) {

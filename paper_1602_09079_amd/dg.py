@@ -16,6 +16,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 DG_FORCING = 1
 DG_CLOSURE = 2
 DG_CHECK_RANGE = 4
+DG_LIMIT = 8
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
                 5: "DG_ERR_STATE"}
 
@@ -24,7 +25,7 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_dt", "dg_step", "dg_totals", "dg_set_forcing", "dg_ou_update", "dg_nmodes", "dg_gauss_nodes",
            "dg_error_string", "dg_set_closure", "dg_closure_fallbacks", "dg_closure_features", "dg_closure_targets",
            "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
-           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize"]
+           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats"]
 
 
 class DGError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
             "dg_column_stats_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
             "dg_column_stats": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
             "dg_standardize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp]),
+            "dg_limiter_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -148,10 +150,12 @@ class Solver:
     """One DG context on the current CUDA (HIP) device and stream."""
 
     def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
-                 forcing=False, check_range=False, closure=False, stream=None):
+                 forcing=False, check_range=False, closure=False, limit=False, stream=None):
         import torch
         if forcing:
             flags |= DG_FORCING
+        if limit:
+            flags |= DG_LIMIT
         if closure:
             flags |= DG_CLOSURE
         if check_range:
@@ -269,6 +273,12 @@ class Solver:
         a = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).astype(np.float32))
              for v in (params, feat_mean, feat_std, out_scale, out_bound)]
         self._check(lib().dg_set_closure(self._ctx, *[v.ctypes.data_as(_fp) for v in a]), "dg_set_closure")
+
+    def limiter_stats(self):
+        """Cells the positivity limiter changed since the previous call."""
+        v = ctypes.c_int64()
+        self._check(lib().dg_limiter_stats(self._ctx, ctypes.byref(v)), "dg_limiter_stats")
+        return v.value
 
     def closure_fallbacks(self):
         v = ctypes.c_int64()

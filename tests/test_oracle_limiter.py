@@ -136,3 +136,13 @@ def test_limited_step_equals_plain_on_positive_states():
     a, _ = O.step(cfg, y, h, 2)
     b, _ = O.step_limited(cfg, y, h, 2)
     np.testing.assert_array_equal(a, b)
+
+
+def test_relative_targets_closed_form():
+    """rel > 0 (single-precision storage) raises the density target to rel * rhobar."""
+    cfg, y = _one_cell_state(1)
+    a, rel = 2.0, 2.0 ** -20
+    y[0, 1, 0, 0, 0] = a
+    rmin = 1.0 - a * math.sqrt(3.0)
+    _, th = O.limit(cfg, y, rel=rel)
+    assert th[0, 0] == pytest.approx((1.0 - rel) / (1.0 - rmin), rel=1e-14)
