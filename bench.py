@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
+    p.add_argument("--no-limiter", action="store_true", help="skip the positivity-limiter timing")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
     return p.parse_args()
@@ -143,6 +144,38 @@ def measure_tier(args, dg, torch, prec, qp_dev, n, k):
     return out
 
 
+def limiter_cost(args, dg, torch, prec, qp_dev, n, k):
+    """Stage launches of the primary tier with the positivity limiter of Sec. 2.5 on the
+    stage input (the paper applies it every stage; the smooth workload never needs it, so this
+    is the cost of checking)."""
+    s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing, limit=True)
+    if not args.no_forcing:
+        nvec, ahat, _ = driving_table(dg)
+        s.set_forcing(nvec, ahat)
+    y = s.project(qp_dev.to(s.dtype))
+    w1 = torch.empty_like(y)
+    w2 = torch.empty_like(y)
+    h = s.dt(y)
+    s.stage(y, y, w1, 0.0, 1.0, h)
+    torch.cuda.synchronize()
+    evs = []
+    for rep in range(max(2, args.steps)):
+        for (y0, yin, out, a, b) in ((y, y, w1, 0.0, 1.0), (y, w1, w2, 0.75, 0.25), (y, w2, w1, 1 / 3, 2 / 3)):
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(s.stream)
+            s.stage(y0, yin, out, a, b, h)
+            eb.record(s.stream)
+            evs.append((ea, eb))
+    torch.cuda.synchronize()
+    ms = sum(ea.elapsed_time(eb) for ea, eb in evs) / len(evs)
+    changed = s.limiter_stats()
+    log(args, f"[bench] {prec} with the positivity limiter: stage {ms:.3f} ms, cells changed {changed}")
+    del s, y, w1, w2
+    torch.cuda.empty_cache()
+    return dict(tier=prec, stage_ms=ms, cells_changed=changed)
+
+
 def cpu_baseline(args, k):
     """Oracle (FP64 C, OpenMP) on a bounded sample: one SSP stage on a cpu_n^3 mesh."""
     import numpy as np
@@ -190,6 +223,10 @@ def main():
     results = {}
     for prec in args.tiers.split(","):
         results[prec] = measure_tier(args, dg, torch, prec, qp, n, k)
+    fp32_grade0 = [p for p in ("bf16x3", "fp32") if p in results]
+    prim0 = args.primary if args.primary != "auto" else max(fp32_grade0 or list(results),
+                                                            key=lambda p: results[p]["dof_updates_per_s"])
+    lim = None if args.no_limiter else limiter_cost(args, dg, torch, prim0, qp, n, k)
     del qp
     torch.cuda.empty_cache()
     if args.copy_calibration > 0:
@@ -245,6 +282,8 @@ def main():
     }
     if "fp64" in results:
         line["speedup_vs_fp64"] = r["dof_updates_per_s"] / results["fp64"]["dof_updates_per_s"]
+    if lim is not None:
+        line["limiter"] = dict(lim, stage_ms_without=r["stage_ms"])
     print(json.dumps(line), flush=True)
 
 

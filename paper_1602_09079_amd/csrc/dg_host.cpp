@@ -385,6 +385,12 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
                         for (int l = 0; l < c->N; l++) lt.push_back(B.phi(l, xi));
                     }
         c->limnp = 3 * m * c->n * c->n;
+        // then max over the points of |phi_l| (mode 0 unused): bounds the deviation from the mean
+        for (int l = 0; l < c->N; l++) {
+            double mx = 0.0;
+            for (int p = 0; l > 0 && p < c->limnp; p++) mx = std::max(mx, std::fabs(lt[(size_t)p * c->N + l]));
+            lt.push_back(mx);
+        }
         if (hipMalloc(&c->limtab, lt.size() * sizeof(double)) != hipSuccess ||
             hipMemcpy(c->limtab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMalloc(&c->limcount, sizeof(unsigned long long)) != hipSuccess ||

@@ -1130,7 +1130,7 @@ __global__ __launch_bounds__(256) void limit_kernel(S *__restrict__ y, const dou
     using C = S;
     extern __shared__ __attribute__((aligned(16))) char lsm[];
     C *lt = reinterpret_cast<C *>(lsm);
-    for (int j = threadIdx.x; j < np * N; j += blockDim.x) lt[j] = (C)tab[j];
+    for (int j = threadIdx.x; j < (np + 1) * N; j += blockDim.x) lt[j] = (C)tab[j];
     __syncthreads();
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= nc) return;
@@ -1142,6 +1142,37 @@ __global__ __launch_bounds__(256) void limit_kernel(S *__restrict__ y, const dou
 #pragma unroll
         for (int l = 0; l < N; l++) w[i][l] = y[base + (long long)(i * N + l) * nx];
     const C g1 = (C)(gamma - 1.0), ep = (C)eps;
+    {
+        // Sufficient test first: with D_i = sum_l |u_il| max_S |phi_l| bounding |q_i - qbar_i| on the
+        // point set, rho >= rbar - D_0 and p >= (gamma-1)(Ebar - D_4 - |m|^2_max / (2 rho_min)) there.
+        // When both bounds clear the targets by more than the rounding of either evaluation, every
+        // point passes, both scaling factors are 1 and the cell is left as it is.
+        C dv[NF];
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            C a = 0;
+#pragma unroll
+            for (int l = 1; l < N; l++) a += __builtin_fabs(w[i][l]) * lt[np * N + l];
+            dv[i] = a;
+        }
+        constexpr C u = sizeof(C) == 8 ? C(1.2e-16) : C(6e-8);  // unit roundoff
+        const C rb = w[0][0];
+        const C tr = (C)rel * rb > ep ? (C)rel * rb : ep;
+        const C tp = (C)rel * g1 * w[4][0] > ep ? (C)rel * g1 * w[4][0] : ep;
+        const C rlo = rb - dv[0];
+        C m2 = 0;
+#pragma unroll
+        for (int i = 1; i < 4; i++) {
+            const C mm = __builtin_fabs(w[i][0]) + dv[i];
+            m2 += mm * mm;
+        }
+        const C kin = C(0.5) * m2 / rlo;
+        const C el = w[4][0] - dv[4];
+        const C plo = g1 * (el - kin);
+        const C slack = C(256) * u * (rb + dv[0]);
+        const C pslack = C(256) * u * g1 * (__builtin_fabs(w[4][0]) + dv[4] + kin);
+        if (rlo > C(2) * tr + slack && plo > C(2) * tp + pslack) return;
+    }
     // density: theta_1 from the minimum over the points
     C rmin = w[0][0];
     for (int p = 0; p < np; p++) {
@@ -1222,10 +1253,10 @@ static hipError_t launch_limit_k(int prec, void *y, const double *tab, int np, l
     const long long nb = (nc + 255) / 256;
     const int N = Dims<K>::N;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((limit_kernel<K, double>), dim3(nb), dim3(256), np * N * 8, s, (double *)y, tab, np, nc, nx,
+        hipLaunchKernelGGL((limit_kernel<K, double>), dim3(nb), dim3(256), (np + 1) * N * 8, s, (double *)y, tab, np, nc, nx,
                            gamma, eps, 0.0, count);
     else
-        hipLaunchKernelGGL((limit_kernel<K, float>), dim3(nb), dim3(256), np * N * 4, s, (float *)y, tab, np, nc, nx,
+        hipLaunchKernelGGL((limit_kernel<K, float>), dim3(nb), dim3(256), (np + 1) * N * 4, s, (float *)y, tab, np, nc, nx,
                            gamma, eps, LIMIT_REL_FP32, count);
     return hipGetLastError();
 }
