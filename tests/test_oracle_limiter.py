@@ -146,3 +146,60 @@ def test_relative_targets_closed_form():
     rmin = 1.0 - a * math.sqrt(3.0)
     _, th = O.limit(cfg, y, rel=rel)
     assert th[0, 0] == pytest.approx((1.0 - rel) / (1.0 - rmin), rel=1e-14)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_each_point_set_reproduces_the_cell_mean(k):
+    """Sec. 2.5: with the GLL weights along the axis and the Gauss weights across it,
+    each of S_x, S_y, S_z integrates a degree-k polynomial exactly, so the cell mean is
+    a convex combination of the values on S (the property the limiter rests on)."""
+    m = 2 if k <= 1 else 3
+    xl, wl = O.gll(m)
+    xg, wg = O.gauss_legendre(k + 1)
+    pts = O.limiter_points(k)
+    nb = m * (k + 1) ** 2
+    rng = np.random.default_rng(70 + k)
+    u = rng.standard_normal(O.nmodes(k))
+    q = _values_at(k, u, pts)
+
+    def wt(nodes, weights, v):
+        j = int(np.argmin(np.abs(nodes - v)))
+        assert abs(nodes[j] - v) < 1e-14
+        return weights[j]
+
+    for a in range(3):
+        s = 0.0
+        for p in range(a * nb, (a + 1) * nb):
+            w = 1.0
+            for o in range(3):
+                w *= wt(xl, wl, pts[p, o]) if o == a else wt(xg, wg, pts[p, o])
+            assert w > 0
+            s += w * q[p] / 8.0
+        assert s == pytest.approx(u[0], abs=1e-13)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter_is_not_stricter_than_needed(k):
+    """The scaling factors are the largest that reach the targets: where theta_2 < 1 the
+    minimum pressure over S after limiting equals eps; where only theta_1 < 1 the minimum
+    density over S equals eps."""
+    cfg = O.make_cfg(k, (4, 3, 3), gamma=G)
+    rng = np.random.default_rng(131 + k)
+    y = rng.standard_normal(O.state_shape(cfg)) * 0.6
+    y[0, 0] = 1.0 + 0.2 * rng.random(y[0, 0].shape)
+    y[1:4, 0] = 0.3 * rng.standard_normal(y[1:4, 0].shape)
+    y[4, 0] = 2.0 + rng.random(y[4, 0].shape)
+    # the first z layer: density variation only, at rest with a large uniform energy
+    y[1:, :, 0] = 0.0
+    y[4, 0, 0] = 10.0
+    y[0, 1:, 0] *= 3.0
+    yl, th = O.limit(cfg, y)
+    N = O.nmodes(k)
+    phi = np.array([O.basis(k, p) for p in O.limiter_points(k)])
+    q = np.einsum("pl,ilc->ipc", phi, yl.reshape(5, N, -1))
+    p = (G - 1.0) * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0])
+    both = th[:, 1] < 1.0
+    only1 = (th[:, 0] < 1.0) & ~both
+    assert both.any() and only1.any()
+    np.testing.assert_allclose(p[:, both].min(axis=0), EPS, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(q[0][:, only1].min(axis=0), EPS, rtol=0, atol=1e-13)
