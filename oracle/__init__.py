@@ -341,3 +341,24 @@ def step_limited(cfg, y, h=0.0, nsteps=1, t=0.0, frc=None, eps=LIMIT_EPS):
     lib().orc_step_limited(ctypes.byref(cfg), _d(y), ctypes.c_double(h), nsteps, ctypes.byref(tt), _fptr(frc),
                            ctypes.c_double(eps))
     return y, tt.value
+
+
+def isothermal_reset(cfg, y, cs=1.0, rho0=1.0):
+    """Sec. 3.2.  Returns (copy of y with the energy weights reset, dissipated energy)."""
+    y = np.array(y, dtype=np.float64, copy=True, order="C")
+    L = lib()
+    L.orc_isothermal_reset.restype = ctypes.c_double
+    d = L.orc_isothermal_reset(ctypes.byref(cfg), _d(y), ctypes.c_double(cs), ctypes.c_double(rho0))
+    return y, d
+
+
+def step_isothermal(cfg, y, h=0.0, nsteps=1, t=0.0, frc=None, cs=1.0, rho0=1.0, limit=False, eps=LIMIT_EPS):
+    """nsteps steps each followed by the reset (and the limiter with limit=True).
+    Returns (y, t, dissipated energy summed over the steps)."""
+    y = np.array(y, dtype=np.float64, copy=True, order="C")
+    tt = ctypes.c_double(t)
+    dis = ctypes.c_double(0.0)
+    lib().orc_step_isothermal(ctypes.byref(cfg), _d(y), ctypes.c_double(h), nsteps, ctypes.byref(tt), _fptr(frc),
+                              ctypes.c_double(cs), ctypes.c_double(rho0), int(bool(limit)), ctypes.c_double(eps),
+                              ctypes.byref(dis))
+    return y, tt.value, dis.value

@@ -868,3 +868,65 @@ void orc_step_limited(const orc_cfg *cfg, double *y, double dt, int nsteps, doub
     free(y1);
     free(y2);
 }
+
+/* ------------------------------------------------------------------ */
+/* Sec. 3.2: isothermal reset                                          */
+/* ------------------------------------------------------------------ */
+
+static double mean_internal(const double *y, int N, size_t nc, size_t K)
+{
+    double r = y[((size_t)0 * N) * nc + K];
+    double mx = y[((size_t)1 * N) * nc + K], my = y[((size_t)2 * N) * nc + K], mz = y[((size_t)3 * N) * nc + K];
+    double E = y[((size_t)4 * N) * nc + K];
+    return E - 0.5 * (mx * mx + my * my + mz * mz) / r;
+}
+
+double orc_isothermal_reset(const orc_cfg *cfg, double *y, double cs, double rho0)
+{
+    tables t;
+    tables_init(&t, cfg->k);
+    size_t nc = ncells_of(cfg);
+    int N = t.N, Q = t.Q;
+    double vol = cfg->box[0] * cfg->box[1] * cfg->box[2] / (double)nc;
+    double gm1 = cfg->gamma - 1.0;
+    double *dis = malloc(sizeof(double) * nc);
+#pragma omp parallel for schedule(static)
+    for (size_t K = 0; K < nc; K++) {
+        double before = mean_internal(y, N, nc, K);
+        double e[GMAX * GMAX * GMAX];
+        for (int q = 0; q < Q; q++) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < 4; i++)
+                for (int l = 0; l < N; l++) v[i] += y[((size_t)i * N + l) * nc + K] * t.phi_v[q * N + l];
+            double rho = v[0];
+            double eps = cs * cs / gm1 * pow(rho / rho0, gm1);
+            e[q] = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho + rho * eps;
+        }
+        for (int l = 0; l < N; l++) {
+            double s = 0.0;
+            for (int q = 0; q < Q; q++) s += e[q] * t.phi_v[q * N + l] * t.w_v[q];
+            y[((size_t)4 * N + l) * nc + K] = s / 8.0;
+        }
+        dis[K] = vol * (before - mean_internal(y, N, nc, K));
+    }
+    double total = 0.0;
+    for (size_t K = 0; K < nc; K++) total += dis[K];
+    free(dis);
+    tables_free(&t);
+    return total;
+}
+
+void orc_step_isothermal(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t,
+                         const orc_forcing *frc, double cs, double rho0, int limit, double eps,
+                         double *dissipated)
+{
+    for (int it = 0; it < nsteps; it++) {
+        if (limit)
+            orc_step_limited(cfg, y, dt, 1, t, frc, eps);
+        else
+            orc_step(cfg, y, dt, 1, t, frc);
+        double d = orc_isothermal_reset(cfg, y, cs, rho0);
+        if (dissipated) *dissipated += d;
+        if (limit) orc_limit(cfg, y, eps, 0.0, NULL);
+    }
+}

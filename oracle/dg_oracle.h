@@ -113,6 +113,22 @@ double orc_dt_limited(const orc_cfg *cfg, const double *y);
 void   orc_step_limited(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t, const orc_forcing *frc,
                         double eps);
 
+/* ---- Sec. 3.2: isothermal reset and the dissipated energy ----
+ * After a time step the specific internal energy
+ *   eps(rho) = cs^2/(gamma-1) (rho/rho0)^(gamma-1)
+ * is imposed at the (k+1)^3 Gauss points of every cell: the energy weights become
+ *   w_E,l = (1/8) sum_q (|m_q|^2/(2 rho_q) + rho_q eps(rho_q)) phi_l(xi_q) omega_q
+ * with rho_q, m_q from the cell's current weights (rho and m unchanged).
+ * Returns the dissipated energy sum_K |K| (rhoe_before - rhoe_after), where per
+ * cell rhoe = w_E,0 - |w_m,0|^2 / (2 w_rho,0) (the cell-mean internal energy). */
+double orc_isothermal_reset(const orc_cfg *cfg, double *y, double cs, double rho0);
+/* nsteps SSP-RK3 steps, each followed by the reset; with limit != 0 the limiter (eps, rel = 0)
+ * is applied to every stage input as in orc_step_limited and once more after the reset, and the
+ * limited time step is used.  dissipated (may be NULL) accumulates the reset's return values. */
+void orc_step_isothermal(const orc_cfg *cfg, double *y, double dt, int nsteps, double *t,
+                         const orc_forcing *frc, double cs, double rho0, int limit, double eps,
+                         double *dissipated);
+
 /* ---- closure support (not in the paper) ---- */
 /* exact L2 restriction of a degree-kf state on (2n)^3 cells onto degree-kc on n^3 cells */
 void orc_restrict(int kf, int kc, const int32_t nc[3], const double *yf, double *yc);
