@@ -61,7 +61,8 @@ enum {
     DG_FORCING = 1u,      /* add the driving source term of Sec. 3.1 (needs dg_set_forcing) */
     DG_CLOSURE = 2u,      /* k = 1 only: add the learned closure correction (needs dg_set_closure) */
     DG_CHECK_RANGE = 4u,  /* dg_step checks cell means for rho>0, p>0, finite after each step */
-    DG_LIMIT = 8u         /* positivity limiter of Sec. 2.5 on every stage input (see dg_limiter_stats) */
+    DG_LIMIT = 8u,        /* positivity limiter of Sec. 2.5 on every stage input (see dg_limiter_stats) */
+    DG_ISOTHERMAL = 16u   /* dg_step: isothermal reset of Sec. 3.2 after every step (needs dg_set_isothermal) */
 };
 
 typedef struct {
@@ -71,7 +72,7 @@ typedef struct {
     double gamma;       /* adiabatic index, > 1 */
     double cfl;         /* Courant factor C of Sec. 2.4, in (0, 1] */
     int32_t precision;  /* a dg_precision value */
-    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT */
+    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL */
 } dg_config;
 
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
@@ -265,6 +266,33 @@ dg_status dg_gauss_nodes(int32_t n, double *xi);   /* n-point Gauss-Legendre nod
 
 /* Last error message of ctx ("" if none); a static string for ctx == NULL. */
 const char *dg_error_string(const dg_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Isothermal reset and dissipation measurement (Sec. 3.2).
+ * The gas is an ideal gas with gamma close to 1 (the paper: 1.01); after each
+ * step the specific internal energy is reset to
+ *   eps(rho) = cs^2/(gamma-1) (rho/rho0)^(gamma-1)
+ * at the (k+1)^3 Gauss points of every cell, and the energy weights become
+ *   w_E,l = (1/8) sum_q (|m_q|^2/(2 rho_q) + rho_q eps(rho_q)) phi_l(xi_q) omega_q
+ * (rho_q, m_q from the current weights; the density and momentum weights are
+ * unchanged).  The dissipated energy of a reset is
+ *   sum_K |K| (rhoe_before - rhoe_after),  rhoe = w_E,0 - |w_m,0|^2/(2 w_rho,0),
+ * accumulated on the device in FP64 with a fixed summation order.  The
+ * arithmetic at the points runs in the storage precision.  With DG_ISOTHERMAL
+ * dg_step resets after every step and then, with DG_LIMIT, applies the
+ * positivity limiter to the reset state.
+ *
+ * Set the reset's sound speed cs and reference density rho0 (both finite and
+ * > 0, else DG_ERR_ARG); allocates the partial-sum buffer on the first call. */
+dg_status dg_set_isothermal(dg_ctx *ctx, double cs, double rho0);
+
+/* One reset of y (DEVICE, in place), as dg_step does after a step; adds to the
+ * dissipation account.  DG_ERR_STATE before dg_set_isothermal.  Asynchronous. */
+dg_status dg_isothermal_reset(dg_ctx *ctx, void *y);
+
+/* Dissipated energy accumulated since the previous call (0 if none), then reset.
+ * out: HOST.  Synchronises. */
+dg_status dg_dissipated(dg_ctx *ctx, double *out);
 
 #ifdef __cplusplus
 }

@@ -322,7 +322,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
-    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT)) return DG_ERR_ARG;
+    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL)) return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     {
@@ -358,14 +358,19 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     // projection table: phi_l(xi_q) w_q / 8
     {
         const Basis B(cfg->k);
-        std::vector<double> pt((size_t)c->Q * c->N);
+        std::vector<double> pt((size_t)c->Q * c->N), ph((size_t)c->Q * c->N);
         double xi[3];
         for (int q = 0; q < c->Q; q++) {
             B.point(q, xi);
-            for (int l = 0; l < c->N; l++) pt[(size_t)q * c->N + l] = B.phi(l, xi) * B.weight(q) / 8.0;
+            for (int l = 0; l < c->N; l++) {
+                ph[(size_t)q * c->N + l] = B.phi(l, xi);
+                pt[(size_t)q * c->N + l] = B.phi(l, xi) * B.weight(q) / 8.0;
+            }
         }
         if (hipMalloc(&c->ptab, pt.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
         if (hipMemcpy(c->ptab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+        if (hipMalloc(&c->phitab, ph.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
+        if (hipMemcpy(c->phitab, ph.data(), ph.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
     }
     if (cfg->flags & DG_LIMIT) {
         // phi_l at the limiter points: GLL nodes along one axis, Gauss nodes along the others
@@ -443,21 +448,12 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
 
 dg_status dg_destroy(dg_ctx *c) {
     if (!c) return DG_OK;
-    if (c->tables) hipFree(c->tables);
-    if (c->ptab) hipFree(c->ptab);
-    if (c->slots) hipFree(c->slots);
-    if (c->flag) hipFree(c->flag);
-    if (c->partials) hipFree(c->partials);
-    if (c->fmodes) hipFree(c->fmodes);
-    if (c->acache) hipFree(c->acache);
-    if (c->limtab) hipFree(c->limtab);
-    if (c->limcount) hipFree(c->limcount);
-    if (c->clo) hipFree(c->clo);
-    if (c->corr) hipFree(c->corr);
-    if (c->clo_partials) hipFree(c->clo_partials);
-    if (c->clo_fallbacks) hipFree(c->clo_fallbacks);
-    for (int j = 0; j < 4; j++)
-        if (c->restrict_tab[j]) hipFree(c->restrict_tab[j]);
+    void *bufs[] = {c->tables, c->ptab,      c->slots,        c->flag,     c->partials,     c->fmodes,
+                    c->acache, c->limtab,    c->phitab,       c->iso_partials, c->limcount, c->clo,
+                    c->corr,   c->clo_partials, c->clo_fallbacks, c->restrict_tab[0], c->restrict_tab[1],
+                    c->restrict_tab[2], c->restrict_tab[3]};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);  // release what was allocated; a failure here has no remedy
     delete c;
     return DG_OK;
 }
@@ -593,11 +589,65 @@ dg_status dg_dt(dg_ctx *c, const void *y, double *dt) {
     return DG_OK;
 }
 
+static hipError_t run_reset(dg_ctx *c, void *y) {
+    const double gm1 = c->cfg.gamma - 1.0;
+    return launch_reset(c->cfg.k, c->cfg.precision, y, c->phitab, c->ptab, c->ncells, c->cfg.n[0], gm1,
+                        c->iso_cs * c->iso_cs / gm1, c->iso_rho0, c->h[0] * c->h[1] * c->h[2], c->iso_partials,
+                        c->slots + 4, c->stream);
+}
+
+dg_status dg_set_isothermal(dg_ctx *c, double cs, double rho0) {
+    if (!c) return DG_ERR_ARG;
+    if (!(cs > 0.0) || !(rho0 > 0.0) || !std::isfinite(cs) || !std::isfinite(rho0)) {
+        c->err = "dg_set_isothermal: cs and rho0 must be finite and > 0";
+        return DG_ERR_ARG;
+    }
+    if (!c->iso_partials && hipMalloc(&c->iso_partials, reset_partials(c->ncells) * sizeof(double)) != hipSuccess) {
+        c->iso_partials = nullptr;
+        c->err = "dg_set_isothermal: hipMalloc failed";
+        return DG_ERR_HIP;
+    }
+    c->iso_cs = cs;
+    c->iso_rho0 = rho0;
+    c->have_iso = true;
+    return DG_OK;
+}
+
+dg_status dg_isothermal_reset(dg_ctx *c, void *y) {
+    if (!c) return DG_ERR_ARG;
+    if (!y) {
+        c->err = "dg_isothermal_reset: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    if (!c->have_iso) {
+        c->err = "dg_isothermal_reset: dg_set_isothermal has not been called";
+        return DG_ERR_STATE;
+    }
+    HIPCHK(c, run_reset(c, y));
+    return DG_OK;
+}
+
+dg_status dg_dissipated(dg_ctx *c, double *out) {
+    if (!c) return DG_ERR_ARG;
+    if (!out) {
+        c->err = "dg_dissipated: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    HIPCHK(c, hipMemcpyAsync(out, c->slots + 4, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(c->slots + 4), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
 dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, double *t_inout) {
     if (!c) return DG_ERR_ARG;
     if (!y || !work || nsteps < 0) {
         c->err = "dg_step: NULL pointer or negative step count";
         return DG_ERR_ARG;
+    }
+    if ((c->cfg.flags & DG_ISOTHERMAL) && !c->have_iso) {
+        c->err = "dg_step: DG_ISOTHERMAL needs dg_set_isothermal first";
+        return DG_ERR_STATE;
     }
     const size_t sb = dg_state_count(c) * elem_bytes(c);
     void *w1 = work;
@@ -618,6 +668,12 @@ dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, dou
         if ((st = run_stage(c, y, y, w1, 0.0, 1.0, dt, 1, false, false)) != DG_OK) return st;
         if ((st = run_stage(c, y, w1, w2, 0.75, 0.25, dt, 1, false)) != DG_OK) return st;
         if ((st = run_stage(c, y, w2, y, 1.0 / 3.0, 2.0 / 3.0, dt, 1, dev_dt && t_inout)) != DG_OK) return st;
+        if (c->cfg.flags & DG_ISOTHERMAL) {  // Sec. 3.2: reset after the step, then the limiter
+            HIPCHK(c, run_reset(c, y));
+            if (lim)
+                HIPCHK(c, launch_limit(c->cfg.k, c->cfg.precision, y, c->limtab, c->limnp, c->ncells, c->cfg.n[0],
+                                       c->cfg.gamma, LIMIT_EPS, c->limcount, c->stream));
+        }
         if (check) {
             int flag = 0;
             HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));

@@ -1271,6 +1271,122 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
     }
 }
 
+// ------------------------------------------------------------------ isothermal reset (Sec. 3.2)
+
+__device__ inline float pow_d(float x, float p) { return powf(x, p); }
+__device__ inline double pow_d(double x, double p) { return pow(x, p); }
+
+constexpr int RESET_THREADS = 256;
+
+// One thread per cell (x consecutive over the lanes).  rho and m are evaluated at the (k+1)^3
+// Gauss points, the energy density |m|^2/(2 rho) + rho eps(rho), eps = ce (rho/rho0)^(gamma-1),
+// ce = cs^2/(gamma-1), is projected back onto the energy weights, and the block's sum of
+// |K| (rhoe_before - rhoe_after) (cell means, FP64) goes to partials[block].
+template <int K, class S>
+__global__ __launch_bounds__(RESET_THREADS) void reset_kernel(S *__restrict__ y, const double *__restrict__ phi,
+                                                              const double *__restrict__ proj, long long nc, int nx,
+                                                              double gm1, double ce, double rho0, double vol,
+                                                              double *__restrict__ partials) {
+    constexpr int N = Dims<K>::N, Q = Dims<K>::Q;
+    using C = S;
+    extern __shared__ __attribute__((aligned(16))) char lsm[];
+    C *lp = reinterpret_cast<C *>(lsm);  // phi_l(xi_q)          [Q][N]
+    C *lq = lp + Q * N;                   // phi_l(xi_q) w_q / 8  [Q][N]
+    __shared__ double red[RESET_THREADS];
+    for (int j = threadIdx.x; j < Q * N; j += blockDim.x) {
+        lp[j] = (C)phi[j];
+        lq[j] = (C)proj[j];
+    }
+    __syncthreads();
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double dis = 0.0;
+    if (cell < nc) {
+        const long long r = cell / nx;
+        const long long base = r * (long long)NF * N * nx + (cell - r * nx);
+        C w[4][N];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int l = 0; l < N; l++) w[i][l] = y[base + (long long)(i * N + l) * nx];
+        const C e_old = y[base + (long long)(4 * N) * nx];
+        C acc[N];
+#pragma unroll
+        for (int l = 0; l < N; l++) acc[l] = 0;
+        const C g = (C)gm1, cc = (C)ce, ir0 = C(1) / (C)rho0;
+        for (int q = 0; q < Q; q++) {
+            C v[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                C t = 0;
+#pragma unroll
+                for (int l = 0; l < N; l++) t += w[i][l] * lp[q * N + l];
+                v[i] = t;
+            }
+            const C rho = v[0];
+            const C e = C(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho + cc * rho * pow_d(rho * ir0, g);
+#pragma unroll
+            for (int l = 0; l < N; l++) acc[l] += e * lq[q * N + l];
+        }
+#pragma unroll
+        for (int l = 0; l < N; l++) y[base + (long long)(4 * N + l) * nx] = acc[l];
+        const double rb = (double)w[0][0], kin = 0.5 * ((double)w[1][0] * (double)w[1][0] +
+                                                        (double)w[2][0] * (double)w[2][0] +
+                                                        (double)w[3][0] * (double)w[3][0]) / rb;
+        dis = vol * (((double)e_old - kin) - ((double)acc[0] - kin));
+    }
+    red[threadIdx.x] = dis;
+    __syncthreads();
+    for (int h = RESET_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// acc += sum of p[0..n) in a fixed order (one workgroup: contiguous chunks per thread, then a tree)
+__global__ __launch_bounds__(256) void sum_into_kernel(const double *__restrict__ p, long long n, double *acc) {
+    __shared__ double red[256];
+    const long long ch = (n + 255) / 256;
+    const long long lo = threadIdx.x * ch, hi = lo + ch < n ? lo + ch : n;
+    double s = 0.0;
+    for (long long j = lo; j < hi; j++) s += p[j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *acc += red[0];
+}
+
+long long reset_partials(long long nc) { return (nc + RESET_THREADS - 1) / RESET_THREADS; }
+
+template <int K>
+static hipError_t launch_reset_k(int prec, void *y, const double *phi, const double *proj, long long nc, int nx,
+                                 double gm1, double ce, double rho0, double vol, double *partials, double *acc,
+                                 hipStream_t s) {
+    const long long nb = reset_partials(nc);
+    const int QN = Dims<K>::Q * Dims<K>::N;
+    if (prec == DG_FP64)
+        hipLaunchKernelGGL((reset_kernel<K, double>), dim3(nb), dim3(RESET_THREADS), 2 * QN * 8, s, (double *)y, phi,
+                           proj, nc, nx, gm1, ce, rho0, vol, partials);
+    else
+        hipLaunchKernelGGL((reset_kernel<K, float>), dim3(nb), dim3(RESET_THREADS), 2 * QN * 4, s, (float *)y, phi,
+                           proj, nc, nx, gm1, ce, rho0, vol, partials);
+    hipLaunchKernelGGL(sum_into_kernel, dim3(1), dim3(256), 0, s, partials, nb, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int k, int prec, void *y, const double *phi, const double *proj, long long nc, int nx,
+                        double gm1, double ce, double rho0, double vol, double *partials, double *acc, hipStream_t s) {
+    switch (k) {
+        case 1: return launch_reset_k<1>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        case 2: return launch_reset_k<2>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        case 3: return launch_reset_k<3>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // ------------------------------------------------------------------ CFL reduction (Sec. 2.4)
 
 __device__ inline double wave_max(double v) {

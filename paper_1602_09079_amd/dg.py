@@ -17,6 +17,7 @@ DG_FORCING = 1
 DG_CLOSURE = 2
 DG_CHECK_RANGE = 4
 DG_LIMIT = 8
+DG_ISOTHERMAL = 16
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
                 5: "DG_ERR_STATE"}
 
@@ -25,7 +26,8 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_dt", "dg_step", "dg_totals", "dg_set_forcing", "dg_ou_update", "dg_nmodes", "dg_gauss_nodes",
            "dg_error_string", "dg_set_closure", "dg_closure_fallbacks", "dg_closure_features", "dg_closure_targets",
            "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
-           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats"]
+           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats",
+           "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated"]
 
 
 class DGError(RuntimeError):
@@ -86,6 +88,9 @@ def lib():
             "dg_column_stats": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
             "dg_standardize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp]),
             "dg_limiter_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
+            "dg_set_isothermal": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+            "dg_isothermal_reset": (ctypes.c_int, [_vp, _vp]),
+            "dg_dissipated": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -150,8 +155,10 @@ class Solver:
     """One DG context on the current CUDA (HIP) device and stream."""
 
     def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
-                 forcing=False, check_range=False, closure=False, limit=False, stream=None):
+                 forcing=False, check_range=False, closure=False, limit=False, isothermal=False, stream=None):
         import torch
+        if isothermal:
+            flags |= DG_ISOTHERMAL
         if forcing:
             flags |= DG_FORCING
         if limit:
@@ -278,6 +285,22 @@ class Solver:
         """Cells the positivity limiter changed since the previous call."""
         v = ctypes.c_int64()
         self._check(lib().dg_limiter_stats(self._ctx, ctypes.byref(v)), "dg_limiter_stats")
+        return v.value
+
+    def set_isothermal(self, cs=1.0, rho0=1.0):
+        """Sound speed and reference density of the isothermal reset."""
+        self._check(lib().dg_set_isothermal(self._ctx, ctypes.c_double(cs), ctypes.c_double(rho0)),
+                    "dg_set_isothermal")
+
+    def isothermal_reset(self, y):
+        """One reset of y in place (its dissipated energy goes to dissipated())."""
+        self._check(lib().dg_isothermal_reset(self._ctx, self._ptr(y, self.state_shape())), "dg_isothermal_reset")
+        return y
+
+    def dissipated(self):
+        """Dissipated energy of the resets since the previous call."""
+        v = ctypes.c_double()
+        self._check(lib().dg_dissipated(self._ctx, ctypes.byref(v)), "dg_dissipated")
         return v.value
 
     def closure_fallbacks(self):

@@ -1,0 +1,120 @@
+"""GPU parity of the isothermal reset and the dissipation measurement
+(arXiv 1602.09079, Sec. 3.2) against the FP64 oracle.
+
+* one reset (dg_isothermal_reset) of a turbulent state with a perturbed energy:
+  density and momentum weights bitwise unchanged; energy weights within 1e-13
+  (FP64) / 2e-6 (FP32 storage) of the largest energy weight; the dissipated
+  energy within 1e-10 (FP64) / 1e-4 (FP32) relative;
+* dg_step with DG_ISOTHERMAL (gamma = 1.01, reset after every step), also with
+  DG_LIMIT and the driving, against the oracle's steps;
+* the account: dg_dissipated returns the sum since the previous call, then 0;
+* errors: the flag without dg_set_isothermal, invalid cs / rho0.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.layout import from_abi, to_abi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+G = 1.01
+
+
+@pytest.fixture(scope="module")
+def dgm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_09079_amd import dg
+    dg.lib()
+    return dg
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(to_abi(a))).to(device="cuda", dtype=dtype)
+
+
+def host(y):
+    return from_abi(y.cpu().double().numpy())
+
+
+def hot_state(k, n, seed, mach=0.4):
+    """Turbulence surrogate at gamma = 1.01 whose energy weights are perturbed by a few percent
+    (a gas heated away from the isothermal level, with in-cell structure)."""
+    from paper_1602_09079_amd import synth
+    cfg = O.make_cfg(k, n, gamma=G)
+    y = O.project(cfg, synth.turbulence(n, O.gauss_legendre(k + 1)[0], seed=seed, mach=mach).numpy())
+    rng = np.random.default_rng(seed)
+    y[4] *= 1.0 + 0.03 * rng.random(y[4].shape)
+    return cfg, y
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_reset_parity(dgm, k, prec):
+    n = (19, 5, 4)  # 380 cells: one full block of 256 and a ragged one
+    cfg, y = hot_state(k, n, 60 + k)
+    cs, rho0 = 1.1, 0.9
+    ystore = y if prec == "fp64" else y.astype(np.float32).astype(np.float64)
+    want, dwant = O.isothermal_reset(cfg, ystore, cs, rho0)
+    s = dgm.Solver(k, n, gamma=G, precision=prec)
+    s.set_isothermal(cs, rho0)
+    yd = dev(y, s.dtype)
+    s.isothermal_reset(yd)
+    got = host(yd)
+    np.testing.assert_array_equal(got[:4], ystore[:4])
+    scale = np.abs(want[4]).max()
+    err = np.abs(got[4] - want[4]).max() / scale
+    assert err <= (1e-13 if prec == "fp64" else 2e-6), err
+    d = s.dissipated()
+    assert d == pytest.approx(dwant, rel=1e-10 if prec == "fp64" else 1e-4)
+    assert s.dissipated() == 0.0
+
+
+@pytest.mark.parametrize("flags", ["plain", "limit", "forcing"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_steps_with_reset_parity(dgm, prec, flags):
+    k, n = 2, (12, 6, 5)
+    cfg, y = hot_state(k, n, 71)
+    cs = 1.0
+    frc = None
+    kw = {}
+    if flags == "limit":
+        kw["limit"] = True
+    s = dgm.Solver(k, n, gamma=G, precision=prec, isothermal=True, forcing=flags == "forcing", **kw)
+    s.set_isothermal(cs, 1.0)
+    if flags == "forcing":
+        from paper_1602_09079_amd import synth
+        nvec = synth.forcing_modes(1.0, 3.0)
+        rng = np.random.default_rng(5)
+        ahat = rng.standard_normal((len(nvec), 3, 2)) * 0.5
+        s.set_forcing(nvec, ahat)
+        frc = O.ForcingTable(nvec, ahat)
+    yd = dev(y, s.dtype)
+    h = 0.5 * O.dt(cfg, y)
+    s.step(yd, 3, h)
+    ystore = y if prec == "fp64" else y.astype(np.float32).astype(np.float64)
+    want, _, dwant = O.step_isothermal(cfg, ystore, h, 3, frc=frc, cs=cs, rho0=1.0, limit=flags == "limit")
+    g = host(yd).reshape(5, -1)
+    w = want.reshape(5, -1)
+    err = np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)
+    assert np.all(err <= (1e-11 if prec == "fp64" else 1e-5)), err
+    assert s.dissipated() == pytest.approx(dwant, rel=1e-8 if prec == "fp64" else 2e-3)
+
+
+def test_reset_errors(dgm):
+    s = dgm.Solver(1, 4, gamma=G, precision="fp64", isothermal=True)
+    y = torch.ones(s.state_shape(), dtype=torch.float64, device="cuda")
+    with pytest.raises(dgm.DGError) as e:
+        s.step(y, 1, 1e-3)
+    assert e.value.status == dgm.DG_ERR_STATE
+    with pytest.raises(dgm.DGError) as e:
+        s.isothermal_reset(y)
+    assert e.value.status == dgm.DG_ERR_STATE
+    for cs, r0 in ((0.0, 1.0), (1.0, -1.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        with pytest.raises(dgm.DGError) as e:
+            s.set_isothermal(cs, r0)
+        assert e.value.status == dgm.DG_ERR_ARG
+    assert s.dissipated() == 0.0
