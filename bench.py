@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
-    p.add_argument("--no-limiter", action="store_true", help="skip the positivity-limiter timing")
+    p.add_argument("--no-limiter", action="store_true", help="skip the limiter and isothermal-reset timings")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
     return p.parse_args()
@@ -176,6 +176,33 @@ def limiter_cost(args, dg, torch, prec, qp_dev, n, k):
     return dict(tier=prec, stage_ms=ms, cells_changed=changed)
 
 
+def reset_cost(args, dg, torch, prec, qp_dev, n, k):
+    """The isothermal reset of Sec. 3.2 (once per step in the paper's runs) on the benchmark state:
+    average launch time and its rate over the algorithmic bytes (reads rho, m and the energy mean,
+    writes the energy weights)."""
+    s = dg.Solver(k, n, precision=prec)
+    s.set_isothermal(1.0, 1.0)
+    y = s.project(qp_dev.to(s.dtype))
+    s.isothermal_reset(y)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    ea = torch.cuda.Event(enable_timing=True)
+    eb = torch.cuda.Event(enable_timing=True)
+    ea.record(s.stream)
+    for _ in range(reps):
+        s.isothermal_reset(y)
+    eb.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ea.elapsed_time(eb) / reps
+    el = 8 if prec == "fp64" else 4
+    alg = (5 * s.N + 1) * el * n ** 3
+    s.dissipated()
+    log(args, f"[bench] {prec} isothermal reset: {ms:.3f} ms, {alg / ms / 1e6:.0f} GB/s algorithmic")
+    del s, y
+    torch.cuda.empty_cache()
+    return dict(tier=prec, reset_ms=ms, algorithmic_GBs=alg / ms / 1e6, hbm_frac=alg / ms / 1e6 / HBM_PEAK_GBS)
+
+
 def cpu_baseline(args, k):
     """Oracle (FP64 C, OpenMP) on a bounded sample: one SSP stage on a cpu_n^3 mesh."""
     import numpy as np
@@ -227,6 +254,7 @@ def main():
     prim0 = args.primary if args.primary != "auto" else max(fp32_grade0 or list(results),
                                                             key=lambda p: results[p]["dof_updates_per_s"])
     lim = None if args.no_limiter else limiter_cost(args, dg, torch, prim0, qp, n, k)
+    iso = None if args.no_limiter else reset_cost(args, dg, torch, prim0, qp, n, k)
     del qp
     torch.cuda.empty_cache()
     if args.copy_calibration > 0:
@@ -284,6 +312,8 @@ def main():
         line["speedup_vs_fp64"] = r["dof_updates_per_s"] / results["fp64"]["dof_updates_per_s"]
     if lim is not None:
         line["limiter"] = dict(lim, stage_ms_without=r["stage_ms"])
+    if iso is not None:
+        line["isothermal_reset"] = iso
     print(json.dumps(line), flush=True)
 
 

@@ -358,19 +358,17 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     // projection table: phi_l(xi_q) w_q / 8
     {
         const Basis B(cfg->k);
-        std::vector<double> pt((size_t)c->Q * c->N), ph((size_t)c->Q * c->N);
+        std::vector<double> pt((size_t)c->Q * c->N);
         double xi[3];
         for (int q = 0; q < c->Q; q++) {
             B.point(q, xi);
-            for (int l = 0; l < c->N; l++) {
-                ph[(size_t)q * c->N + l] = B.phi(l, xi);
-                pt[(size_t)q * c->N + l] = B.phi(l, xi) * B.weight(q) / 8.0;
-            }
+            for (int l = 0; l < c->N; l++) pt[(size_t)q * c->N + l] = B.phi(l, xi) * B.weight(q) / 8.0;
         }
         if (hipMalloc(&c->ptab, pt.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
         if (hipMemcpy(c->ptab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
-        if (hipMalloc(&c->phitab, ph.size() * 8) != hipSuccess) return fail(DG_ERR_HIP);
-        if (hipMemcpy(c->phitab, ph.data(), ph.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+        for (int u = 0; u <= cfg->k; u++)
+            for (int a = 0; a < c->n; a++) c->leg1d.p[u][a] = leg(u, B.xg[a]);
+        for (int a = 0; a < c->n; a++) c->leg1d.w[a] = B.wg[a];
     }
     if (cfg->flags & DG_LIMIT) {
         // phi_l at the limiter points: GLL nodes along one axis, Gauss nodes along the others
@@ -449,7 +447,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
 dg_status dg_destroy(dg_ctx *c) {
     if (!c) return DG_OK;
     void *bufs[] = {c->tables, c->ptab,      c->slots,        c->flag,     c->partials,     c->fmodes,
-                    c->acache, c->limtab,    c->phitab,       c->iso_partials, c->limcount, c->clo,
+                    c->acache, c->limtab,    c->iso_partials, c->limcount, c->clo,
                     c->corr,   c->clo_partials, c->clo_fallbacks, c->restrict_tab[0], c->restrict_tab[1],
                     c->restrict_tab[2], c->restrict_tab[3]};
     for (void *b : bufs)
@@ -591,7 +589,7 @@ dg_status dg_dt(dg_ctx *c, const void *y, double *dt) {
 
 static hipError_t run_reset(dg_ctx *c, void *y) {
     const double gm1 = c->cfg.gamma - 1.0;
-    return launch_reset(c->cfg.k, c->cfg.precision, y, c->phitab, c->ptab, c->ncells, c->cfg.n[0], gm1,
+    return launch_reset(c->cfg.k, c->cfg.precision, y, c->leg1d, c->ncells, c->cfg.n[0], gm1,
                         c->iso_cs * c->iso_cs / gm1, c->iso_rho0, c->h[0] * c->h[1] * c->h[2], c->iso_partials,
                         c->slots + 4, c->stream);
 }

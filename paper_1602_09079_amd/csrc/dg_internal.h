@@ -82,9 +82,13 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
                         double eps, unsigned long long *count, hipStream_t s);
 // isothermal reset of Sec. 3.2: energy weights re-projected in place; the dissipated energy
 // (FP64, fixed order) is added to *acc.  partials: reset_partials(nc) doubles.
+struct Leg1D {
+    double p[4][4];  // p[u][a]: scaled Legendre polynomial of degree u at Gauss node a (k+1 nodes)
+    double w[4];     // Gauss weights
+};
 long long reset_partials(long long nc);
-hipError_t launch_reset(int k, int prec, void *y, const double *phi, const double *proj, long long nc, int nx,
-                        double gm1, double ce, double rho0, double vol, double *partials, double *acc, hipStream_t s);
+hipError_t launch_reset(int k, int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
+                        double rho0, double vol, double *partials, double *acc, hipStream_t s);
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
                               const GaussNodes &xg, void *out, hipStream_t s);
 
@@ -217,7 +221,7 @@ struct dg_ctx {
     int limnp = 0;
     unsigned long long *limcount = nullptr;  // cells changed by the limiter since the last query
     // isothermal reset (Sec. 3.2; dg_set_isothermal)
-    double *phitab = nullptr;              // phi_l(xi_q) at the volume points [Q][N]
+    dgmi::Leg1D leg1d{};                   // 1D Legendre values and weights at the Gauss nodes
     double *iso_partials = nullptr;        // per-block dissipated energy
     double iso_cs = 0.0, iso_rho0 = 0.0;
     bool have_iso = false;

@@ -1273,65 +1273,141 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
 
 // ------------------------------------------------------------------ isothermal reset (Sec. 3.2)
 
-__device__ inline float pow_d(float x, float p) { return powf(x, p); }
+// rho^(gamma-1) / rho0^(gamma-1): FP32 through the hardware base-2 logarithm and exponential,
+// FP64 through pow
+__device__ inline float pow_d(float x, float p) { return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x)); }
 __device__ inline double pow_d(double x, double p) { return pow(x, p); }
 
 constexpr int RESET_THREADS = 256;
 
-// One thread per cell (x consecutive over the lanes).  rho and m are evaluated at the (k+1)^3
-// Gauss points, the energy density |m|^2/(2 rho) + rho eps(rho), eps = ce (rho/rho0)^(gamma-1),
-// ce = cs^2/(gamma-1), is projected back onto the energy weights, and the block's sum of
-// |K| (rhoe_before - rhoe_after) (cell means, FP64) goes to partials[block].
+// index of mode (u, v, w) in the graded order (total degree, then u descending, then v descending)
+template <int K>
+__host__ __device__ constexpr int mode_of(int u, int v, int w) {
+    int l = 0;
+    for (int d = 0; d <= K; d++)
+        for (int a = d; a >= 0; a--)
+            for (int b = d - a; b >= 0; b--) {
+                if (a == u && b == v && d - a - b == w) return l;
+                l++;
+            }
+    return -1;
+}
+
+static_assert(mode_of<3>(0, 0, 0) == 0 && mode_of<3>(1, 0, 0) == 1 && mode_of<3>(0, 0, 1) == 3 &&
+                  mode_of<3>(1, 1, 0) == 5 && mode_of<3>(3, 0, 0) == 10 && mode_of<3>(0, 0, 3) == 19,
+              "graded mode order");
+
+// One thread per cell (x consecutive over the lanes), one z slice of the Gauss grid at a time.
+// rho and m at the slice's points by sum factorisation over the tensor-product Legendre factors
+// (z, then y, then x), the energy density |m|^2/(2 rho) + rho eps(rho), eps = ce (rho/rho0)^(gamma-1)
+// with ce = cs^2/(gamma-1), projected back in the reverse order (x, y, then z into the modes).
+// The block's sum of |K| (rhoe_before - rhoe_after) (cell means, FP64) goes to partials[block].
 template <int K, class S>
-__global__ __launch_bounds__(RESET_THREADS) void reset_kernel(S *__restrict__ y, const double *__restrict__ phi,
-                                                              const double *__restrict__ proj, long long nc, int nx,
+__global__ __launch_bounds__(RESET_THREADS) void reset_kernel(S *__restrict__ y, Leg1D L, long long nc, int nx,
                                                               double gm1, double ce, double rho0, double vol,
                                                               double *__restrict__ partials) {
-    constexpr int N = Dims<K>::N, Q = Dims<K>::Q;
+    constexpr int N = Dims<K>::N, n = K + 1;
     using C = S;
-    extern __shared__ __attribute__((aligned(16))) char lsm[];
-    C *lp = reinterpret_cast<C *>(lsm);  // phi_l(xi_q)          [Q][N]
-    C *lq = lp + Q * N;                   // phi_l(xi_q) w_q / 8  [Q][N]
     __shared__ double red[RESET_THREADS];
-    for (int j = threadIdx.x; j < Q * N; j += blockDim.x) {
-        lp[j] = (C)phi[j];
-        lq[j] = (C)proj[j];
-    }
-    __syncthreads();
+    C P[K + 1][n], WP[K + 1][n];
+#pragma unroll
+    for (int u = 0; u <= K; u++)
+#pragma unroll
+        for (int a = 0; a < n; a++) {
+            P[u][a] = (C)L.p[u][a];
+            WP[u][a] = (C)(L.w[a] * L.p[u][a]);
+        }
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double dis = 0.0;
     if (cell < nc) {
         const long long r = cell / nx;
         const long long base = r * (long long)NF * N * nx + (cell - r * nx);
-        C w[4][N];
+        C wt[4][N];
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int l = 0; l < N; l++) w[i][l] = y[base + (long long)(i * N + l) * nx];
+            for (int l = 0; l < N; l++) wt[i][l] = y[base + (long long)(i * N + l) * nx];
         const C e_old = y[base + (long long)(4 * N) * nx];
         C acc[N];
 #pragma unroll
         for (int l = 0; l < N; l++) acc[l] = 0;
         const C g = (C)gm1, cc = (C)ce, ir0 = C(1) / (C)rho0;
-        for (int q = 0; q < Q; q++) {
-            C v[4];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                C t = 0;
+        for (int c = 0; c < n; c++) {
+            // one field's values at the slice's points (z, then y, then x factor)
+            auto eval = [&](int i, C q[n][n]) {
+                C t1[K + 1][K + 1];
 #pragma unroll
-                for (int l = 0; l < N; l++) t += w[i][l] * lp[q * N + l];
-                v[i] = t;
+                for (int u = 0; u <= K; u++)
+#pragma unroll
+                    for (int v = 0; u + v <= K; v++) {
+                        C t = 0;
+#pragma unroll
+                        for (int w = 0; u + v + w <= K; w++) t += wt[i][mode_of<K>(u, v, w)] * P[w][c];
+                        t1[u][v] = t;
+                    }
+                C t2[K + 1][n];
+#pragma unroll
+                for (int u = 0; u <= K; u++)
+#pragma unroll
+                    for (int b = 0; b < n; b++) {
+                        C t = 0;
+#pragma unroll
+                        for (int v = 0; u + v <= K; v++) t += t1[u][v] * P[v][b];
+                        t2[u][b] = t;
+                    }
+#pragma unroll
+                for (int b = 0; b < n; b++)
+#pragma unroll
+                    for (int a = 0; a < n; a++) {
+                        C t = 0;
+#pragma unroll
+                        for (int u = 0; u <= K; u++) t += t2[u][b] * P[u][a];
+                        q[b][a] = t;
+                    }
+            };
+            C rho[n][n], m2[n][n], qm[n][n];
+            eval(0, rho);
+#pragma unroll
+            for (int i = 1; i < 4; i++) {
+                eval(i, qm);
+#pragma unroll
+                for (int b = 0; b < n; b++)
+#pragma unroll
+                    for (int a = 0; a < n; a++) m2[b][a] = (i == 1 ? C(0) : m2[b][a]) + qm[b][a] * qm[b][a];
             }
-            const C rho = v[0];
-            const C e = C(0.5) * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho + cc * rho * pow_d(rho * ir0, g);
+            C e[n][n];
 #pragma unroll
-            for (int l = 0; l < N; l++) acc[l] += e * lq[q * N + l];
+            for (int b = 0; b < n; b++)
+#pragma unroll
+                for (int a = 0; a < n; a++)
+                    e[b][a] = C(0.5) * m2[b][a] / rho[b][a] + cc * rho[b][a] * pow_d(rho[b][a] * ir0, g);
+            C s1[K + 1][n];
+#pragma unroll
+            for (int u = 0; u <= K; u++)
+#pragma unroll
+                for (int b = 0; b < n; b++) {
+                    C t = 0;
+#pragma unroll
+                    for (int a = 0; a < n; a++) t += WP[u][a] * e[b][a];
+                    s1[u][b] = t;
+                }
+#pragma unroll
+            for (int u = 0; u <= K; u++)
+#pragma unroll
+                for (int v = 0; u + v <= K; v++) {
+                    C t = 0;
+#pragma unroll
+                    for (int b = 0; b < n; b++) t += WP[v][b] * s1[u][b];
+#pragma unroll
+                    for (int w = 0; u + v + w <= K; w++) acc[mode_of<K>(u, v, w)] += C(0.125) * WP[w][c] * t;
+                }
         }
 #pragma unroll
         for (int l = 0; l < N; l++) y[base + (long long)(4 * N + l) * nx] = acc[l];
-        const double rb = (double)w[0][0], kin = 0.5 * ((double)w[1][0] * (double)w[1][0] +
-                                                        (double)w[2][0] * (double)w[2][0] +
-                                                        (double)w[3][0] * (double)w[3][0]) / rb;
+        const double rb = (double)wt[0][0], kin = 0.5 * ((double)wt[1][0] * (double)wt[1][0] +
+                                                         (double)wt[2][0] * (double)wt[2][0] +
+                                                         (double)wt[3][0] * (double)wt[3][0]) / rb;
         dis = vol * (((double)e_old - kin) - ((double)acc[0] - kin));
     }
     red[threadIdx.x] = dis;
@@ -1362,27 +1438,25 @@ __global__ __launch_bounds__(256) void sum_into_kernel(const double *__restrict_
 long long reset_partials(long long nc) { return (nc + RESET_THREADS - 1) / RESET_THREADS; }
 
 template <int K>
-static hipError_t launch_reset_k(int prec, void *y, const double *phi, const double *proj, long long nc, int nx,
-                                 double gm1, double ce, double rho0, double vol, double *partials, double *acc,
-                                 hipStream_t s) {
+static hipError_t launch_reset_k(int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
+                                 double rho0, double vol, double *partials, double *acc, hipStream_t s) {
     const long long nb = reset_partials(nc);
-    const int QN = Dims<K>::Q * Dims<K>::N;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((reset_kernel<K, double>), dim3(nb), dim3(RESET_THREADS), 2 * QN * 8, s, (double *)y, phi,
-                           proj, nc, nx, gm1, ce, rho0, vol, partials);
+        hipLaunchKernelGGL((reset_kernel<K, double>), dim3(nb), dim3(RESET_THREADS), 0, s, (double *)y, L, nc, nx,
+                           gm1, ce, rho0, vol, partials);
     else
-        hipLaunchKernelGGL((reset_kernel<K, float>), dim3(nb), dim3(RESET_THREADS), 2 * QN * 4, s, (float *)y, phi,
-                           proj, nc, nx, gm1, ce, rho0, vol, partials);
+        hipLaunchKernelGGL((reset_kernel<K, float>), dim3(nb), dim3(RESET_THREADS), 0, s, (float *)y, L, nc, nx, gm1,
+                           ce, rho0, vol, partials);
     hipLaunchKernelGGL(sum_into_kernel, dim3(1), dim3(256), 0, s, partials, nb, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_reset(int k, int prec, void *y, const double *phi, const double *proj, long long nc, int nx,
-                        double gm1, double ce, double rho0, double vol, double *partials, double *acc, hipStream_t s) {
+hipError_t launch_reset(int k, int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
+                        double rho0, double vol, double *partials, double *acc, hipStream_t s) {
     switch (k) {
-        case 1: return launch_reset_k<1>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
-        case 2: return launch_reset_k<2>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
-        case 3: return launch_reset_k<3>(prec, y, phi, proj, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        case 1: return launch_reset_k<1>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        case 2: return launch_reset_k<2>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
+        case 3: return launch_reset_k<3>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
         default: return hipErrorInvalidValue;
     }
 }
