@@ -294,6 +294,47 @@ dg_status dg_isothermal_reset(dg_ctx *ctx, void *y);
  * out: HOST.  Synchronises. */
 dg_status dg_dissipated(dg_ctx *ctx, double *out);
 
+/* ---------------------------------------------------------------------------
+ * Turbulence diagnostics (Sec. 3.3, 4.1, 4.4).  The DG polynomials are sampled
+ * on a sub-cell grid: each cell is split into S equal parts per axis (the paper
+ * uses S = 4) and evaluated at the part centres xi_j = -1 + (2j+1)/S, giving
+ * M_a = S n[a] points per axis; grid point X sits at x = (X + 1/2) box[a]/M_a.
+ * Point values are computed in the storage precision, 1 <= S <= 4 (else
+ * DG_ERR_ARG).  The first call allocates a small device buffer.
+ *
+ * The five conserved fields on the grid.  out: DEVICE, storage type,
+ * [5][M_z][M_y][M_x] (5 M_x M_y M_z elements).  Asynchronous. */
+dg_status dg_sample(dg_ctx *ctx, const void *y, int32_t S, void *out);
+
+/* Bytes of the workspace dg_velocity_spectrum needs: one real-to-complex FFT
+ * buffer of M^2 * 2(M/2+1) elements of the storage type (M = S n). */
+size_t dg_spectrum_workspace_bytes(const dg_ctx *ctx, int32_t S);
+
+/* Shell power spectrum of the velocity v = m/rho (Sec. 3.3), cubic meshes only
+ * (equal n and box on every axis, else DG_ERR_UNSUPPORTED):
+ *   P(s) = sum_i sum_{n: nearest integer to |n| is s} |v_hat_i(n)|^2 / M^6,
+ *   v_hat_i(n) = sum_X v_i(X) exp(-2 pi i n.X/M),
+ * so that sum_s P(s) is the grid mean of |v|^2; E(k) = P(s) box/(2 pi) at
+ * k = 2 pi s / box.  The transforms are hipFFT real-to-complex (FP32 for the
+ * FP32-storage tiers, FP64 for DG_FP64; the plan is made on the first call and
+ * kept); shells are summed in FP64 with atomics (the last bits can vary between
+ * calls).  out: HOST double [nbins], 1 <= nbins <= 4096, shells >= nbins are
+ * dropped.  work: DEVICE, dg_spectrum_workspace_bytes(ctx, S).  Synchronises. */
+dg_status dg_velocity_spectrum(dg_ctx *ctx, const void *y, int32_t S, int32_t nbins, double *out, void *work);
+
+/* Density PDF (Sec. 4.4): counts of log10(rho) at the sampled points in nbins
+ * equal bins of [lo, hi); counts[0]: points below lo, with rho <= 0 or not
+ * finite; counts[nbins+1]: points at or above hi.  counts: HOST int64
+ * [nbins + 2], 1 <= nbins <= 4096, lo < hi finite.  Exact integer counts (the
+ * bin of a point is decided in the storage precision).  Synchronises. */
+dg_status dg_density_pdf(dg_ctx *ctx, const void *y, int32_t S, double lo, double hi, int32_t nbins,
+                         int64_t *counts);
+
+/* rms Mach number (Sec. 4.1): sqrt of the mean over the sampled points of
+ * |v|^2 / c^2, c^2 = gamma p / rho, summed in FP64 in a fixed order.
+ * out: HOST.  Synchronises. */
+dg_status dg_rms_mach(dg_ctx *ctx, const void *y, int32_t S, double *out);
+
 #ifdef __cplusplus
 }
 #endif

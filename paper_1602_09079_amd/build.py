@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmi.so")
-SOURCES = ["dg_kernels.hip", "closure_kernels.hip", "dg_host.cpp"]
+SOURCES = ["dg_kernels.hip", "closure_kernels.hip", "diag_kernels.hip", "dg_host.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -39,7 +39,7 @@ def build(verbose=False, jobs=4):
         if p.wait() != 0:
             raise RuntimeError("compile failed: " + " ".join(cmd))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -7,6 +7,7 @@
 // instructions the stage kernel issues, so that the kernel's loads from LDS are
 // contiguous and the chained products need no data movement.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -452,6 +453,9 @@ dg_status dg_destroy(dg_ctx *c) {
                     c->restrict_tab[2], c->restrict_tab[3]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);  // release what was allocated; a failure here has no remedy
+    if (c->diag_bins) (void)hipFree(c->diag_bins);
+    if (c->diag_partials) (void)hipFree(c->diag_partials);
+    if (c->fft) (void)hipfftDestroy(static_cast<hipfftHandle>(c->fft));
     delete c;
     return DG_OK;
 }
@@ -1065,5 +1069,171 @@ extern "C" dg_status dg_limiter_stats(dg_ctx *c, int64_t *count) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_zero_u64(c->limcount, c->stream));
     *count = (int64_t)v;
+    return DG_OK;
+}
+
+// ------------------------------------------------------------------ diagnostics (Sec. 3.3, 4.1, 4.4)
+
+static dg_status diag_begin(dg_ctx *c, const void *y, int S, const char *who, Leg1D *L) {
+    if (!y) {
+        c->err = std::string(who) + ": NULL pointer";
+        return DG_ERR_ARG;
+    }
+    if (S < 1 || S > DIAG_MAX_S) {
+        c->err = std::string(who) + ": S must be in 1.." + std::to_string(DIAG_MAX_S);
+        return DG_ERR_ARG;
+    }
+    if (!c->diag_bins) {
+        if (hipMalloc(&c->diag_bins, (2 * DIAG_MAX_BINS + 2) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->diag_partials, (sample_blocks(c->ncells) + 1) * sizeof(double)) != hipSuccess) {
+            c->err = std::string(who) + ": hipMalloc failed";
+            return DG_ERR_HIP;
+        }
+    }
+    // scaled Legendre polynomials at the centres of the S equal parts of [-1, 1]
+    *L = Leg1D{};
+    for (int u = 0; u <= c->cfg.k; u++)
+        for (int a = 0; a < S; a++) L->p[u][a] = leg(u, -1.0 + (2.0 * a + 1.0) / S);
+    return DG_OK;
+}
+
+static SampleArgs sample_args(const dg_ctx *c, const void *y, int what) {
+    SampleArgs a{};
+    a.y = y;
+    a.nc = c->ncells;
+    a.nx = c->cfg.n[0];
+    a.ny = c->cfg.n[1];
+    a.what = what;
+    a.gamma = c->cfg.gamma;
+    return a;
+}
+
+dg_status dg_sample(dg_ctx *c, const void *y, int32_t S, void *out) {
+    if (!c) return DG_ERR_ARG;
+    Leg1D L;
+    dg_status st = diag_begin(c, y, S, "dg_sample", &L);
+    if (st != DG_OK) return st;
+    if (!out) {
+        c->err = "dg_sample: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    SampleArgs a = sample_args(c, y, 0);
+    a.out = out;
+    a.px = (long long)S * c->cfg.n[0];
+    a.py = a.px * S * c->cfg.n[1];
+    a.pf = a.py * S * c->cfg.n[2];
+    HIPCHK(c, launch_sample(c->cfg.k, S, c->cfg.precision, a, L, c->stream));
+    return DG_OK;
+}
+
+static bool cubic(const dg_ctx *c) {
+    return c->cfg.n[0] == c->cfg.n[1] && c->cfg.n[1] == c->cfg.n[2] && c->cfg.box[0] == c->cfg.box[1] &&
+           c->cfg.box[1] == c->cfg.box[2];
+}
+
+size_t dg_spectrum_workspace_bytes(const dg_ctx *c, int32_t S) {
+    if (!c || S < 1 || S > DIAG_MAX_S) return 0;
+    const size_t M = (size_t)S * c->cfg.n[0];
+    return M * M * 2 * (M / 2 + 1) * elem_bytes(c);
+}
+
+dg_status dg_velocity_spectrum(dg_ctx *c, const void *y, int32_t S, int32_t nbins, double *out, void *work) {
+    if (!c) return DG_ERR_ARG;
+    Leg1D L;
+    dg_status st = diag_begin(c, y, S, "dg_velocity_spectrum", &L);
+    if (st != DG_OK) return st;
+    if (!out || !work || nbins < 1 || nbins > DIAG_MAX_BINS) {
+        c->err = "dg_velocity_spectrum: NULL pointer or nbins outside 1.." + std::to_string(DIAG_MAX_BINS);
+        return DG_ERR_ARG;
+    }
+    if (!cubic(c)) {
+        c->err = "dg_velocity_spectrum: needs the same cell count and box length on every axis";
+        return DG_ERR_UNSUPPORTED;
+    }
+    const int M = S * c->cfg.n[0];
+    const bool f64 = c->cfg.precision == DG_FP64;
+    if (c->fft && c->fft_m != M) {
+        (void)hipfftDestroy(static_cast<hipfftHandle>(c->fft));
+        c->fft = nullptr;
+    }
+    if (!c->fft) {
+        hipfftHandle h = nullptr;
+        if (hipfftPlan3d(&h, M, M, M, f64 ? HIPFFT_D2Z : HIPFFT_R2C) != HIPFFT_SUCCESS) {
+            c->err = "dg_velocity_spectrum: hipfftPlan3d failed";
+            return DG_ERR_HIP;
+        }
+        c->fft = h;
+        c->fft_m = M;
+    }
+    hipfftHandle h = static_cast<hipfftHandle>(c->fft);
+    if (hipfftSetStream(h, c->stream) != HIPFFT_SUCCESS) {
+        c->err = "dg_velocity_spectrum: hipfftSetStream failed";
+        return DG_ERR_HIP;
+    }
+    HIPCHK(c, launch_fill_zero(reinterpret_cast<unsigned long long *>(c->diag_bins), nbins, c->stream));
+    const double scale = 1.0 / ((double)M * M * M * (double)M * M * M);
+    for (int comp = 1; comp <= 3; comp++) {
+        SampleArgs a = sample_args(c, y, comp);
+        a.out = work;
+        a.px = 2LL * (M / 2 + 1);  // rows padded for the in-place real-to-complex transform
+        a.py = a.px * M;
+        HIPCHK(c, launch_sample(c->cfg.k, S, c->cfg.precision, a, L, c->stream));
+        const hipfftResult r = f64 ? hipfftExecD2Z(h, (hipfftDoubleReal *)work, (hipfftDoubleComplex *)work)
+                                   : hipfftExecR2C(h, (hipfftReal *)work, (hipfftComplex *)work);
+        if (r != HIPFFT_SUCCESS) {
+            c->err = "dg_velocity_spectrum: FFT execution failed";
+            return DG_ERR_HIP;
+        }
+        HIPCHK(c, launch_shells(c->cfg.precision, work, M, nbins, scale, c->diag_bins, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(out, c->diag_bins, nbins * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+dg_status dg_density_pdf(dg_ctx *c, const void *y, int32_t S, double lo, double hi, int32_t nbins, int64_t *counts) {
+    if (!c) return DG_ERR_ARG;
+    Leg1D L;
+    dg_status st = diag_begin(c, y, S, "dg_density_pdf", &L);
+    if (st != DG_OK) return st;
+    if (!counts || nbins < 1 || nbins > DIAG_MAX_BINS || !std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) {
+        c->err = "dg_density_pdf: NULL pointer, nbins outside 1.." + std::to_string(DIAG_MAX_BINS) +
+                 " or an invalid range";
+        return DG_ERR_ARG;
+    }
+    unsigned long long *dc = reinterpret_cast<unsigned long long *>(c->diag_bins + DIAG_MAX_BINS);
+    HIPCHK(c, launch_fill_zero(dc, nbins + 2, c->stream));
+    SampleArgs a = sample_args(c, y, 4);
+    a.lo = lo;
+    a.hi = hi;
+    a.nbins = nbins;
+    a.counts = dc;
+    HIPCHK(c, launch_sample(c->cfg.k, S, c->cfg.precision, a, L, c->stream));
+    static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
+    HIPCHK(c, hipMemcpyAsync(counts, dc, (nbins + 2) * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+dg_status dg_rms_mach(dg_ctx *c, const void *y, int32_t S, double *out) {
+    if (!c) return DG_ERR_ARG;
+    Leg1D L;
+    dg_status st = diag_begin(c, y, S, "dg_rms_mach", &L);
+    if (st != DG_OK) return st;
+    if (!out) {
+        c->err = "dg_rms_mach: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    const long long nb = sample_blocks(c->ncells);
+    SampleArgs a = sample_args(c, y, 4);
+    a.mach_partials = c->diag_partials;
+    HIPCHK(c, launch_sample(c->cfg.k, S, c->cfg.precision, a, L, c->stream));
+    double *tot = c->diag_partials + nb;
+    HIPCHK(c, launch_fill_zero(reinterpret_cast<unsigned long long *>(tot), 1, c->stream));
+    HIPCHK(c, launch_sum_into(c->diag_partials, nb, tot, c->stream));
+    double v = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&v, tot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *out = std::sqrt(v / ((double)c->ncells * S * S * S));
     return DG_OK;
 }

@@ -24,6 +24,22 @@ inline int nmodes_of(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 // register r.  FP32/BF16 accumulators: 4g + r.  FP64 (16x16x4f64): g + 4r.
 inline int out_row(int prec, int g, int r) { return prec == DG_FP64 ? g + 4 * r : 4 * g + r; }
 
+// index of mode (u, v, w) in the graded order (total degree, then u descending, then v descending)
+template <int K>
+__host__ __device__ constexpr int mode_of(int u, int v, int w) {
+    int l = 0;
+    for (int d = 0; d <= K; d++)
+        for (int a = d; a >= 0; a--)
+            for (int b = d - a; b >= 0; b--) {
+                if (a == u && b == v && d - a - b == w) return l;
+                l++;
+            }
+    return -1;
+}
+static_assert(mode_of<3>(0, 0, 0) == 0 && mode_of<3>(1, 0, 0) == 1 && mode_of<3>(0, 0, 1) == 3 &&
+                  mode_of<3>(1, 1, 0) == 5 && mode_of<3>(3, 0, 0) == 10 && mode_of<3>(0, 0, 3) == 19,
+              "graded mode order");
+
 // Mode assignment shared by every product: lane group g owns the modes
 // g*spl .. g*spl + spl - 1 (spl = ceil(N/4)), mode slot s = 0..spl-1.  Slot s is
 // the K-step s (FP32/FP64) or value s (BF16) of the B operands of GEMM1/GEMM3,
@@ -87,6 +103,29 @@ struct Leg1D {
     double w[4];     // Gauss weights
 };
 long long reset_partials(long long nc);
+
+// ---- turbulence diagnostics (Sec. 3.3, 4.1, 4.4) on the S^3 sub-cell grid
+constexpr int DIAG_MAX_S = 4;        // sub-cell points per axis
+constexpr int DIAG_MAX_BINS = 4096;  // spectrum shells / PDF bins
+struct SampleArgs {
+    const void *y;
+    long long nc;
+    int nx, ny;
+    int what;             // 0: the five conserved fields; 1..3: velocity component what-1; 4: statistics
+    void *out;            // grid (what 0..3): [field][Z][Y][X] with the pitches below
+    long long px, py, pf; // row, plane and field pitches of out, in elements
+    double gamma;
+    double lo, hi;        // PDF range of log10(rho); nbins > 0 enables the PDF
+    int nbins;
+    unsigned long long *counts;  // [nbins + 2]
+    double *mach_partials;       // per block sum of |v|^2/c^2 over the block's points, or nullptr
+};
+long long sample_blocks(long long nc);
+hipError_t launch_sample(int k, int S, int prec, const SampleArgs &a, const Leg1D &L, hipStream_t s);
+// bins[s] += scale * weight * |c|^2 over an R2C spectrum [M][M][M/2+1] (interleaved complex)
+hipError_t launch_shells(int prec, const void *spec, int M, int nbins, double scale, double *bins, hipStream_t s);
+hipError_t launch_fill_zero(unsigned long long *p, long long n, hipStream_t s);
+hipError_t launch_sum_into(const double *p, long long n, double *acc, hipStream_t s);
 hipError_t launch_reset(int k, int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
                         double rho0, double vol, double *partials, double *acc, hipStream_t s);
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
@@ -225,5 +264,10 @@ struct dg_ctx {
     double *iso_partials = nullptr;        // per-block dissipated energy
     double iso_cs = 0.0, iso_rho0 = 0.0;
     bool have_iso = false;
+    // diagnostics (dg_sample, dg_velocity_spectrum, dg_density_pdf, dg_rms_mach)
+    void *fft = nullptr;                   // hipFFT plan (R2C / D2Z, fft_m^3), made on first use
+    int fft_m = 0;
+    double *diag_bins = nullptr;           // [DIAG_MAX_BINS] shell sums, then [DIAG_MAX_BINS + 2] counts
+    double *diag_partials = nullptr;       // per-block Mach sums, then the total
     std::string err;
 };

@@ -1280,23 +1280,6 @@ __device__ inline double pow_d(double x, double p) { return pow(x, p); }
 
 constexpr int RESET_THREADS = 256;
 
-// index of mode (u, v, w) in the graded order (total degree, then u descending, then v descending)
-template <int K>
-__host__ __device__ constexpr int mode_of(int u, int v, int w) {
-    int l = 0;
-    for (int d = 0; d <= K; d++)
-        for (int a = d; a >= 0; a--)
-            for (int b = d - a; b >= 0; b--) {
-                if (a == u && b == v && d - a - b == w) return l;
-                l++;
-            }
-    return -1;
-}
-
-static_assert(mode_of<3>(0, 0, 0) == 0 && mode_of<3>(1, 0, 0) == 1 && mode_of<3>(0, 0, 1) == 3 &&
-                  mode_of<3>(1, 1, 0) == 5 && mode_of<3>(3, 0, 0) == 10 && mode_of<3>(0, 0, 3) == 19,
-              "graded mode order");
-
 // One thread per cell (x consecutive over the lanes), one z slice of the Gauss grid at a time.
 // rho and m at the slice's points by sum factorisation over the tensor-product Legendre factors
 // (z, then y, then x), the energy density |m|^2/(2 rho) + rho eps(rho), eps = ce (rho/rho0)^(gamma-1)
@@ -1436,6 +1419,11 @@ __global__ __launch_bounds__(256) void sum_into_kernel(const double *__restrict_
 }
 
 long long reset_partials(long long nc) { return (nc + RESET_THREADS - 1) / RESET_THREADS; }
+
+hipError_t launch_sum_into(const double *p, long long n, double *acc, hipStream_t s) {
+    hipLaunchKernelGGL(sum_into_kernel, dim3(1), dim3(256), 0, s, p, n, acc);
+    return hipGetLastError();
+}
 
 template <int K>
 static hipError_t launch_reset_k(int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,

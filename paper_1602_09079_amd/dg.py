@@ -27,7 +27,8 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_error_string", "dg_set_closure", "dg_closure_fallbacks", "dg_closure_features", "dg_closure_targets",
            "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
            "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats",
-           "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated"]
+           "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated", "dg_sample",
+           "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach"]
 
 
 class DGError(RuntimeError):
@@ -91,6 +92,12 @@ def lib():
             "dg_set_isothermal": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
             "dg_isothermal_reset": (ctypes.c_int, [_vp, _vp]),
             "dg_dissipated": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+            "dg_sample": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp]),
+            "dg_spectrum_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
+            "dg_velocity_spectrum": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
+            "dg_density_pdf": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int32, _vp]),
+            "dg_rms_mach": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -301,6 +308,41 @@ class Solver:
         """Dissipated energy of the resets since the previous call."""
         v = ctypes.c_double()
         self._check(lib().dg_dissipated(self._ctx, ctypes.byref(v)), "dg_dissipated")
+        return v.value
+
+    # ------------------------------------------------------------ diagnostics (Sec. 3.3, 4.1, 4.4)
+    def sample(self, y, S=4):
+        """The five conserved fields on the sub-cell grid: [5][S nz][S ny][S nx]."""
+        import torch
+        out = torch.empty((5, S * self.n[2], S * self.n[1], S * self.n[0]), dtype=self.dtype, device=self.device)
+        self._check(lib().dg_sample(self._ctx, self._ptr(y, self.state_shape()), S, _vp(out.data_ptr())),
+                    "dg_sample")
+        return out
+
+    def velocity_spectrum(self, y, S=4, nbins=None, work=None):
+        """Shell powers P(s), s < nbins (default S n), summed over the velocity components."""
+        import numpy as np
+        import torch
+        nbins = S * self.n[0] if nbins is None else nbins
+        if work is None:
+            work = torch.empty(lib().dg_spectrum_workspace_bytes(self._ctx, S), dtype=torch.uint8, device=self.device)
+        out = np.zeros(nbins)
+        self._check(lib().dg_velocity_spectrum(self._ctx, self._ptr(y, self.state_shape()), S, nbins,
+                                               out.ctypes.data_as(_dp), _vp(work.data_ptr())), "dg_velocity_spectrum")
+        return out
+
+    def density_pdf(self, y, S=4, lo=-1.0, hi=1.0, nbins=100):
+        """Counts of log10(rho): [below lo, nbins bins of [lo, hi), at or above hi]."""
+        import numpy as np
+        out = np.zeros(nbins + 2, dtype=np.int64)
+        self._check(lib().dg_density_pdf(self._ctx, self._ptr(y, self.state_shape()), S, lo, hi, nbins,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "dg_density_pdf")
+        return out
+
+    def rms_mach(self, y, S=4):
+        v = ctypes.c_double()
+        self._check(lib().dg_rms_mach(self._ctx, self._ptr(y, self.state_shape()), S, ctypes.byref(v)),
+                    "dg_rms_mach")
         return v.value
 
     def closure_fallbacks(self):
