@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--cpu-n", type=int, default=32, help="mesh of the oracle's timed sample")
     p.add_argument("--quiet", action="store_true")
     p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
+    p.add_argument("--diagnostics", action="store_true", help="also time the spectrum, PDF and Mach diagnostics")
     p.add_argument("--no-limiter", action="store_true", help="skip the limiter and isothermal-reset timings")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
@@ -203,6 +204,33 @@ def reset_cost(args, dg, torch, prec, qp_dev, n, k):
     return dict(tier=prec, reset_ms=ms, algorithmic_GBs=alg / ms / 1e6, hbm_frac=alg / ms / 1e6 / HBM_PEAK_GBS)
 
 
+def diagnostics_cost(args, dg, torch, prec, qp_dev, n, k):
+    """The diagnostics of Sec. 3.3, 4.1, 4.4 on the benchmark state, 4^3 sub-cell points per cell
+    (a 4n grid per axis): velocity shell spectrum (three real-to-complex FFTs), log-density PDF,
+    rms Mach.  Wall time per call after a first call (which makes the FFT plan)."""
+    s = dg.Solver(k, n, precision=prec)
+    y = s.project(qp_dev.to(s.dtype))
+    work = torch.empty(dg.lib().dg_spectrum_workspace_bytes(s._ctx, 4), dtype=torch.uint8, device=s.device)
+    out = {}
+    for name, fn in (("spectrum", lambda: s.velocity_spectrum(y, 4, 4 * n, work=work)),
+                     ("pdf", lambda: s.density_pdf(y, 4, -0.5, 0.5, 200)),
+                     ("rms_mach", lambda: s.rms_mach(y, 4))):
+        t0 = time.perf_counter()
+        fn()
+        first = time.perf_counter() - t0
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        out[name + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        out[name + "_first_ms"] = first * 1e3
+    log(args, f"[bench] {prec} diagnostics on the {4 * n}^3 sub-cell grid: " +
+        ", ".join(f"{kk} {v:.1f}" for kk, v in out.items()))
+    del s, y, work
+    torch.cuda.empty_cache()
+    return dict(tier=prec, grid=4 * n, **out)
+
+
 def cpu_baseline(args, k):
     """Oracle (FP64 C, OpenMP) on a bounded sample: one SSP stage on a cpu_n^3 mesh."""
     import numpy as np
@@ -255,6 +283,7 @@ def main():
                                                             key=lambda p: results[p]["dof_updates_per_s"])
     lim = None if args.no_limiter else limiter_cost(args, dg, torch, prim0, qp, n, k)
     iso = None if args.no_limiter else reset_cost(args, dg, torch, prim0, qp, n, k)
+    diag = diagnostics_cost(args, dg, torch, prim0, qp, n, k) if args.diagnostics else None
     del qp
     torch.cuda.empty_cache()
     if args.copy_calibration > 0:
@@ -314,6 +343,8 @@ def main():
         line["limiter"] = dict(lim, stage_ms_without=r["stage_ms"])
     if iso is not None:
         line["isothermal_reset"] = iso
+    if diag is not None:
+        line["diagnostics"] = diag
     print(json.dumps(line), flush=True)
 
 
