@@ -7,6 +7,8 @@
   energy within 1e-10 (FP64) / 1e-4 (FP32) relative;
 * dg_step with DG_ISOTHERMAL (gamma = 1.01, reset after every step), also with
   DG_LIMIT and the driving, against the oracle's steps;
+* the paper's own set-up (band 1 < |n| < 2, gamma = 1.01, reset, limiter, device
+  CFL steps) at a small size;
 * the account: dg_dissipated returns the sum since the previous call, then 0;
 * errors: the flag without dg_set_isothermal, invalid cs / rho0.
 """
@@ -118,3 +120,42 @@ def test_reset_errors(dgm):
             s.set_isothermal(cs, r0)
         assert e.value.status == dgm.DG_ERR_ARG
     assert s.dissipated() == 0.0
+
+
+@pytest.mark.parametrize("prec,k", [("fp64", 1), ("fp64", 3), ("fp32", 2), ("bf16x3", 3)])
+def test_paper_workload_parity(dgm, prec, k):
+    """The paper's own turbulence set-up at a small size (Sec. 3.1, 3.2): driving on the band
+    1 < |n| < 2, gamma = 1.01 with the isothermal reset (cs = 1), the positivity limiter, rms
+    Mach 0.2 start, CFL steps on the device; four steps against the oracle."""
+    from paper_1602_09079_amd import synth
+    n = (10, 8, 6)
+    cfg = O.make_cfg(k, n, gamma=G)
+    y = O.project(cfg, synth.turbulence(n, O.gauss_legendre(k + 1)[0], seed=1602, mach=0.2).numpy())
+    y, _ = O.isothermal_reset(cfg, y, 1.0, 1.0)  # start on the isothermal level
+    nvec = synth.forcing_modes(1.0, 2.0)
+    th = synth.ou_stationary_start(7, len(nvec))
+    z = synth.ou_normals(7, len(nvec), 1)[0]
+    _, ah_lib = dgm.ou_update(nvec, th, z, 0.9, 1.0, 0.5, 1.0, 2.0)
+    _, ah_orc = O.ou_update(nvec, th, z, 0.9, 1.0, 0.5, 1.0, 2.0)
+    s = dgm.Solver(k, n, gamma=G, precision=prec, isothermal=True, limit=True, forcing=True)
+    s.set_isothermal(1.0, 1.0)
+    s.set_forcing(nvec, ah_lib)
+    yd = dev(y, s.dtype)
+    t = s.step(yd, 4)
+    ystore = y if prec == "fp64" else y.astype(np.float32).astype(np.float64)
+    want, tw, dwant = O.step_isothermal(cfg, ystore, 0.0, 4, frc=O.ForcingTable(nvec, ah_orc), cs=1.0, rho0=1.0,
+                                        limit=True)
+    assert t == pytest.approx(tw, rel=1e-12 if prec == "fp64" else 1e-6)
+    g = host(yd).reshape(5, -1)
+    w = want.reshape(5, -1)
+    err = np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)
+    assert np.all(err <= (1e-11 if prec == "fp64" else 1e-5)), err
+    d = s.dissipated()
+    if prec == "fp64":
+        assert d == pytest.approx(dwant, rel=1e-7, abs=1e-12)
+    else:
+        # with gamma = 1.01 the internal energy (~ cs^2/(gamma-1) = 100 per unit mass) dwarfs what a
+        # step dissipates near the isothermal level; FP32 storage rounds E by ~1e-7 of itself per
+        # reset, so the FP32 account is only good to that level (measure dissipation in FP64)
+        etot = O.totals(cfg, want)[4]
+        assert abs(d - dwant) <= 4 * 2.0 ** -20 * etot
