@@ -23,7 +23,7 @@ c_int_p = ctypes.POINTER(ctypes.c_int32)
 
 class Cfg(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
-                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("riemann", ctypes.c_int32)]
 
 
 class Forcing(ctypes.Structure):
@@ -57,7 +57,7 @@ def _i(a):
     return a.ctypes.data_as(c_int_p)
 
 
-def make_cfg(k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3):
+def make_cfg(k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, riemann="hllc"):
     if isinstance(n, int):
         n = (n, n, n)
     c = Cfg()
@@ -67,6 +67,7 @@ def make_cfg(k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3):
         c.box[a] = box[a]
     c.gamma = gamma
     c.cfl = cfl
+    c.riemann = {"hllc": 0, "exact": 1}[riemann]
     return c
 
 
@@ -146,6 +147,13 @@ def hllc(qL, qR, axis, gamma):
     F = np.zeros(5)
     lib().orc_hllc(_d(np.ascontiguousarray(qL, dtype=np.float64)), _d(np.ascontiguousarray(qR, dtype=np.float64)),
                    axis, ctypes.c_double(gamma), _d(F))
+    return F
+
+
+def exact_riemann(qL, qR, axis, gamma):
+    F = np.zeros(5)
+    lib().orc_exact_riemann(_d(np.ascontiguousarray(qL, dtype=np.float64)),
+                            _d(np.ascontiguousarray(qR, dtype=np.float64)), axis, ctypes.c_double(gamma), _d(F))
     return F
 
 

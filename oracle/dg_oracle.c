@@ -289,6 +289,112 @@ void orc_hllc(const double qL[5], const double qR[5], int axis, double gamma, do
     }
 }
 
+/* Exact Riemann solver (the alternative numerical flux of Sec. 2.3), after Toro, Riemann
+ * Solvers and Numerical Methods for Fluid Dynamics, ch. 4: the star pressure is the root of
+ * f_L(p) + f_R(p) + (u_R - u_L) = 0 with the shock (Rankine-Hugoniot) or rarefaction
+ * (isentropic) branch of each side, found here by bisection (slow, obviously convergent: f is
+ * increasing in p); the similarity solution is sampled on the face (x/t = 0) and its Euler
+ * flux returned.  Tangential velocities travel with the contact.  When the data generate
+ * vacuum (2(c_L + c_R)/(gamma-1) <= u_R - u_L) the vacuum solution is sampled. */
+static double wave_f(double p, double rK, double pK, double cK, double gamma)
+{
+    if (p > pK) {
+        double A = 2.0 / ((gamma + 1.0) * rK), B = (gamma - 1.0) / (gamma + 1.0) * pK;
+        return (p - pK) * sqrt(A / (p + B));
+    }
+    return 2.0 * cK / (gamma - 1.0) * (pow(p / pK, (gamma - 1.0) / (2.0 * gamma)) - 1.0);
+}
+
+/* primitive state (rho, u_normal, p) at x/t = 0 of the fan on side K (sign = -1 left, +1 right) */
+static void fan_state(double rK, double uK, double pK, double cK, double gamma, double sign, double W[3])
+{
+    double g1 = gamma - 1.0, gp = gamma + 1.0;
+    double c = 2.0 / gp - sign * g1 / (gp * cK) * uK;
+    W[0] = rK * pow(c, 2.0 / g1);
+    W[1] = 2.0 / gp * (-sign * cK + g1 / 2.0 * uK);
+    W[2] = pK * pow(c, 2.0 * gamma / g1);
+}
+
+void orc_exact_riemann(const double qL[5], const double qR[5], int axis, double gamma, double F[5])
+{
+    double rL = qL[0], rR = qR[0];
+    double uL = qL[1 + axis] / rL, uR = qR[1 + axis] / rR;
+    double pL = pressure(qL, gamma), pR = pressure(qR, gamma);
+    double cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+    double g1 = gamma - 1.0, gp = gamma + 1.0;
+    double W[3];      /* rho, u_normal, p on the face */
+    const double *qt; /* side whose tangential velocities are carried */
+    if (2.0 * (cL + cR) / g1 <= uR - uL) {
+        /* vacuum between two rarefactions */
+        double sL = uL + 2.0 * cL / g1, sR = uR - 2.0 * cR / g1;
+        if (0.0 <= sL) {
+            qt = qL;
+            if (0.0 <= uL - cL) { W[0] = rL; W[1] = uL; W[2] = pL; }
+            else fan_state(rL, uL, pL, cL, gamma, -1.0, W);
+        } else if (0.0 >= sR) {
+            qt = qR;
+            if (0.0 >= uR + cR) { W[0] = rR; W[1] = uR; W[2] = pR; }
+            else fan_state(rR, uR, pR, cR, gamma, 1.0, W);
+        } else {
+            qt = qL;
+            W[0] = 0.0; W[1] = 0.0; W[2] = 0.0;
+        }
+    } else {
+        /* star pressure by bisection on the increasing function f */
+        double lo = 0.0, hi = fmax(pL, pR);
+        double du = uR - uL;
+        while (wave_f(hi, rL, pL, cL, gamma) + wave_f(hi, rR, pR, cR, gamma) + du < 0.0) hi *= 2.0;
+        for (int it = 0; it < 200; it++) {
+            double mid = 0.5 * (lo + hi);
+            if (mid == lo || mid == hi) break;
+            if (wave_f(mid, rL, pL, cL, gamma) + wave_f(mid, rR, pR, cR, gamma) + du < 0.0) lo = mid;
+            else hi = mid;
+        }
+        double ps = 0.5 * (lo + hi);
+        double us = 0.5 * (uL + uR) + 0.5 * (wave_f(ps, rR, pR, cR, gamma) - wave_f(ps, rL, pL, cL, gamma));
+        if (0.0 <= us) {
+            qt = qL;
+            if (ps > pL) { /* left shock */
+                double S = uL - cL * sqrt(gp / (2.0 * gamma) * ps / pL + g1 / (2.0 * gamma));
+                if (0.0 <= S) { W[0] = rL; W[1] = uL; W[2] = pL; }
+                else { W[0] = rL * (ps / pL + g1 / gp) / (g1 / gp * ps / pL + 1.0); W[1] = us; W[2] = ps; }
+            } else { /* left rarefaction */
+                double head = uL - cL, tail = us - cL * pow(ps / pL, g1 / (2.0 * gamma));
+                if (0.0 <= head) { W[0] = rL; W[1] = uL; W[2] = pL; }
+                else if (0.0 >= tail) { W[0] = rL * pow(ps / pL, 1.0 / gamma); W[1] = us; W[2] = ps; }
+                else fan_state(rL, uL, pL, cL, gamma, -1.0, W);
+            }
+        } else {
+            qt = qR;
+            if (ps > pR) { /* right shock */
+                double S = uR + cR * sqrt(gp / (2.0 * gamma) * ps / pR + g1 / (2.0 * gamma));
+                if (0.0 >= S) { W[0] = rR; W[1] = uR; W[2] = pR; }
+                else { W[0] = rR * (ps / pR + g1 / gp) / (g1 / gp * ps / pR + 1.0); W[1] = us; W[2] = ps; }
+            } else { /* right rarefaction */
+                double head = uR + cR, tail = us + cR * pow(ps / pR, g1 / (2.0 * gamma));
+                if (0.0 >= head) { W[0] = rR; W[1] = uR; W[2] = pR; }
+                else if (0.0 <= tail) { W[0] = rR * pow(ps / pR, 1.0 / gamma); W[1] = us; W[2] = ps; }
+                else fan_state(rR, uR, pR, cR, gamma, 1.0, W);
+            }
+        }
+    }
+    /* Euler flux of the face state, tangential velocities from side qt */
+    double v[3];
+    for (int a = 0; a < 3; a++) v[a] = qt[1 + a] / qt[0];
+    v[axis] = W[1];
+    double E = W[2] / g1 + 0.5 * W[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    F[0] = W[0] * W[1];
+    for (int a = 0; a < 3; a++) F[1 + a] = W[0] * W[1] * v[a];
+    F[1 + axis] += W[2];
+    F[4] = W[1] * (E + W[2]);
+}
+
+static void face_flux(const orc_cfg *cfg, const double qL[5], const double qR[5], int axis, double F[5])
+{
+    if (cfg->riemann == 1) orc_exact_riemann(qL, qR, axis, cfg->gamma, F);
+    else orc_hllc(qL, qR, axis, cfg->gamma, F);
+}
+
 /* ------------------------------------------------------------------ */
 /* Sec. 3.1: driving acceleration                                      */
 /* ------------------------------------------------------------------ */
@@ -407,10 +513,10 @@ static void cell_rhs(const orc_cfg *cfg, const tables *t, const double *y, size_
             double qa[5], qb[5], Fp[5], Fm[5];
             eval_at(y, nc, K, N, php, qa);  /* my trace on the + face */
             eval_at(y, nc, Kp, N, phm, qb); /* right neighbour's trace on its - face */
-            orc_hllc(qa, qb, axis, g, Fp);
+            face_flux(cfg, qa, qb, axis, Fp);
             eval_at(y, nc, Km, N, php, qa); /* left neighbour's trace on its + face */
             eval_at(y, nc, K, N, phm, qb);  /* my trace on the - face */
-            orc_hllc(qa, qb, axis, g, Fm);
+            face_flux(cfg, qa, qb, axis, Fm);
             for (int i = 0; i < NF; i++)
                 for (int l = 0; l < N; l++) surf[i][l] += s[axis] * (Fp[i] * php[l] - Fm[i] * phm[l]) * t->w_f[p];
         }

@@ -35,6 +35,7 @@ typedef struct {
     double box[3];      /* box lengths; cells are box[a]/n[a] wide */
     double gamma;       /* adiabatic index */
     double cfl;         /* Courant factor C of Sec. 2.4 */
+    int32_t riemann;    /* numerical flux: 0 HLLC (Toro ch. 10), 1 exact Riemann solver (Toro ch. 4) */
 } orc_cfg;
 
 typedef struct {
@@ -62,6 +63,7 @@ void orc_project(const orc_cfg *cfg, const double *qp, double *y);
 /* ---- Sec. 2.3: the operator ---- */
 void orc_euler_flux(const double q[5], int axis, double gamma, double F[5]);
 void orc_hllc(const double qL[5], const double qR[5], int axis, double gamma, double F[5]);
+void orc_exact_riemann(const double qL[5], const double qR[5], int axis, double gamma, double F[5]);
 /* r = R(y) with dy/dt + R(y) = 0 (eq. dg:eqn:time); frc may be NULL */
 void orc_rhs(const orc_cfg *cfg, const double *y, const orc_forcing *frc, double *r);
 /* R at listed cells only (cell = (z*ny + y)*nx + x); r: [ncells_list][5][N] */
