@@ -145,6 +145,32 @@ def measure_tier(args, dg, torch, prec, qp_dev, n, k):
     return out
 
 
+def exact_riemann_cost(args, dg, torch, prec, qp_dev, n, k):
+    """Stage launches of the primary tier with the exact Riemann solver as the face flux."""
+    s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing, riemann="exact")
+    if not args.no_forcing:
+        nvec, ahat, _ = driving_table(dg)
+        s.set_forcing(nvec, ahat)
+    y = s.project(qp_dev.to(s.dtype))
+    w1 = torch.empty_like(y)
+    h = s.dt(y)
+    s.stage(y, y, w1, 0.0, 1.0, h)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    ea = torch.cuda.Event(enable_timing=True)
+    eb = torch.cuda.Event(enable_timing=True)
+    ea.record(s.stream)
+    for _ in range(reps):
+        s.stage(y, y, w1, 0.0, 1.0, h)
+    eb.record(s.stream)
+    torch.cuda.synchronize()
+    ms = ea.elapsed_time(eb) / reps
+    log(args, f"[bench] {prec} stage 1 with the exact Riemann solver: {ms:.3f} ms")
+    del s, y, w1
+    torch.cuda.empty_cache()
+    return dict(tier=prec, stage1_ms=ms)
+
+
 def limiter_cost(args, dg, torch, prec, qp_dev, n, k):
     """Stage launches of the primary tier with the positivity limiter of Sec. 2.5 on the
     stage input (the paper applies it every stage; the smooth workload never needs it, so this
@@ -284,6 +310,7 @@ def main():
     lim = None if args.no_limiter else limiter_cost(args, dg, torch, prim0, qp, n, k)
     iso = None if args.no_limiter else reset_cost(args, dg, torch, prim0, qp, n, k)
     diag = diagnostics_cost(args, dg, torch, prim0, qp, n, k) if args.diagnostics else None
+    ers = None if args.no_limiter else exact_riemann_cost(args, dg, torch, prim0, qp, n, k)
     del qp
     torch.cuda.empty_cache()
     if args.copy_calibration > 0:
@@ -345,6 +372,8 @@ def main():
         line["isothermal_reset"] = iso
     if diag is not None:
         line["diagnostics"] = diag
+    if ers is not None:
+        line["exact_riemann"] = dict(ers, stage1_ms_hllc=results[ers["tier"]]["stage_ms_each"][0])
     print(json.dumps(line), flush=True)
 
 

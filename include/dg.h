@@ -62,7 +62,8 @@ enum {
     DG_CLOSURE = 2u,      /* k = 1 only: add the learned closure correction (needs dg_set_closure) */
     DG_CHECK_RANGE = 4u,  /* dg_step checks cell means for rho>0, p>0, finite after each step */
     DG_LIMIT = 8u,        /* positivity limiter of Sec. 2.5 on every stage input (see dg_limiter_stats) */
-    DG_ISOTHERMAL = 16u   /* dg_step: isothermal reset of Sec. 3.2 after every step (needs dg_set_isothermal) */
+    DG_ISOTHERMAL = 16u,  /* dg_step: isothermal reset of Sec. 3.2 after every step (needs dg_set_isothermal) */
+    DG_EXACT_RIEMANN = 32u /* face flux from the exact Riemann solver instead of HLLC (see below) */
 };
 
 typedef struct {
@@ -72,7 +73,7 @@ typedef struct {
     double gamma;       /* adiabatic index, > 1 */
     double cfl;         /* Courant factor C of Sec. 2.4, in (0, 1] */
     int32_t precision;  /* a dg_precision value */
-    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL */
+    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN */
 } dg_config;
 
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
@@ -334,6 +335,19 @@ dg_status dg_density_pdf(dg_ctx *ctx, const void *y, int32_t S, double lo, doubl
  * |v|^2 / c^2, c^2 = gamma p / rho, summed in FP64 in a fixed order.
  * out: HOST.  Synchronises. */
 dg_status dg_rms_mach(dg_ctx *ctx, const void *y, int32_t S, double *out);
+
+/* ---------------------------------------------------------------------------
+ * DG_EXACT_RIEMANN: the numerical flux of eq. dg:eqn:surface_int comes from the
+ * exact solution of each face's Riemann problem (the alternative to HLLC that
+ * Sec. 2.3 names; Toro, Riemann Solvers and Numerical Methods for Fluid
+ * Dynamics, ch. 4): the star pressure from the shock / rarefaction wave curves
+ * by Newton iteration from the primitive-variable estimate (one more step after
+ * the first whose relative change is below 1e-8 FP64 / 1e-4 otherwise; 24 at most), the solution sampled at the face and its
+ * Euler flux taken, tangential velocities from the side of the contact the face
+ * lies on; vacuum-generating data are sampled from the two rarefactions.  The
+ * rest of the scheme is unchanged.  Computed in the tier's pointwise precision
+ * (FP32 for the FP32-storage tiers).  Costs more than HLLC (iterations,
+ * divergent lanes). */
 
 #ifdef __cplusplus
 }

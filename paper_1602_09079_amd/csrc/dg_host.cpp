@@ -323,7 +323,9 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
-    if (cfg->flags & ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL)) return DG_ERR_ARG;
+    if (cfg->flags &
+        ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN))
+        return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     {
@@ -539,6 +541,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;
+    s.riemann = (c->cfg.flags & DG_EXACT_RIEMANN) ? 1 : 0;
     s.acache = c->acache;
     for (int i = 0; i < 3; i++) s.h[i] = c->h[i];
     HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));

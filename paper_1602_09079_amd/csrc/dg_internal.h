@@ -155,6 +155,7 @@ struct StageArgs {
     double h[3];          // cell widths
     const void *corr;     // closure correction c (state layout) or nullptr: R <- R - (c - cmean on mode 0)
     const double *cmean;  // [5] mean of c's mode-0 rows per field
+    int riemann;          // face flux: 0 HLLC, 1 exact Riemann solver
 };
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);

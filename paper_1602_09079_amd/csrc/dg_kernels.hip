@@ -286,6 +286,116 @@ __device__ inline void hllc(const C qL[5], const C qR[5], C gam, C F[5]) {
     for (int i = 0; i < 5; i++) F[i] = plain ? FK[i] : Fs[i] * inv;
 }
 
+// x^y for x > 0 in the precision of C (FP32: hardware base-2 logarithm and exponential)
+__device__ inline float powpos(float x, float y) { return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x)); }
+__device__ inline double powpos(double x, double y) { return pow(x, y); }
+
+// Exact Riemann solver (the alternative to HLLC; Toro, Riemann Solvers and Numerical Methods
+// for Fluid Dynamics, ch. 4) across a face normal to AXIS.  The star pressure p* is the root of
+// f_L(p) + f_R(p) + u_R - u_L, each f_K the shock branch (p > p_K) or the rarefaction branch,
+// found by Newton from the primitive-variable estimate, kept positive; the wave pattern is
+// sampled at x/t = 0 and the Euler flux of that state returned, the tangential velocities
+// taken from the side of the contact the face lies on.  Vacuum-generating data (2(c_L + c_R)/
+// (gamma-1) <= u_R - u_L) are sampled from the two rarefactions and the vacuum between them.
+template <class PR, int AXIS, class C>
+__device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
+    const C g1 = gam - C(1), gp = gam + C(1), z = g1 / (C(2) * gam);
+    const C iL = C(1) / qL[0], iR = C(1) / qR[0];
+    const C rL = qL[0], rR = qR[0];
+    const C uL = qL[1 + AXIS] * iL, uR = qR[1 + AXIS] * iR;
+    const C pL = g1 * (qL[4] - C(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
+    const C pR = g1 * (qR[4] - C(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
+    const C cL = PR::sqrt_(gam * pL * iL), cR = PR::sqrt_(gam * pR * iR);
+    // f_K and its derivative
+    auto wave = [&](C p, C rK, C pK, C cK, C &df) -> C {
+        if (p > pK) {
+            const C A = C(2) / (gp * rK), Bk = g1 / gp * pK;
+            const C sq = PR::sqrt_(A / (p + Bk));
+            df = sq * (C(1) - C(0.5) * (p - pK) / (p + Bk));
+            return (p - pK) * sq;
+        }
+        const C pr = p / pK;
+        const C t = powpos(pr, z);
+        df = t / (pr * rK * cK);
+        return C(2) * cK / g1 * (t - C(1));
+    };
+    C W0, W1, W2;  // face state: rho, normal velocity, pressure
+    bool from_left;
+    const C du = uR - uL;
+    auto fan = [&](C rK, C uK, C pK, C cK, C sgn) {  // sgn = -1 left fan, +1 right fan
+        const C c = C(2) / gp - sgn * g1 / (gp * cK) * uK;
+        W0 = rK * powpos(c, C(2) / g1);
+        W1 = C(2) / gp * (-sgn * cK + C(0.5) * g1 * uK);
+        W2 = pK * powpos(c, C(2) * gam / g1);
+    };
+    if (C(2) * (cL + cR) / g1 <= du) {
+        const C sL = uL + C(2) * cL / g1, sR = uR - C(2) * cR / g1;
+        if (C(0) <= sL) {
+            from_left = true;
+            if (C(0) <= uL - cL) { W0 = rL; W1 = uL; W2 = pL; }
+            else fan(rL, uL, pL, cL, C(-1));
+        } else if (C(0) >= sR) {
+            from_left = false;
+            if (C(0) >= uR + cR) { W0 = rR; W1 = uR; W2 = pR; }
+            else fan(rR, uR, pR, cR, C(1));
+        } else {
+            from_left = true;
+            W0 = C(0); W1 = C(0); W2 = C(0);
+        }
+    } else {
+        const C tiny = (sizeof(C) == 8 ? C(1e-300) : C(1e-30));
+        C p = C(0.5) * (pL + pR) - C(0.125) * du * (rL + rR) * (cL + cR);
+        p = p > tiny ? p : tiny;
+        // Newton converges quadratically: once a step changes p by less than tol2 (relative), one
+        // more step brings it to rounding, then stop
+        const C tol2 = sizeof(C) == 8 ? C(1e-8) : C(1e-4);
+        bool last = false;
+        for (int it = 0; it < 24; it++) {
+            C dfL, dfR;
+            const C f = wave(p, rL, pL, cL, dfL) + wave(p, rR, pR, cR, dfR) + du;
+            C pn = p - f * PR::rcp(dfL + dfR);
+            pn = pn > tiny ? pn : C(0.1) * p;
+            const C ch = __builtin_fabs(pn - p) * PR::rcp(pn + p);
+            p = pn;
+            if (last) break;
+            last = ch <= tol2;
+        }
+        C d0, d1;
+        const C us = C(0.5) * (uL + uR) + C(0.5) * (wave(p, rR, pR, cR, d1) - wave(p, rL, pL, cL, d0));
+        from_left = C(0) <= us;
+        const C rK = from_left ? rL : rR, uK = from_left ? uL : uR, pK = from_left ? pL : pR;
+        const C cK = from_left ? cL : cR, sg = from_left ? C(-1) : C(1);
+        // in the frame mirrored for the right side, every test reads as for the left side
+        if (p > pK) {
+            const C S = uK + sg * cK * PR::sqrt_(gp / (C(2) * gam) * p / pK + g1 / (C(2) * gam));
+            if (sg * S <= C(0)) { W0 = rK; W1 = uK; W2 = pK; }
+            else {
+                W0 = rK * (p / pK + g1 / gp) / (g1 / gp * p / pK + C(1));
+                W1 = us; W2 = p;
+            }
+        } else {
+            const C head = uK + sg * cK;
+            const C tail = us + sg * cK * powpos(p / pK, z);
+            if (sg * head <= C(0)) { W0 = rK; W1 = uK; W2 = pK; }
+            else if (sg * tail >= C(0)) { W0 = rK * powpos(p / pK, C(1) / gam); W1 = us; W2 = p; }
+            else fan(rK, uK, pK, cK, sg);
+        }
+    }
+    const C *qt = from_left ? qL : qR;
+    const C it = from_left ? iL : iR;
+    C v[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) v[a] = qt[1 + a] * it;
+    v[AXIS] = W1;
+    const C E = W2 / g1 + C(0.5) * W0 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const C mflux = W0 * W1;
+    F[0] = mflux;
+#pragma unroll
+    for (int a = 0; a < 3; a++) F[1 + a] = mflux * v[a];
+    F[1 + AXIS] += W2;
+    F[4] = W1 * (E + W2);
+}
+
 // ------------------------------------------------------------------ table geometry (matches make_layout)
 
 template <int K, int PREC>
@@ -417,7 +527,7 @@ __device__ inline void accel_load(__amdgpu_buffer_rsrc_t r, unsigned off, double
     v[3] = w1[1];
 }
 
-template <int K, int PREC, bool FORCE>
+template <int K, int PREC, bool FORCE, int RS>
 __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<PREC>(), stage_waves_per_eu<PREC>()))) void stage_kernel(StageArgs a) {
     using SC = StageCfg<K, PREC>;
     using PR = typename SC::PR;
@@ -545,7 +655,10 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                 qL[i] = valid ? tl[i][r] : C(i == 0 ? 1 : (i == 4 ? 2 : 0));
                 qR[i] = valid ? tr_[i][r] : C(i == 0 ? 1 : (i == 4 ? 2 : 0));
             }
-            hllc<PR, AX>(qL, qR, gam, F);
+            if constexpr (RS == 1)
+                exact_rs<PR, AX>(qL, qR, gam, F);
+            else
+                hllc<PR, AX>(qL, qR, gam, F);
 #pragma unroll
             for (int i = 0; i < 5; i++) Fo[i][r] = F[i];
         }
@@ -955,20 +1068,31 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 template <int K, int PREC>
 static hipError_t launch_stage_t(const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
     constexpr int T = stage_threads<PREC>();
-    if (a.forcing)
-        hipLaunchKernelGGL((stage_kernel<K, PREC, true>), dim3(grid), dim3(T), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL((stage_kernel<K, PREC, false>), dim3(grid), dim3(T), lds_bytes, s, a);
+    if (a.riemann == 1) {
+        if (a.forcing)
+            hipLaunchKernelGGL((stage_kernel<K, PREC, true, 1>), dim3(grid), dim3(T), lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((stage_kernel<K, PREC, false, 1>), dim3(grid), dim3(T), lds_bytes, s, a);
+    } else {
+        if (a.forcing)
+            hipLaunchKernelGGL((stage_kernel<K, PREC, true, 0>), dim3(grid), dim3(T), lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((stage_kernel<K, PREC, false, 0>), dim3(grid), dim3(T), lds_bytes, s, a);
+    }
     return hipGetLastError();
 }
 
 template <int K, int PREC>
 static hipError_t set_attr_t(int lds_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_kernel<K, PREC, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_kernel<K, PREC, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    const void *fns[] = {reinterpret_cast<const void *>(&stage_kernel<K, PREC, false, 0>),
+                         reinterpret_cast<const void *>(&stage_kernel<K, PREC, true, 0>),
+                         reinterpret_cast<const void *>(&stage_kernel<K, PREC, false, 1>),
+                         reinterpret_cast<const void *>(&stage_kernel<K, PREC, true, 1>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define DG_DISPATCH(k, prec, CALL, ARGS)                                             \
@@ -992,7 +1116,7 @@ hipError_t set_stage_attributes(int k, int prec, int lds_bytes) {
 
 template <int K, int PREC>
 static hipError_t occ_t(int lds_bytes, int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC, true>, stage_threads<PREC>(),
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_kernel<K, PREC, true, 0>, stage_threads<PREC>(),
                                                         lds_bytes);
 }
 

@@ -18,6 +18,7 @@ DG_CLOSURE = 2
 DG_CHECK_RANGE = 4
 DG_LIMIT = 8
 DG_ISOTHERMAL = 16
+DG_EXACT_RIEMANN = 32
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
                 5: "DG_ERR_STATE"}
 
@@ -162,8 +163,13 @@ class Solver:
     """One DG context on the current CUDA (HIP) device and stream."""
 
     def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
-                 forcing=False, check_range=False, closure=False, limit=False, isothermal=False, stream=None):
+                 forcing=False, check_range=False, closure=False, limit=False, isothermal=False, riemann="hllc",
+                 stream=None):
         import torch
+        if riemann not in ("hllc", "exact"):
+            raise ValueError("riemann must be 'hllc' or 'exact'")
+        if riemann == "exact":
+            flags |= DG_EXACT_RIEMANN
         if isothermal:
             flags |= DG_ISOTHERMAL
         if forcing:
