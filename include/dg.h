@@ -44,7 +44,7 @@ typedef struct dg_ctx dg_ctx;
 typedef enum {
     DG_OK = 0,
     DG_ERR_ARG = 1,          /* invalid argument or configuration */
-    DG_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. k outside 1..3) */
+    DG_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. k > 3) */
     DG_ERR_HIP = 3,          /* a HIP runtime call failed */
     DG_ERR_RANGE = 4,        /* non-physical state detected (DG_CHECK_RANGE) */
     DG_ERR_STATE = 5         /* call out of order (e.g. forcing flag without a table) */
@@ -67,7 +67,7 @@ enum {
 };
 
 typedef struct {
-    int32_t k;          /* polynomial degree; this build supports 1, 2, 3 */
+    int32_t k;          /* polynomial degree; this build supports 0 (first-order finite volume), 1, 2, 3 */
     int32_t n[3];       /* cells per axis, each >= 2 */
     double box[3];      /* box lengths (> 0); cell widths are box[a]/n[a] */
     double gamma;       /* adiabatic index, > 1 */
@@ -79,7 +79,7 @@ typedef struct {
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
  * upload them and allocate the context's small device slots (dt, time,
  * partial sums).  hip_stream: a hipStream_t (NULL = default stream).
- * DG_ERR_ARG and no context for: k < 1, any n < 2, box <= 0, gamma <= 1,
+ * DG_ERR_ARG and no context for: k < 0, any n < 2, box <= 0, gamma <= 1,
  * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3,
  * DG_CLOSURE with k != 1, or a slab (5 N(k) n[0] elements) of 2 GiB or more. */
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out);

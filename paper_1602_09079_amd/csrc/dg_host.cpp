@@ -317,7 +317,7 @@ const char *dg_error_string(const dg_ctx *ctx) { return ctx ? ctx->err.c_str() :
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!cfg || !out) return DG_ERR_ARG;
     *out = nullptr;
-    if (cfg->k < 1) return DG_ERR_ARG;
+    if (cfg->k < 0) return DG_ERR_ARG;
     for (int a = 0; a < 3; a++)
         if (cfg->n[a] < 2 || !(cfg->box[a] > 0.0) || !std::isfinite(cfg->box[a])) return DG_ERR_ARG;
     if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
@@ -350,14 +350,17 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         c->h[a] = cfg->box[a] / cfg->n[a];
         s[a] = 1.0 / (4.0 * c->h[a]);  // (dx^2/4) / |K| of eqs. dg:eqn:volume_int and dg:eqn:surface_int
     }
-    c->lay = make_layout(cfg->k, cfg->precision);
     auto fail = [&](dg_status st) {
         dg_destroy(c);
         return st;
     };
-    const std::vector<char> blob = build_tables(c->lay, s);
-    if (hipMalloc(&c->tables, blob.size()) != hipSuccess) return fail(DG_ERR_HIP);
-    if (hipMemcpy(c->tables, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail(DG_ERR_HIP);
+    if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
+        c->lay = make_layout(cfg->k, cfg->precision);
+        const std::vector<char> blob = build_tables(c->lay, s);
+        if (hipMalloc(&c->tables, blob.size()) != hipSuccess) return fail(DG_ERR_HIP);
+        if (hipMemcpy(c->tables, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(DG_ERR_HIP);
+    }
     // projection table: phi_l(xi_q) w_q / 8
     {
         const Basis B(cfg->k);
@@ -408,6 +411,11 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipMemset(c->slots, 0, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->flag, sizeof(int)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
+    if (cfg->k == 0) {
+        c->grid = (int)std::min<long long>((ncells + 255) / 256, 1LL << 30);
+        *out = c;
+        return DG_OK;
+    }
     {
         int dev0 = 0, maxlds = 0;
         if (hipGetDevice(&dev0) != hipSuccess ||

@@ -1065,6 +1065,100 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     }
 }
 
+// k = 0: one weight per field, and the scheme is first-order Godunov finite volume:
+// R = sum_a (Fhat(q, q_{+a}) - Fhat(q_{-a}, q)) / h_a minus the source at the cell centre (the
+// single Gauss point).  One thread per cell; the six neighbours' weights are read directly (each
+// face is solved by both of its cells), no products, no LDS.
+constexpr int FV_THREADS = 256;
+
+template <int PREC, bool FORCE, int RS>
+__global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
+    using PR = Prec<PREC>;
+    using S = typename PR::S;
+    using C = typename PR::C;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double dtd = a.dt;
+    if (a.rate) dtd = a.dtfac / a.rate[0];
+    if (a.tacc && blockIdx.x == 0 && threadIdx.x == 0) a.tacc[0] += dtd;
+    if (cell >= a.ncells) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int ix = (int)(cell % nx);
+    const long long row = cell / nx;
+    const int iy = (int)(row % ny), iz = (int)(row / ny);
+    const S *yin = static_cast<const S *>(a.yin);
+    auto load = [&](int x, int yy, int zz, C q[5]) {
+        x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        const long long b = ((long long)zz * ny + yy) * NF * nx + x;
+#pragma unroll
+        for (int i = 0; i < NF; i++) q[i] = (C)yin[b + (long long)i * nx];
+    };
+    const C gam = (C)a.gamma;
+    auto flux = [&](auto axis_c, const C qL[5], const C qR[5], C F[5]) {
+        constexpr int AX = decltype(axis_c)::value;
+        if constexpr (RS == 1)
+            exact_rs<PR, AX>(qL, qR, gam, F);
+        else
+            hllc<PR, AX>(qL, qR, gam, F);
+    };
+    C q[5], R[5] = {0, 0, 0, 0, 0};
+    load(ix, iy, iz, q);
+    auto axis_term = [&](auto axis_c, int dx, int dy, int dz) {
+        constexpr int AX = decltype(axis_c)::value;
+        C qm[5], qp[5], Fm[5], Fp[5];
+        load(ix - dx, iy - dy, iz - dz, qm);
+        load(ix + dx, iy + dy, iz + dz, qp);
+        flux(axis_c, qm, q, Fm);
+        flux(axis_c, q, qp, Fp);
+        const C ih = (C)(1.0 / a.h[AX]);
+#pragma unroll
+        for (int i = 0; i < NF; i++) R[i] += (Fp[i] - Fm[i]) * ih;
+    };
+    axis_term(std::integral_constant<int, 0>{}, 1, 0, 0);
+    axis_term(std::integral_constant<int, 1>{}, 0, 1, 0);
+    axis_term(std::integral_constant<int, 2>{}, 0, 0, 1);
+    if constexpr (FORCE) {
+        // the driving acceleration at the cell centre, from the k = 0 cache layout (point 0 of tile 0)
+        const S *ac = static_cast<const S *>(a.acache) + row * (16LL * 3 * nx) + (long long)ix * 4;
+        C sE = 0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const C av = (C)ac[(long long)c * 16 * nx];
+            R[1 + c] -= q[0] * av;
+            sE += q[1 + c] * av;
+        }
+        R[4] -= sE;
+    }
+    S *out = static_cast<S *>(a.out);
+    const S *y0 = static_cast<const S *>(a.y0);
+    const long long b = row * NF * nx + ix;
+    const C dt = (C)dtd;
+#pragma unroll
+    for (int i = 0; i < NF; i++) {
+        const long long j = b + (long long)i * nx;
+        if (a.mode == 0) {
+            out[j] = (S)R[i];
+        } else {
+            const C base = (C)a.b * (q[i] - dt * R[i]);
+            out[j] = (S)(a.a != 0.0 ? (C)a.a * (C)y0[j] + base : base);
+        }
+    }
+}
+
+template <int PREC>
+static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
+    const long long nb = (a.ncells + FV_THREADS - 1) / FV_THREADS;
+    if (a.riemann == 1) {
+        if (a.forcing) hipLaunchKernelGGL((fv_stage_kernel<PREC, true, 1>), dim3(nb), dim3(FV_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((fv_stage_kernel<PREC, false, 1>), dim3(nb), dim3(FV_THREADS), 0, s, a);
+    } else {
+        if (a.forcing) hipLaunchKernelGGL((fv_stage_kernel<PREC, true, 0>), dim3(nb), dim3(FV_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((fv_stage_kernel<PREC, false, 0>), dim3(nb), dim3(FV_THREADS), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 template <int K, int PREC>
 static hipError_t launch_stage_t(const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
     constexpr int T = stage_threads<PREC>();
@@ -1107,6 +1201,15 @@ static hipError_t set_attr_t(int lds_bytes) {
     }
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
+    if (k == 0) {
+        switch (prec) {
+            case DG_FP64: return launch_fv_t<DG_FP64>(a, s);
+            case DG_FP32: return launch_fv_t<DG_FP32>(a, s);
+            case DG_BF16: return launch_fv_t<DG_BF16>(a, s);
+            case DG_BF16X3: return launch_fv_t<DG_BF16X3>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     DG_DISPATCH(k, prec, launch_stage_t, (a, grid, lds_bytes, s))
 }
 
@@ -1170,6 +1273,7 @@ static hipError_t launch_project_k(int prec, const void *qp, void *y, const doub
 hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long nc, int nx,
                           hipStream_t s) {
     switch (k) {
+        case 0: return launch_project_k<0>(prec, qp, y, ptab, nc, nx, s);
         case 1: return launch_project_k<1>(prec, qp, y, ptab, nc, nx, s);
         case 2: return launch_project_k<2>(prec, qp, y, ptab, nc, nx, s);
         case 3: return launch_project_k<3>(prec, qp, y, ptab, nc, nx, s);
@@ -1233,6 +1337,7 @@ static hipError_t launch_accel_k(int prec, const double *modes, int nmodes, int 
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
                               const GaussNodes &xg, void *out, hipStream_t s) {
     switch (k) {
+        case 0: return launch_accel_k<0>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
         case 1: return launch_accel_k<1>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
         case 2: return launch_accel_k<2>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
         case 3: return launch_accel_k<3>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
@@ -1388,6 +1493,7 @@ static hipError_t launch_limit_k(int prec, void *y, const double *tab, int np, l
 hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, long long nc, int nx, double gamma,
                         double eps, unsigned long long *count, hipStream_t s) {
     switch (k) {
+        case 0: return launch_limit_k<0>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         case 1: return launch_limit_k<1>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         case 2: return launch_limit_k<2>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         case 3: return launch_limit_k<3>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
@@ -1566,6 +1672,7 @@ static hipError_t launch_reset_k(int prec, void *y, const Leg1D &L, long long nc
 hipError_t launch_reset(int k, int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
                         double rho0, double vol, double *partials, double *acc, hipStream_t s) {
     switch (k) {
+        case 0: return launch_reset_k<0>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
         case 1: return launch_reset_k<1>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
         case 2: return launch_reset_k<2>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);
         case 3: return launch_reset_k<3>(prec, y, L, nc, nx, gm1, ce, rho0, vol, partials, acc, s);

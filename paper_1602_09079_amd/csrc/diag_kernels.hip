@@ -189,6 +189,7 @@ static hipError_t launch_sample_k(int S, int prec, const SampleArgs &a, const Le
 
 hipError_t launch_sample(int k, int S, int prec, const SampleArgs &a, const Leg1D &L, hipStream_t s) {
     switch (k) {
+        case 0: return launch_sample_k<0>(S, prec, a, L, s);
         case 1: return launch_sample_k<1>(S, prec, a, L, s);
         case 2: return launch_sample_k<2>(S, prec, a, L, s);
         case 3: return launch_sample_k<3>(S, prec, a, L, s);

@@ -66,7 +66,7 @@ def test_ou_update_matches_oracle():
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(k=0, n=8), dg.DG_ERR_ARG),
+    (dict(k=-1, n=8), dg.DG_ERR_ARG),
     (dict(k=4, n=8), dg.DG_ERR_UNSUPPORTED),
     (dict(k=1, n=(8, 1, 8)), dg.DG_ERR_ARG),
     (dict(k=1, n=8, box=(1.0, 0.0, 1.0)), dg.DG_ERR_ARG),
