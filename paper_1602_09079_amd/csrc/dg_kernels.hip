@@ -1694,12 +1694,19 @@ __device__ inline long long mean_index(long long cell, int i, int N, int nx) {
     return ((r * NF + i) * N) * nx + (cell - r * nx);
 }
 
+// Grid-stride over the cells with a fixed grid: each thread keeps the largest rate of its cells, the
+// workgroup reduces them (wave shuffles, then LDS), and one atomic max per workgroup goes to the slot
+// (a per-wave atomic on one address serialised ~260k atomics per call at 256^3).
+constexpr int CFL_THREADS = 256, CFL_BLOCKS = 2048;
+
 template <class S>
-__global__ void cfl_kernel(const S *__restrict__ y, int N, int nx, long long nc, double gamma, double hx, double hy,
-                           double hz, double *rate_slot, double *zero_slot) {
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(CFL_THREADS) void cfl_kernel(const S *__restrict__ y, int N, int nx, long long nc,
+                                                          double gamma, double hx, double hy, double hz,
+                                                          double *rate_slot, double *zero_slot) {
+    __shared__ double wmax[CFL_THREADS / 64];
     double rate = 0.0;
-    if (cell < nc) {
+    for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < nc;
+         cell += (long long)gridDim.x * blockDim.x) {
         const double rho = (double)y[mean_index(cell, 0, N, nx)];
         const double mx = (double)y[mean_index(cell, 1, N, nx)];
         const double my = (double)y[mean_index(cell, 2, N, nx)];
@@ -1708,25 +1715,32 @@ __global__ void cfl_kernel(const S *__restrict__ y, int N, int nx, long long nc,
         const double inv = 1.0 / rho;
         const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) * inv);
         const double c = sqrt(gamma * p * inv);
-        rate = (fabs(mx * inv) + c) / hx + (fabs(my * inv) + c) / hy + (fabs(mz * inv) + c) / hz;
-        if (!(rate >= 0.0)) rate = __builtin_inf();  // non-physical cell: force dt -> 0
+        double r = (fabs(mx * inv) + c) / hx + (fabs(my * inv) + c) / hy + (fabs(mz * inv) + c) / hz;
+        if (!(r >= 0.0)) r = __builtin_inf();  // non-physical cell: force dt -> 0
+        rate = fmax(rate, r);
     }
     rate = wave_max(rate);
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(reinterpret_cast<unsigned long long *>(rate_slot), (unsigned long long)__double_as_longlong(rate));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rate;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int w = 1; w < CFL_THREADS / 64; w++) m = fmax(m, wmax[w]);
+        // the bit patterns of non-negative doubles order like their values
+        atomicMax(reinterpret_cast<unsigned long long *>(rate_slot), (unsigned long long)__double_as_longlong(m));
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0 && zero_slot) *zero_slot = 0.0;
 }
 
 hipError_t launch_cfl(int prec, const void *y, int N, int nx, long long nc, double gamma, const double h[3],
                       double *rate_slot, double *zero_slot, hipStream_t s) {
-    const int th = 256;
-    const long long nb = (nc + th - 1) / th;
+    long long nb = (nc + CFL_THREADS - 1) / CFL_THREADS;
+    if (nb > CFL_BLOCKS) nb = CFL_BLOCKS;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((cfl_kernel<double>), dim3(nb), dim3(th), 0, s, (const double *)y, N, nx, nc, gamma, h[0],
-                           h[1], h[2], rate_slot, zero_slot);
+        hipLaunchKernelGGL((cfl_kernel<double>), dim3(nb), dim3(CFL_THREADS), 0, s, (const double *)y, N, nx, nc, gamma,
+                           h[0], h[1], h[2], rate_slot, zero_slot);
     else
-        hipLaunchKernelGGL((cfl_kernel<float>), dim3(nb), dim3(th), 0, s, (const float *)y, N, nx, nc, gamma, h[0],
-                           h[1], h[2], rate_slot, zero_slot);
+        hipLaunchKernelGGL((cfl_kernel<float>), dim3(nb), dim3(CFL_THREADS), 0, s, (const float *)y, N, nx, nc, gamma,
+                           h[0], h[1], h[2], rate_slot, zero_slot);
     return hipGetLastError();
 }
 
