@@ -814,6 +814,11 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     // wave (5 x 4 values per lane).  When the two regions do not both fit, they coincide and two
     // more barriers order the reuse (a.ex_single).
     C *ex_t = reinterpret_cast<C *>(lds + a.ex_off);
+    // BF16 tiers: y0 of up to four slots travels through the trace region (see the second y-face
+    // barrier).  The FP32 tier keeps register loads: there the extra live range costs spills.
+    constexpr int DMA_SL = SPL < 4 ? SPL : 4;  // slots of y0 that fit a wave's part of the trace region
+    constexpr bool DMA = YSH && (PREC == DG_BF16 || PREC == DG_BF16X3);
+    const bool dma_y0 = DMA && !a.ex_single && a.mode != 0 && a.a != 0.0;
     C *ex_f = reinterpret_cast<C *>(lds + a.ex_off2);
     auto ex_put = [&](C *ex, int slot, const C v[NF][4]) {
 #pragma unroll
@@ -952,6 +957,21 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                     ex_put(ex_f, wrow, Fp);
                 }
                 __syncthreads();
+                // the trace region is free until the next step's puts: the stage-combine input y0 of
+                // this wave's slots (four at most) is copied into its part by the load unit now, so the
+                // round trip hides behind the remaining faces
+                if (DMA && dma_y0 && act) {
+                    const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
+#pragma unroll
+                    for (int u = 0; u < DMA_SL; u++) {
+                        unsigned eo = KPL == 1 ? boff[u][0] : boff[0][u];
+#pragma unroll
+                        for (int i = 0; i < NF; i++)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                r0, (__attribute__((address_space(3))) void *)(ex_t + ((wrow * NF + i) * 4 + u) * 64),
+                                (int)sizeof(S), eo, (int)((unsigned)i * fbytes), 0, 0);
+                    }
+                }
                 if (wrow > 0) {
                     C Fm[NF][4];
                     ex_get(ex_f, wrow - 1, Fm);
@@ -1014,7 +1034,23 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                         asm volatile("" : "+v"(eo[u]));
                     }
                     C y0v[NF][EG], cv[NF][EG];
-                    if (with0) {
+                    if (DMA && dma_y0) {
+                        // slots past the copied ones are loaded here
+#pragma unroll
+                        for (int u = 0; u < EG; u++)
+                            if (s0 + u >= DMA_SL) {
+                                const auto r0 = slab_rsrc(y0, slabn, rz);
+#pragma unroll
+                                for (int i = 0; i < NF; i++) y0v[i][u] = (C)bload(S(), r0, eo[u], (unsigned)i * fbytes);
+                            }
+                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies into LDS have landed
+#pragma unroll
+                        for (int u = 0; u < EG; u++)
+                            if (s0 + u < DMA_SL) {
+#pragma unroll
+                                for (int i = 0; i < NF; i++) y0v[i][u] = ex_t[((wrow * NF + i) * 4 + s0 + u) * 64 + lane];
+                            }
+                    } else if (with0) {
                         const auto r0 = slab_rsrc(y0, slabn, rz);
 #pragma unroll
                         for (int u = 0; u < EG; u++)
