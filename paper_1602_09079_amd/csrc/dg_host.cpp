@@ -431,6 +431,11 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             c->lds = c->ex_off + exb;
         }
         if (c->lds > maxlds) return fail(DG_ERR_UNSUPPORTED);
+        const int erb = (int)stage_endrow_bytes(cfg->precision, cfg->k);
+        if (erb > 0 && c->lds + erb <= maxlds) {
+            c->ex_off3 = c->lds;
+            c->lds += erb;
+        }
     }
     if (set_stage_attributes(cfg->k, cfg->precision, c->lds) != hipSuccess) return fail(DG_ERR_HIP);
     int dev = 0, ncu = 0, per_cu = 0;
@@ -546,6 +551,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.ex_off = c->ex_off;
     s.ex_off2 = c->ex_off2;
     s.ex_single = c->ex_off2 == c->ex_off ? 1 : 0;
+    s.ex_off3 = c->ex_off3;
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;

@@ -59,6 +59,11 @@ inline int stage_block_threads(int prec) { return prec == DG_FP64 ? 256 : 64 * Y
 inline int stage_rows_per_item(int prec) { return prec == DG_FP64 ? 1 : YROWS; }
 // LDS bytes of one y-face exchange region: a slot of 5 fields x 4 values x 64 lanes per wave
 inline size_t stage_exchange_bytes(int prec) { return prec == DG_FP64 ? 0 : (size_t)YROWS * NF * 4 * 64 * 4; }
+// the two end rows of a workgroup's y group, prefetched into LDS: the mean and the mode slots of
+// every field per lane (FP32 storage)
+inline size_t stage_endrow_bytes(int prec, int k) {
+    return prec == DG_FP64 ? 0 : (size_t)2 * NF * (1 + (nmodes_of(k) + 3) / 4) * 64 * 4;
+}
 
 // Geometry of the MFMA operand tables for one (k, precision).  A "fragment" is
 // what the 64 lanes feed to one MFMA as its A operand.  GEMM1/3/4 use the wide
@@ -148,6 +153,7 @@ struct StageArgs {
     int ex_off;           // LDS byte offset of the y-face trace slots
     int ex_off2;          // LDS byte offset of the y-face flux slots (== ex_off: shared, ex_single = 1)
     int ex_single;
+    int ex_off3;          // LDS byte offset of the end-row buffers, or -1 when they do not fit
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
@@ -246,6 +252,7 @@ struct dg_ctx {
     int zlen = 1;                  // z chunk length of the stage sweep
     int ex_off = 0;                // LDS offsets of the y-face trace and flux regions (after the tables)
     int ex_off2 = 0;
+    int ex_off3 = -1;              // LDS offset of the end-row buffers (-1: not used)
     int cur_slot = 1;              // slot holding the latest CFL rate
     int lds = 0;
     long long step_count = 0;

@@ -613,6 +613,55 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             }
         }
     };
+    // end rows of the y group (waves 0 and nact-1): copied into LDS by buffer loads one step ahead
+    constexpr int ERV = NF * (1 + SPL);  // values per lane of a block: the mean and the slots, per field
+    const bool erows = YSH && a.ex_off3 >= 0;
+    C *ex_e = reinterpret_cast<C *>(lds + (a.ex_off3 >= 0 ? a.ex_off3 : 0));
+    // the block of slab r copied into LDS buffer e (0: the row below the group, 1: the row above)
+    auto load_lds = [&](long long r, int e) {
+      if constexpr (YSH) {
+        const auto rs = slab_rsrc(yin, slabn, r);
+        C *dst = ex_e + e * ERV * 64;
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            const int so = (int)((unsigned)i * fbytes);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (__attribute__((address_space(3))) void *)(dst + (i * (1 + SPL)) * 64), (int)sizeof(S), xoff, so, 0,
+                0);
+#pragma unroll
+            for (int s = 0; s < SPL; s++) {
+                const unsigned vo = KPL == 1 ? boff[s][0] : boff[0][s];
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void *)(dst + (i * (1 + SPL) + 1 + s) * 64), (int)sizeof(S),
+                    vo, so, 0, 0);
+            }
+        }
+      }
+    };
+    auto read_lds = [&](int e, B &b) {
+      if constexpr (YSH) {
+        // vmcnt(0): the copies have landed (the compiler does not track them); the memory clobber keeps
+        // the LDS reads below the wait
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        asm volatile("" ::: "memory");
+        const C *src = ex_e + e * ERV * 64;
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            b.qbar[i] = src[(i * (1 + SPL)) * 64 + lane];
+#pragma unroll
+            for (int s = 0; s < SPL; s++) {
+                const C v = src[(i * (1 + SPL) + 1 + s) * 64 + lane];
+                if constexpr (B::RAW) {
+                    b.v[i][s] = v;
+                } else {
+                    C vv[KPL];
+                    vv[0] = v;
+                    b.w[i][s] = PR::mkb(vv);
+                }
+            }
+        }
+      }
+    };
     // B operand of field i, K-step s of a block (converted here for the BF16 tiers)
     auto bop = [&](const B &b, int i, int s) -> typename PR::BF {
         if constexpr (B::RAW) {
@@ -866,6 +915,10 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             return (long long)zz * ny + yy;
         };
 
+        if (erows && act) {
+            if (wrow == 0) load_lds(cidx(iy0 - 1, z0), 0);
+            if (wrow == nact - 1) load_lds(cidx(iy0 + nact, z0), 1);
+        }
         T.refresh();
         B cur;
         load(cidx(iy, z0), cur);
@@ -929,8 +982,14 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                             C tb[NF][4];
                             {
                                 B nb;
-                                load(cidx(iy0 - 1, z), nb);
-                                trace(nb, 3, tb);
+                                if (erows) {
+                                    read_lds(0, nb);
+                                    trace(nb, 3, tb);
+                                    if (z + 1 < z1) load_lds(cidx(iy0 - 1, z + 1), 0);  // reads consumed above
+                                } else {
+                                    load(cidx(iy0 - 1, z), nb);
+                                    trace(nb, 3, tb);
+                                }
                             }
                             riemann(std::integral_constant<int, 1>{}, tb, tm, Fm);
                         }
@@ -945,8 +1004,14 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                         trace(cur, 3, tp);
                         if (wrow == nact - 1) {
                             B nb;
-                            load(cidx(iy0 + nact, z), nb);
-                            trace(nb, 2, ta);
+                            if (erows) {
+                                read_lds(1, nb);
+                                trace(nb, 2, ta);
+                                if (z + 1 < z1) load_lds(cidx(iy0 + nact, z + 1), 1);  // reads consumed above
+                            } else {
+                                load(cidx(iy0 + nact, z), nb);
+                                trace(nb, 2, ta);
+                            }
                         } else {
                             ex_get(ex_t, wrow + 1 < ROWS ? wrow + 1 : wrow, ta);
                         }
@@ -1043,7 +1108,10 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 #pragma unroll
                                 for (int i = 0; i < NF; i++) y0v[i][u] = (C)bload(S(), r0, eo[u], (unsigned)i * fbytes);
                             }
-                        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies into LDS have landed
+                        // vmcnt(0): the copies into LDS have landed (the compiler does not track them);
+                        // the memory clobber keeps the LDS reads below the wait
+                        __builtin_amdgcn_s_waitcnt(0x0F70);
+                        asm volatile("" ::: "memory");
 #pragma unroll
                         for (int u = 0; u < EG; u++)
                             if (s0 + u < DMA_SL) {
