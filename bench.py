@@ -145,6 +145,48 @@ def measure_tier(args, dg, torch, prec, qp_dev, n, k):
     return out
 
 
+def share_cost(args, dg, torch, prec, qp_dev, n, k, parts=8):
+    """One GPU's share of the mesh split into `parts` z slabs (n x n x n/parts cells, halo planes
+    instead of the periodic wrap): stage launch time, and the two halo planes a stage needs (their
+    bytes, and a device-to-device copy of them standing in for the transfer)."""
+    dz = n // parts
+    s = dg.Solver(k, (n, n, dz), precision=prec, cfl=0.3, forcing=not args.no_forcing, zhalo=True)
+    s.set_slab(0, n)
+    if not args.no_forcing:
+        nvec, ahat, _ = driving_table(dg)
+        s.set_forcing(nvec, ahat)
+    y = s.project(qp_dev[:, :, :, :, :dz].contiguous().to(s.dtype))
+    lo, hi = torch.empty_like(y[0]), torch.empty_like(y[0])
+    src_lo, src_hi = y[-1].clone(), y[0].clone()
+    s.set_halo(lo, hi)
+    w1 = torch.empty_like(y)
+    lo.copy_(src_lo)
+    hi.copy_(src_hi)
+    h = s.dt(y)
+    s.stage(y, y, w1, 0.0, 1.0, h)
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(s.stream)
+    for _ in range(reps):
+        lo.copy_(src_lo)
+        hi.copy_(src_hi)
+    ev[1].record(s.stream)
+    for _ in range(reps):
+        s.stage(y, y, w1, 0.0, 1.0, h)
+    ev[2].record(s.stream)
+    torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / reps
+    ms = ev[1].elapsed_time(ev[2]) / reps
+    plane = lo.numel() * lo.element_size()
+    log(args, f"[bench] {prec} one GPU's share of a {parts}-way z split ({n}x{n}x{dz}): stage 1 {ms:.3f} ms, "
+              f"halo planes 2 x {plane / 1e6:.1f} MB, device copy {copy_ms:.3f} ms")
+    del s, y, w1, lo, hi, src_lo, src_hi
+    torch.cuda.empty_cache()
+    return dict(tier=prec, parts=parts, cells=[n, n, dz], stage1_ms=ms, halo_plane_bytes=plane,
+                halo_copy_ms=copy_ms)
+
+
 def exact_riemann_cost(args, dg, torch, prec, qp_dev, n, k):
     """Stage launches of the primary tier with the exact Riemann solver as the face flux."""
     s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing, riemann="exact")
@@ -311,6 +353,7 @@ def main():
     iso = None if args.no_limiter else reset_cost(args, dg, torch, prim0, qp, n, k)
     diag = diagnostics_cost(args, dg, torch, prim0, qp, n, k) if args.diagnostics else None
     ers = None if args.no_limiter else exact_riemann_cost(args, dg, torch, prim0, qp, n, k)
+    shr = None if args.no_limiter else share_cost(args, dg, torch, prim0, qp, n, k)
     del qp
     torch.cuda.empty_cache()
     if args.copy_calibration > 0:
@@ -374,6 +417,8 @@ def main():
         line["diagnostics"] = diag
     if ers is not None:
         line["exact_riemann"] = dict(ers, stage1_ms_hllc=results[ers["tier"]]["stage_ms_each"][0])
+    if shr is not None:
+        line["z_slab_share"] = dict(shr, whole_stage1_ms=results[shr["tier"]]["stage_ms_each"][0])
     print(json.dumps(line), flush=True)
 
 

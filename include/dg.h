@@ -63,7 +63,8 @@ enum {
     DG_CHECK_RANGE = 4u,  /* dg_step checks cell means for rho>0, p>0, finite after each step */
     DG_LIMIT = 8u,        /* positivity limiter of Sec. 2.5 on every stage input (see dg_limiter_stats) */
     DG_ISOTHERMAL = 16u,  /* dg_step: isothermal reset of Sec. 3.2 after every step (needs dg_set_isothermal) */
-    DG_EXACT_RIEMANN = 32u /* face flux from the exact Riemann solver instead of HLLC (see below) */
+    DG_EXACT_RIEMANN = 32u, /* face flux from the exact Riemann solver instead of HLLC (see below) */
+    DG_ZHALO = 64u        /* the mesh is one z slab of a larger periodic one: halo planes (dg_set_halo) */
 };
 
 typedef struct {
@@ -73,7 +74,7 @@ typedef struct {
     double gamma;       /* adiabatic index, > 1 */
     double cfl;         /* Courant factor C of Sec. 2.4, in (0, 1] */
     int32_t precision;  /* a dg_precision value */
-    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN */
+    uint32_t flags;     /* DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN | DG_ZHALO */
 } dg_config;
 
 /* Validate cfg, build the quadrature/basis tables on the host (Sec. 2.1-2.2),
@@ -348,6 +349,33 @@ dg_status dg_rms_mach(dg_ctx *ctx, const void *y, int32_t S, double *out);
  * rest of the scheme is unchanged.  Computed in the tier's pointwise precision
  * (FP32 for the FP32-storage tiers).  Costs more than HLLC (iterations,
  * divergent lanes). */
+
+/* ---------------------------------------------------------------------------
+ * One GPU's share of a mesh split into z slabs (the way the method shards:
+ * every stage needs one ghost layer of the neighbouring slabs, Sec. 2.3).
+ * With DG_ZHALO the stage kernels take the cells below z = 0 and above
+ * z = n[2] - 1 from two halo planes instead of wrapping periodically; x and y
+ * stay periodic.  A halo plane is one z plane of a state, [y][i][l][x]
+ * (dg_plane_count elements of the storage type): the neighbouring slab's top
+ * plane below, its bottom plane above.  Since the state is stored
+ * [z][y][i][l][x], a slab's boundary plane is contiguous and is sent as is
+ * (no packing).  The caller refreshes the halo planes before every stage
+ * (dg_rhs, dg_stage; dg_step cannot exchange between its stages, so drive the
+ * stages with dg_stage) and reduces the CFL rate across slabs (dg_dt per
+ * slab, then the minimum).  DG_ZHALO with DG_CLOSURE: DG_ERR_UNSUPPORTED.
+ *
+ * Elements of one z plane: 5 N(k) n[0] n[1]. */
+size_t dg_plane_count(const dg_ctx *ctx);
+
+/* The halo planes (DEVICE, caller-owned, read by every later stage launch).
+ * DG_ERR_STATE without DG_ZHALO; a stage without halo planes set returns
+ * DG_ERR_STATE. */
+dg_status dg_set_halo(dg_ctx *ctx, const void *lo, const void *hi);
+
+/* The slab's place in the whole mesh for the driving field: its first plane
+ * is global plane z0 of nz_global (default 0 of n[2]).  Call before
+ * dg_set_forcing.  DG_ERR_ARG unless 0 <= z0 and z0 + n[2] <= nz_global. */
+dg_status dg_set_slab(dg_ctx *ctx, int32_t z0, int32_t nz_global);
 
 #ifdef __cplusplus
 }

@@ -324,10 +324,12 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
     if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
     if (cfg->flags &
-        ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN))
+        ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN |
+                    DG_ZHALO))
         return DG_ERR_ARG;
     if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
+    if ((cfg->flags & DG_CLOSURE) && (cfg->flags & DG_ZHALO)) return DG_ERR_UNSUPPORTED;
     {
         // the stage kernel addresses one (z, y) slab of 5 N(k) rows of n[0] cells with 32-bit offsets
         const double slab_bytes = 5.0 * nmodes_of(cfg->k) * cfg->n[0] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
@@ -503,6 +505,10 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
         c->err = "DG_CLOSURE set but dg_set_closure was not called";
         return DG_ERR_STATE;
     }
+    if ((c->cfg.flags & DG_ZHALO) && !c->halo_lo) {
+        c->err = "DG_ZHALO set but dg_set_halo was not called";
+        return DG_ERR_STATE;
+    }
     StageArgs s{};
     if ((c->cfg.flags & DG_LIMIT) && limit_input)  // Sec. 2.5: the stage input is limited in place
         HIPCHK(c, launch_limit(c->cfg.k, c->cfg.precision, const_cast<void *>(yin), c->limtab, c->limnp, c->ncells,
@@ -556,6 +562,8 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;
     s.riemann = (c->cfg.flags & DG_EXACT_RIEMANN) ? 1 : 0;
+    s.halo_lo = c->halo_lo;
+    s.halo_hi = c->halo_hi;
     s.acache = c->acache;
     for (int i = 0; i < 3; i++) s.h[i] = c->h[i];
     HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
@@ -758,7 +766,8 @@ dg_status dg_set_forcing(dg_ctx *c, int32_t nmodes, const int32_t *nvec, const d
     double wg[5];
     gauss_rule(c->n, xg.x, wg);
     HIPCHK(c, launch_accel_cache(c->cfg.k, c->cfg.precision, c->fmodes, nmodes, c->cfg.n[0], c->cfg.n[1], c->cfg.n[2],
-                                 c->ncells, xg, c->acache, c->stream));
+                                 c->ncells, xg, c->slab_z0, c->slab_nz > 0 ? c->slab_nz : c->cfg.n[2], c->acache,
+                                 c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->nfmodes = nmodes;
     c->have_forcing = true;
@@ -1252,5 +1261,37 @@ dg_status dg_rms_mach(dg_ctx *c, const void *y, int32_t S, double *out) {
     HIPCHK(c, hipMemcpyAsync(&v, tot, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *out = std::sqrt(v / ((double)c->ncells * S * S * S));
+    return DG_OK;
+}
+
+// ------------------------------------------------------------------ z slabs (one GPU's share of a split mesh)
+
+size_t dg_plane_count(const dg_ctx *c) {
+    return c ? (size_t)NF * c->N * c->cfg.n[0] * c->cfg.n[1] : 0;
+}
+
+dg_status dg_set_halo(dg_ctx *c, const void *lo, const void *hi) {
+    if (!c) return DG_ERR_ARG;
+    if (!(c->cfg.flags & DG_ZHALO)) {
+        c->err = "dg_set_halo: the context was made without DG_ZHALO";
+        return DG_ERR_STATE;
+    }
+    if (!lo || !hi) {
+        c->err = "dg_set_halo: NULL pointer";
+        return DG_ERR_ARG;
+    }
+    c->halo_lo = lo;
+    c->halo_hi = hi;
+    return DG_OK;
+}
+
+dg_status dg_set_slab(dg_ctx *c, int32_t z0, int32_t nz_global) {
+    if (!c) return DG_ERR_ARG;
+    if (z0 < 0 || nz_global < c->cfg.n[2] || z0 + c->cfg.n[2] > nz_global) {
+        c->err = "dg_set_slab: need 0 <= z0 and z0 + n[2] <= nz_global";
+        return DG_ERR_ARG;
+    }
+    c->slab_z0 = z0;
+    c->slab_nz = nz_global;
     return DG_OK;
 }

@@ -134,7 +134,7 @@ hipError_t launch_sum_into(const double *p, long long n, double *acc, hipStream_
 hipError_t launch_reset(int k, int prec, void *y, const Leg1D &L, long long nc, int nx, double gm1, double ce,
                         double rho0, double vol, double *partials, double *acc, hipStream_t s);
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
-                              const GaussNodes &xg, void *out, hipStream_t s);
+                              const GaussNodes &xg, int z0, int nzg, void *out, hipStream_t s);
 
 struct StageArgs {
     const void *yin;
@@ -162,6 +162,8 @@ struct StageArgs {
     const void *corr;     // closure correction c (state layout) or nullptr: R <- R - (c - cmean on mode 0)
     const double *cmean;  // [5] mean of c's mode-0 rows per field
     int riemann;          // face flux: 0 HLLC, 1 exact Riemann solver
+    const void *halo_lo;  // z slab: the plane below z = 0 and the plane above z = nz - 1 ([y][i][l][x]),
+    const void *halo_hi;  // or nullptr (periodic in z)
 };
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
@@ -253,6 +255,9 @@ struct dg_ctx {
     int ex_off = 0;                // LDS offsets of the y-face trace and flux regions (after the tables)
     int ex_off2 = 0;
     int ex_off3 = -1;              // LDS offset of the end-row buffers (-1: not used)
+    // z slab of a larger periodic mesh (DG_ZHALO): halo planes and the slab's place for the driving
+    const void *halo_lo = nullptr, *halo_hi = nullptr;
+    int slab_z0 = 0, slab_nz = 0;
     int cur_slot = 1;              // slot holding the latest CFL rate
     int lds = 0;
     long long step_count = 0;

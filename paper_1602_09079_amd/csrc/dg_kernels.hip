@@ -593,8 +593,8 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             }
     };
     // the block of slab r (wave-uniform) whose first column is at x = xc
-    auto load = [&](long long r, B &b) {
-        const auto rs = slab_rsrc(yin, slabn, r);
+    auto load_from = [&](const S *base, long long r, B &b) {
+        const auto rs = slab_rsrc(base, slabn, r);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
             const unsigned so = (unsigned)i * fbytes;
@@ -612,6 +612,18 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                 }
             }
         }
+    };
+    auto load = [&](long long r, B &b) { load_from(yin, r, b); };
+    // the block in z plane zz of y row yy: across the ends of a z slab from the halo planes (one
+    // plane of the neighbouring slab each, [y][i][l][x]) when they are given, else periodic
+    auto loadz = [&](int yy, int zz, B &b) {
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        if (a.halo_lo && zz < 0)
+            load_from(static_cast<const S *>(a.halo_lo), yy, b);
+        else if (a.halo_hi && zz >= nz)
+            load_from(static_cast<const S *>(a.halo_hi), yy, b);
+        else
+            load_from(yin, (long long)(zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * ny + yy, b);
     };
     // end rows of the y group (waves 0 and nact-1): copied into LDS by buffer loads one step ahead
     constexpr int ERV = NF * (1 + SPL);  // values per lane of a block: the mean and the slots, per field
@@ -925,7 +937,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
         C Fz[NF][4];  // flux on the -z face of the current block
         {
             B prv;
-            load(cidx(iy, z0 - 1), prv);
+            loadz(iy, z0 - 1, prv);
             C tp[NF][4], tm[NF][4];
             trace(prv, 5, tp);
             trace(cur, 4, tm);
@@ -943,7 +955,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             if constexpr (FORCE) accel_tile(ar, 0, av);
             lift(4, cur, Fz, acc);  // -z face: flux carried from the previous step
             B nxt;
-            load(cidx(iy, z + 1), nxt);
+            loadz(iy, z + 1, nxt);
             volume(cur, acc, ar, av);
             {  // x faces: the left neighbour's + trace sits in the adjacent lane
                 C tl[NF][4], Fh[NF][4];
@@ -1193,10 +1205,19 @@ __global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
     auto load = [&](int x, int yy, int zz, C q[5]) {
         x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
         yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        const S *src = yin;
+        if (a.halo_lo && zz < 0) {  // across the ends of a z slab: the halo planes
+            src = static_cast<const S *>(a.halo_lo);
+            zz = 0;
+        } else if (a.halo_hi && zz >= nz) {
+            src = static_cast<const S *>(a.halo_hi);
+            zz = 0;
+        } else {
+            zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        }
         const long long b = ((long long)zz * ny + yy) * NF * nx + x;
 #pragma unroll
-        for (int i = 0; i < NF; i++) q[i] = (C)yin[b + (long long)i * nx];
+        for (int i = 0; i < NF; i++) q[i] = (C)src[b + (long long)i * nx];
     };
     const C gam = (C)a.gamma;
     auto flux = [&](auto axis_c, const C qL[5], const C qR[5], C F[5]) {
@@ -1392,7 +1413,7 @@ hipError_t launch_project(int k, int prec, const void *qp, void *y, const double
 // turn in FP64 and its sine and cosine taken in FP64.  Rows past the last point are zero.
 template <int K, class S>
 __global__ void accel_cache_kernel(const double *__restrict__ modes, int nmodes, int nx, int ny, int nz, long long nc,
-                                   GaussNodes xg, S *__restrict__ out) {
+                                   GaussNodes xg, int z0, int nzg, S *__restrict__ out) {
     constexpr int n = K + 1, Q = n * n * n, RT1 = (Q + 15) / 16;
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nc * RT1 * 16) return;
@@ -1408,7 +1429,7 @@ __global__ void accel_cache_kernel(const double *__restrict__ modes, int nmodes,
     if (rho < Q) {
         const int qa = rho % n, qb = (rho / n) % n, qc = rho / (n * n);
         const double X = (ix + 0.5 * (1.0 + xg.x[qa])) / nx, Y = (iy + 0.5 * (1.0 + xg.x[qb])) / ny,
-                     Z = (iz + 0.5 * (1.0 + xg.x[qc])) / nz;
+                     Z = (z0 + iz + 0.5 * (1.0 + xg.x[qc])) / nzg;
         for (int m = 0; m < nmodes; m++) {
             const double *md = modes + 9 * m;
             double ph = md[0] * X + md[1] * Y + md[2] * Z;
@@ -1426,25 +1447,25 @@ __global__ void accel_cache_kernel(const double *__restrict__ modes, int nmodes,
 
 template <int K>
 static hipError_t launch_accel_k(int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
-                                 const GaussNodes &xg, void *out, hipStream_t s) {
+                                 const GaussNodes &xg, int z0, int nzg, void *out, hipStream_t s) {
     constexpr int Q = (K + 1) * (K + 1) * (K + 1), RT1 = (Q + 15) / 16;
     const long long nb = (nc * RT1 * 16 + 255) / 256;
     if (prec == DG_FP64)
         hipLaunchKernelGGL((accel_cache_kernel<K, double>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
-                           (double *)out);
+                           z0, nzg, (double *)out);
     else
         hipLaunchKernelGGL((accel_cache_kernel<K, float>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
-                           (float *)out);
+                           z0, nzg, (float *)out);
     return hipGetLastError();
 }
 
 hipError_t launch_accel_cache(int k, int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
-                              const GaussNodes &xg, void *out, hipStream_t s) {
+                              const GaussNodes &xg, int z0, int nzg, void *out, hipStream_t s) {
     switch (k) {
-        case 0: return launch_accel_k<0>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
-        case 1: return launch_accel_k<1>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
-        case 2: return launch_accel_k<2>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
-        case 3: return launch_accel_k<3>(prec, modes, nmodes, nx, ny, nz, nc, xg, out, s);
+        case 0: return launch_accel_k<0>(prec, modes, nmodes, nx, ny, nz, nc, xg, z0, nzg, out, s);
+        case 1: return launch_accel_k<1>(prec, modes, nmodes, nx, ny, nz, nc, xg, z0, nzg, out, s);
+        case 2: return launch_accel_k<2>(prec, modes, nmodes, nx, ny, nz, nc, xg, z0, nzg, out, s);
+        case 3: return launch_accel_k<3>(prec, modes, nmodes, nx, ny, nz, nc, xg, z0, nzg, out, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,6 +19,7 @@ DG_CHECK_RANGE = 4
 DG_LIMIT = 8
 DG_ISOTHERMAL = 16
 DG_EXACT_RIEMANN = 32
+DG_ZHALO = 64
 STATUS_NAMES = {0: "DG_OK", 1: "DG_ERR_ARG", 2: "DG_ERR_UNSUPPORTED", 3: "DG_ERR_HIP", 4: "DG_ERR_RANGE",
                 5: "DG_ERR_STATE"}
 
@@ -29,7 +30,8 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
            "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats",
            "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated", "dg_sample",
-           "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach"]
+           "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach",
+           "dg_plane_count", "dg_set_halo", "dg_set_slab"]
 
 
 class DGError(RuntimeError):
@@ -99,6 +101,9 @@ def lib():
             "dg_density_pdf": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_int32, _vp]),
             "dg_rms_mach": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+            "dg_plane_count": (ctypes.c_size_t, [_vp]),
+            "dg_set_halo": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_set_slab": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -164,8 +169,10 @@ class Solver:
 
     def __init__(self, k, n, box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.3, precision="fp32", flags=0,
                  forcing=False, check_range=False, closure=False, limit=False, isothermal=False, riemann="hllc",
-                 stream=None):
+                 zhalo=False, stream=None):
         import torch
+        if zhalo:
+            flags |= DG_ZHALO
         if riemann not in ("hllc", "exact"):
             raise ValueError("riemann must be 'hllc' or 'exact'")
         if riemann == "exact":
@@ -315,6 +322,16 @@ class Solver:
         v = ctypes.c_double()
         self._check(lib().dg_dissipated(self._ctx, ctypes.byref(v)), "dg_dissipated")
         return v.value
+
+    # ------------------------------------------------------------ z slabs
+    def set_halo(self, lo, hi):
+        """Halo planes [y][i][l][x] (device tensors of the storage type, kept alive by the caller)."""
+        shape = (self.n[1], 5, self.N, self.n[0])
+        self._halo = (lo, hi)
+        self._check(lib().dg_set_halo(self._ctx, self._ptr(lo, shape), self._ptr(hi, shape)), "dg_set_halo")
+
+    def set_slab(self, z0, nz_global):
+        self._check(lib().dg_set_slab(self._ctx, z0, nz_global), "dg_set_slab")
 
     # ------------------------------------------------------------ diagnostics (Sec. 3.3, 4.1, 4.4)
     def sample(self, y, S=4):

@@ -74,7 +74,7 @@ def test_ou_update_matches_oracle():
     (dict(k=1, n=8, cfl=0.0), dg.DG_ERR_ARG),
     (dict(k=1, n=8, cfl=1.5), dg.DG_ERR_ARG),
     (dict(k=1, n=8, precision=7), dg.DG_ERR_ARG),
-    (dict(k=1, n=8, flags=64), dg.DG_ERR_ARG),
+    (dict(k=1, n=8, flags=128), dg.DG_ERR_ARG),
     (dict(k=2, n=8, flags=dg.DG_CLOSURE), dg.DG_ERR_UNSUPPORTED),
 ])
 def test_config_validation(kw, status):
