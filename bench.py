@@ -150,7 +150,8 @@ def share_cost(args, dg, torch, prec, qp_dev, n, k, parts=8):
     instead of the periodic wrap): stage launch time, and the two halo planes a stage needs (their
     bytes, and a device-to-device copy of them standing in for the transfer)."""
     dz = n // parts
-    s = dg.Solver(k, (n, n, dz), precision=prec, cfl=0.3, forcing=not args.no_forcing, zhalo=True)
+    s = dg.Solver(k, (n, n, dz), box=(1.0, 1.0, dz / n), precision=prec, cfl=0.3, forcing=not args.no_forcing,
+                  zhalo=True)
     s.set_slab(0, n)
     if not args.no_forcing:
         nvec, ahat, _ = driving_table(dg)

@@ -362,7 +362,8 @@ dg_status dg_rms_mach(dg_ctx *ctx, const void *y, int32_t S, double *out);
  * (no packing).  The caller refreshes the halo planes before every stage
  * (dg_rhs, dg_stage; dg_step cannot exchange between its stages, so drive the
  * stages with dg_stage) and reduces the CFL rate across slabs (dg_dt per
- * slab, then the minimum).  DG_ZHALO with DG_CLOSURE: DG_ERR_UNSUPPORTED.
+ * slab, then the minimum).  The slab's box[2] is its own extent (the whole
+ * box's times n[2] / nz_global).  DG_ZHALO with DG_CLOSURE: DG_ERR_UNSUPPORTED.
  *
  * Elements of one z plane: 5 N(k) n[0] n[1]. */
 size_t dg_plane_count(const dg_ctx *ctx);

@@ -46,7 +46,7 @@ def test_slabs_reproduce_whole_mesh(dgm, prec, k, nslab):
     dz = nz // nslab
     slabs = []
     for j in range(nslab):
-        s = dgm.Solver(k, (nx, ny, dz), gamma=G, precision=prec, forcing=True, zhalo=True)
+        s = dgm.Solver(k, (nx, ny, dz), box=(1.0, 1.0, dz / nz), gamma=G, precision=prec, forcing=True, zhalo=True)
         s.set_slab(j * dz, nz)
         s.set_forcing(nvec, ah)
         slabs.append(s)
