@@ -444,14 +444,27 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipGetDevice(&dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-    // z chunk length: long sweeps, but at least ~3 work items per resident item slot
+    // z chunk length: the resident item slots take the items in rounds, and an item costs its
+    // planes plus about one plane of start-up (the -z face of its first plane, the look-ahead
+    // that is not yet overlapped); pick the length (at most 32) that minimises
+    // rounds x (length + 1), the longer one on ties
     const long long nbx = (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
     const int rows = stage_rows_per_item(cfg->precision);
     const int items_per_wg = rows == 1 ? stage_block_threads(cfg->precision) / 64 : 1;  // one item per wave or per workgroup
     const long long nyg = (cfg->n[1] + rows - 1) / rows;
-    const long long resident = (long long)per_cu * ncu * items_per_wg;
-    long long zl = (nbx * nyg * cfg->n[2]) / std::max(1LL, 3 * resident);
-    zl = std::max(1LL, std::min(32LL, std::min(zl, (long long)cfg->n[2])));
+    const long long resident = std::max(1LL, (long long)per_cu * ncu * items_per_wg);
+    long long zl = 1, best = -1;
+    for (long long l = 1; l <= std::min(32LL, (long long)cfg->n[2]); l++) {
+        const long long nch = (cfg->n[2] + l - 1) / l;
+        const long long len = (cfg->n[2] + nch - 1) / nch;  // equal chunks
+        if (len != l) continue;
+        const long long rounds = (nbx * nyg * nch + resident - 1) / resident;
+        const long long cost = rounds * (len + 1);
+        if (best < 0 || cost <= best) {
+            best = cost;
+            zl = len;
+        }
+    }
     c->zlen = (int)zl;
     const long long nitems = nbx * nyg * ((cfg->n[2] + zl - 1) / zl);
     long long grid = (long long)per_cu * ncu;
