@@ -357,6 +357,21 @@ def main():
     shr = None if args.no_limiter else share_cost(args, dg, torch, prim0, qp, n, k)
     del qp
     torch.cuda.empty_cache()
+    # the box's own copy bandwidth (2 GiB device-to-device, read + write bytes), the second roof
+    nel = (2 << 30) // 4
+    src = torch.ones(nel, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record()
+    for _ in range(5):
+        dst.copy_(src)
+    eb.record()
+    torch.cuda.synchronize()
+    copy_GBs = 2 * nel * 4 * 5 / (ea.elapsed_time(eb) / 1e3) / 1e9
+    log(args, f"[bench] device copy bandwidth {copy_GBs:.0f} GB/s")
+    del src, dst
+    torch.cuda.empty_cache()
     if args.copy_calibration > 0:
         nel = int(args.copy_calibration * (1 << 30)) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -373,7 +388,8 @@ def main():
     r = results[primary]
     N = dg.nmodes(k)
     roof = dict(bound="hbm", achieved=round(r["achieved_GBs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4), traffic=None)
+                frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4), traffic=None,
+                copy_GBs=round(copy_GBs, 1), frac_of_copy=round(r["achieved_GBs"] / copy_GBs, 4))
     tf = os.path.join(ROOT, "profiles", f"traffic_stage_k{k}_n{n}_{primary}.json")
     if os.path.exists(tf):
         t = json.load(open(tf))
