@@ -79,9 +79,10 @@ class Experiment:
         self.fine = dg.Solver(2, cfg.nf, **fl)
         self.coarse = dg.Solver(1, cfg.nc, **fl)
         self.coarse_cl = dg.Solver(1, cfg.nc, closure=True, **fl)
+        self.plain2 = dg.Solver(1, cfg.nf, **fl)  # the plain scheme with 8x the cells (DOF ladder)
         if cfg.forcing:
             nvec, ahat = driving()
-            for s in (self.fine, self.coarse, self.coarse_cl):
+            for s in (self.fine, self.coarse, self.coarse_cl, self.plain2):
                 s.set_forcing(nvec, ahat)
         x = dg.gauss_nodes(3)
         qp = synth.turbulence(cfg.nf, x, seed=cfg.ic_seed, mach=cfg.mach, device="cuda", dtype=self.fine.dtype)
@@ -179,6 +180,9 @@ class Experiment:
         self.t = _advance(self.fine, self.yf, cfg.t_gap, self.t)
         t0 = self.t
         yc0 = c.restrict(2, self.yf)
+        # plain k = 1 on the fine mesh from the fine state's degree-1 modes (the L2 projection: the
+        # basis is orthonormal and graded by degree), for the ladder
+        y2 = self.yf[:, :, :, :dg.nmodes(1), :].contiguous()
         prf = c.restrict(2, self.fine.rhs(self.yf))
         self.t = _advance(self.fine, self.yf, cfg.horizon, self.t)
         ref = c.restrict(2, self.yf)
@@ -189,6 +193,10 @@ class Experiment:
         y = yc0.clone()
         c.step(y, n, cfg.horizon / n)
         out["plain"] = dict(rhs_err=_rel_l2(c.rhs(yc0), prf).tolist(), err=_rel_l2(y - yc0, d_ref).tolist())
+        h2 = self.plain2.dt(y2)
+        n2 = max(1, int(math.ceil(cfg.horizon / h2)))
+        self.plain2.step(y2, n2, cfg.horizon / n2)
+        out["plain_8x_dof"] = dict(cells=cfg.nf ** 3, err=_rel_l2(c.restrict(1, y2) - yc0, d_ref).tolist())
         for a in alphas:
             self.install(a)
             cl.closure_fallbacks()
@@ -210,11 +218,31 @@ class Experiment:
         test = self.window([best])
         res = dict(validation=val, alpha=best, test=test)
         p, cl = test["plain"], test[f"alpha={best}"]
+        res["effective_dof_gain"] = effective_dof_gain(p["err"], test["plain_8x_dof"]["err"], cl["err"])
         self.log(f"[closure] alpha={best}; test window t0={test['t0']:.3f}, {test['coarse_steps']} steps")
         self.log(f"[closure] operator error plain {np.round(p['rhs_err'], 3)} closure {np.round(cl['rhs_err'], 3)}")
         self.log(f"[closure] evolution error plain {np.round(p['err'], 3)} closure {np.round(cl['err'], 3)}; "
                  f"fallback rate {cl['fallback_rate']:.2e}")
+        self.log(f"[closure] plain with 8x the cells {np.round(test['plain_8x_dof']['err'], 3)}; effective DOF gain "
+                 f"of the closure per field {np.round(res['effective_dof_gain'], 2)}")
         return res
+
+
+def effective_dof_gain(e1, e8, ec):
+    """Per field: the DOF factor at which the plain scheme would reach the closure's error, read off
+    the plain runs at 1x and 8x the cells (error taken as a power of the DOF between them).  Values
+    outside [1, 8] are clipped to the ladder's ends."""
+    out = []
+    for a, b, c in zip(e1, e8, ec):
+        if not (b < a):
+            out.append(float("nan"))
+        elif c >= a:
+            out.append(1.0)
+        elif c <= b:
+            out.append(8.0)
+        else:
+            out.append(float(8.0 ** (math.log(a / c) / math.log(a / b))))
+    return out
 
 
 def _rel_l2(a, b):
