@@ -360,9 +360,9 @@ dg_status dg_rms_mach(dg_ctx *ctx, const void *y, int32_t S, double *out);
  * plane below, its bottom plane above.  Since the state is stored
  * [z][y][i][l][x], a slab's boundary plane is contiguous and is sent as is
  * (no packing).  The caller refreshes the halo planes before every stage
- * (dg_rhs, dg_stage; dg_step cannot exchange between its stages, so drive the
- * stages with dg_stage) and reduces the CFL rate across slabs (dg_dt per
- * slab, then the minimum).  The slab's box[2] is its own extent (the whole
+ * (dg_rhs, dg_stage; dg_step cannot exchange between its stages and returns
+ * DG_ERR_UNSUPPORTED for a slab: drive the stages with dg_stage) and reduces
+ * the CFL rate across slabs (dg_dt per slab, then the minimum).  The slab's box[2] is its own extent (the whole
  * box's times n[2] / nz_global).  DG_ZHALO with DG_CLOSURE: DG_ERR_UNSUPPORTED.
  *
  * Elements of one z plane: 5 N(k) n[0] n[1]. */

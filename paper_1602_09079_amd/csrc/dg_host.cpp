@@ -689,6 +689,10 @@ dg_status dg_step(dg_ctx *c, void *y, void *work, double dt, int32_t nsteps, dou
         c->err = "dg_step: DG_ISOTHERMAL needs dg_set_isothermal first";
         return DG_ERR_STATE;
     }
+    if (c->cfg.flags & DG_ZHALO) {  // the halo planes must be refreshed between the stages
+        c->err = "dg_step: a z slab (DG_ZHALO) is stepped stage by stage with dg_stage";
+        return DG_ERR_UNSUPPORTED;
+    }
     const size_t sb = dg_state_count(c) * elem_bytes(c);
     void *w1 = work;
     void *w2 = static_cast<char *>(work) + sb;

@@ -89,6 +89,10 @@ def test_slab_errors(dgm):
     with pytest.raises(dgm.DGError) as e:
         s.set_slab(6, 8)  # 6 + 4 > 8
     assert e.value.status == dgm.DG_ERR_ARG
+    s.set_halo(y[0].clone(), y[0].clone())
+    with pytest.raises(dgm.DGError) as e:
+        s.step(y, 1, 1e-3)  # halos cannot be exchanged between dg_step's stages
+    assert e.value.status == dgm.DG_ERR_UNSUPPORTED
     plain = dgm.Solver(1, (8, 8, 4), gamma=G, precision="fp64")
     with pytest.raises(dgm.DGError) as e:
         plain.set_halo(y[0], y[0])
