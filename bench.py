@@ -331,8 +331,8 @@ def cpu_baseline(args, k):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1; the domain-decomposed multi-GPU "
-                                   "path is not built"}))
+        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1; one GPU's share of a z-slab split "
+                                   "is timed as z_slab_share, the transfers between GPUs are not built"}))
         sys.exit(2)
     import torch
 
