@@ -957,29 +957,6 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
             B nxt;
             loadz(iy, z + 1, nxt);
             volume(cur, acc, ar, av);
-            {  // x faces: the left neighbour's + trace sits in the adjacent lane
-                C tl[NF][4], Fh[NF][4];
-                {
-                    C tp[NF][4];
-                    trace(cur, 1, tp);
-#pragma unroll
-                    for (int i = 0; i < NF; i++)
-#pragma unroll
-                        for (int r = 0; r < 4; r++) tl[i][r] = dpp_shr1(tp[i][r]);
-                }
-                {
-                    C tm[NF][4];
-                    trace(cur, 0, tm);
-                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fh);
-                }
-                lift(0, cur, Fh, acc);
-                // the + face flux of a column is the - face flux of its right neighbour
-#pragma unroll
-                for (int i = 0; i < NF; i++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) Fh[i][r] = dpp_shl1(Fh[i][r]);
-                lift(1, cur, Fh, acc);
-            }
             if constexpr (YSH) {
                 // y faces shared by the rows of the workgroup: each face flux is solved once, by the
                 // row below it; the faces at the group's ends use the neighbour rows' weights
@@ -1080,6 +1057,31 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                     riemann(std::integral_constant<int, 1>{}, tp, tn, Fh);
                 }
                 lift(3, cur, Fh, acc);
+            }
+            // x faces after the y faces: with the +z face they cover the round trip of the y0 copy
+            // issued after the second barrier, and the waves reach the first barrier sooner
+            {  // x faces: the left neighbour's + trace sits in the adjacent lane
+                C tl[NF][4], Fh[NF][4];
+                {
+                    C tp[NF][4];
+                    trace(cur, 1, tp);
+#pragma unroll
+                    for (int i = 0; i < NF; i++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) tl[i][r] = dpp_shr1(tp[i][r]);
+                }
+                {
+                    C tm[NF][4];
+                    trace(cur, 0, tm);
+                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fh);
+                }
+                lift(0, cur, Fh, acc);
+                // the + face flux of a column is the - face flux of its right neighbour
+#pragma unroll
+                for (int i = 0; i < NF; i++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) Fh[i][r] = dpp_shl1(Fh[i][r]);
+                lift(1, cur, Fh, acc);
             }
             {  // +z face with block z+1; its flux is the -z flux of the next step
                 C tp[NF][4], tm[NF][4];
