@@ -103,3 +103,21 @@ def test_reset_and_sampling_k0(dgm, prec):
     want, dw = O.isothermal_reset(cfg, ys, 1.0, 1.0)
     err = np.abs(host(yd) - want).max() / np.abs(want).max()
     assert err <= (1e-14 if prec == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_limited_isothermal_steps_k0(dgm, prec):
+    """k = 0 with the limiter (no higher modes to scale, but the limited time step C/2) and the
+    isothermal reset after every step, device CFL steps, against the oracle."""
+    n = (12, 5, 4)
+    cfg, y = turb(n, seed=7, gamma=1.01)
+    y, _ = O.isothermal_reset(cfg, y, 1.0, 1.0)
+    s = dgm.Solver(0, n, gamma=1.01, precision=prec, limit=True, isothermal=True)
+    s.set_isothermal(1.0, 1.0)
+    yd = dev(y, s.dtype)
+    t = s.step(yd, 3)
+    want, tw, _ = O.step_isothermal(cfg, stored(y, prec), 0.0, 3, cs=1.0, rho0=1.0, limit=True)
+    assert t == pytest.approx(tw, rel=1e-13 if prec == "fp64" else 1e-6)
+    assert tw == pytest.approx(3 * 0.5 * O.dt(cfg, y), rel=0.05)  # the limited step is half the plain one
+    err = O.rel_l2(host(yd), want)
+    assert np.all(err <= (1e-12 if prec == "fp64" else 1e-6)), err
