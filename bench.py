@@ -323,9 +323,27 @@ def cpu_baseline(args, k):
     per_stage = el / reps
     dof = 5 * O.nmodes(k) * n ** 3
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=dof / per_stage, unit="DOF-updates/s per RK stage", cores=threads, kind="oracle",
-                sample=f"{reps} SSP stage(s) of the FP64 oracle, k={k}, {n}^3 cells (same per-cell work as the "
-                       f"workload), {per_stage:.3f} s per stage, OMP threads={threads}")
+    out = dict(value=dof / per_stage, unit="DOF-updates/s per RK stage", cores=threads, kind="oracle",
+               sample=f"{reps} SSP stage(s) of the FP64 oracle, k={k}, {n}^3 cells (same per-cell work as the "
+                      f"workload), {per_stage:.3f} s per stage, OMP threads={threads}")
+    # the same on one thread (a child process: the thread count is fixed when OpenMP starts), 16^3 cells
+    code = ("import sys, time; sys.path.insert(0, %r); import oracle as O; from paper_1602_09079_amd import synth; "
+            "n, k = 16, %d; cfg = O.make_cfg(k, n); x = O.gauss_legendre(k + 1)[0]; "
+            "y = O.project(cfg, synth.turbulence(n, x, seed=9079, mach=0.3).numpy()); h = O.dt(cfg, y); "
+            "O.stage(cfg, y, y, 0.0, 1.0, h); t = time.perf_counter(); O.stage(cfg, y, y, 0.0, 1.0, h); "
+            "O.stage(cfg, y, y, 0.0, 1.0, h); print((time.perf_counter() - t) / 2)") % (os.path.dirname(
+                os.path.abspath(__file__)), k)
+    try:
+        import subprocess
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+        t1 = float(r.stdout.strip().splitlines()[-1])
+        out["single_thread_value"] = 5 * O.nmodes(k) * 16 ** 3 / t1
+        out["single_thread_sample"] = f"2 SSP stages of the FP64 oracle, k={k}, 16^3 cells, one thread"
+    except Exception as e:  # the one-thread figure is context only
+        out["single_thread_value"] = None
+        out["single_thread_sample"] = f"not measured: {e}"
+    return out
 
 
 def main():
