@@ -53,12 +53,28 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 _fp = ctypes.POINTER(ctypes.c_float)
 
 
+def hip_runtimes():
+    """Distinct libamdhip64 files mapped into this process (Linux; empty elsewhere)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch's HIP runtime first: the library's libamdhip64 dependency then resolves to the
+        # copy already mapped (same soname).  Loaded the other way round, the process holds two
+        # HIP runtimes and torch's streams and buffers are foreign to the library's.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
+        runtimes = hip_runtimes()
+        if len(runtimes) > 1:
+            raise RuntimeError(f"{LIB_PATH} loaded a second HIP runtime beside torch's: {runtimes}")
         sig = {
             "dg_init": (ctypes.c_int, [ctypes.POINTER(Config), _vp, ctypes.POINTER(_vp)]),
             "dg_destroy": (ctypes.c_int, [_vp]),

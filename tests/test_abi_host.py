@@ -37,6 +37,19 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(L, name), name
 
 
+def test_library_shares_torchs_hip_runtime():
+    """Loaded first in a fresh process, before anything imports torch, the library still maps
+    one HIP runtime: torch's, so that torch's streams and buffers are valid for it."""
+    import subprocess
+    import sys
+    code = ("from paper_1602_09079_amd import dg\n"
+            "dg.lib()\n"
+            "print(len(dg.hip_runtimes()))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
+
 def test_nmodes():
     for k in range(5):
         assert dg.nmodes(k) == O.nmodes(k)
