@@ -239,6 +239,52 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     return blob;
 }
 
+// Tables of the quadrature-form stage kernel (k = 4), in the storage precision, in the kernel's
+// order: phi [l][q], grad [q][d][l] = s_d w_q dphi_l/dxi_d, src [q][l] = w_q phi_l / 8,
+// trace [f][l][p], lift [f][p][l] = (+/-) s_d w_p phi_l (+ on the + face of axis d = f / 2).
+std::vector<char> build_quad_tables(int k, int prec, const double s[3]) {
+    const Basis B(k);
+    const int N = B.N, Q = B.Q, P = B.P;
+    std::vector<double> t;
+    double xi[3];
+    for (int l = 0; l < N; l++)
+        for (int q = 0; q < Q; q++) {
+            B.point(q, xi);
+            t.push_back(B.phi(l, xi));
+        }
+    for (int q = 0; q < Q; q++) {
+        B.point(q, xi);
+        for (int d = 0; d < 3; d++)
+            for (int l = 0; l < N; l++) t.push_back(s[d] * B.weight(q) * B.dphi(l, d, xi));
+    }
+    for (int q = 0; q < Q; q++) {
+        B.point(q, xi);
+        for (int l = 0; l < N; l++) t.push_back(B.weight(q) * B.phi(l, xi) / 8.0);
+    }
+    for (int f = 0; f < 6; f++)
+        for (int l = 0; l < N; l++)
+            for (int p = 0; p < P; p++) {
+                B.face_point(f, p, xi);
+                t.push_back(B.phi(l, xi));
+            }
+    for (int f = 0; f < 6; f++)
+        for (int p = 0; p < P; p++) {
+            B.face_point(f, p, xi);
+            const double c = ((f & 1) ? 1.0 : -1.0) * s[f / 2] * B.face_weight(p);
+            for (int l = 0; l < N; l++) t.push_back(c * B.phi(l, xi));
+        }
+    std::vector<char> blob;
+    if (prec == DG_FP64) {
+        blob.resize(t.size() * 8);
+        std::memcpy(blob.data(), t.data(), blob.size());
+    } else {
+        std::vector<float> f(t.begin(), t.end());
+        blob.resize(f.size() * 4);
+        std::memcpy(blob.data(), f.data(), blob.size());
+    }
+    return blob;
+}
+
 const char *kNoCtx = "invalid or NULL dg_ctx";
 
 dg_status hip_fail(dg_ctx *c, hipError_t e, const char *what) {
@@ -327,7 +373,11 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN |
                     DG_ZHALO))
         return DG_ERR_ARG;
-    if (cfg->k > 3) return DG_ERR_UNSUPPORTED;
+    if (cfg->k > 4) return DG_ERR_UNSUPPORTED;
+    // k = 4 runs the quadrature-form kernel: FP64 and FP32 storage, no limiter (its point set
+    // would need four Gauss-Lobatto nodes per axis)
+    if (cfg->k == 4 && ((cfg->precision != DG_FP64 && cfg->precision != DG_FP32) || (cfg->flags & DG_LIMIT)))
+        return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && (cfg->flags & DG_ZHALO)) return DG_ERR_UNSUPPORTED;
     {
@@ -357,8 +407,13 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         return st;
     };
     if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
-        c->lay = make_layout(cfg->k, cfg->precision);
-        const std::vector<char> blob = build_tables(c->lay, s);
+        std::vector<char> blob;
+        if (cfg->k == 4) {
+            blob = build_quad_tables(cfg->k, cfg->precision, s);
+        } else {
+            c->lay = make_layout(cfg->k, cfg->precision);
+            blob = build_tables(c->lay, s);
+        }
         if (hipMalloc(&c->tables, blob.size()) != hipSuccess) return fail(DG_ERR_HIP);
         if (hipMemcpy(c->tables, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
             return fail(DG_ERR_HIP);
@@ -413,7 +468,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipMemset(c->slots, 0, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->flag, sizeof(int)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
-    if (cfg->k == 0) {
+    if (cfg->k == 0 || cfg->k == 4) {  // launch shapes set by their launchers
         c->grid = (int)std::min<long long>((ncells + 255) / 256, 1LL << 30);
         *out = c;
         return DG_OK;

@@ -104,8 +104,8 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
 // isothermal reset of Sec. 3.2: energy weights re-projected in place; the dissipated energy
 // (FP64, fixed order) is added to *acc.  partials: reset_partials(nc) doubles.
 struct Leg1D {
-    double p[4][4];  // p[u][a]: scaled Legendre polynomial of degree u at Gauss node a (k+1 nodes)
-    double w[4];     // Gauss weights
+    double p[5][5];  // p[u][a]: scaled Legendre polynomial of degree u at Gauss node a (k+1 nodes)
+    double w[5];     // Gauss weights
 };
 long long reset_partials(long long nc);
 

@@ -193,6 +193,7 @@ hipError_t launch_sample(int k, int S, int prec, const SampleArgs &a, const Leg1
         case 1: return launch_sample_k<1>(S, prec, a, L, s);
         case 2: return launch_sample_k<2>(S, prec, a, L, s);
         case 3: return launch_sample_k<3>(S, prec, a, L, s);
+        case 4: return launch_sample_k<4>(S, prec, a, L, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -32,7 +32,7 @@ def driving(dgm):
 
 
 @pytest.mark.parametrize("prec,k", [("fp64", 2), ("fp32", 3), ("bf16x3", 3), ("bf16", 1), ("fp32", 0),
-                                    ("fp64", 3)])
+                                    ("fp64", 3), ("fp64", 4), ("fp32", 4)])
 @pytest.mark.parametrize("nslab", [2, 3])
 def test_slabs_reproduce_whole_mesh(dgm, prec, k, nslab):
     from paper_1602_09079_amd import synth

@@ -87,7 +87,7 @@ def test_scaled_legendre_closed_forms():
                                                   abs=1e-13)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_basis_orthonormal_under_gauss_rule(k):
     """(1/8) sum_q phi_l phi_m w_q = delta_lm with (k+1)^3 points (degree 2k <= 2k+1)."""
     n = k + 1

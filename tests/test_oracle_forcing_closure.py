@@ -79,7 +79,7 @@ def test_accel_is_real_and_divergence_free():
     np.testing.assert_allclose(O.accel(one, box, x), want, atol=1e-15)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_constant_acceleration_source(k):
     """A constant acceleration (the n = 0 mode) on a uniform gas: R_m = -rho a,
     R_E = -m.a in the mean rows only (Sec. 3.1, source projected with the volume rule)."""

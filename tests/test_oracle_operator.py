@@ -20,7 +20,7 @@ def nodes(k):
 
 # ------------------------------------------------------------------ projection
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_projection_exact_for_degree_k_polynomials(k):
     """Sec. 2.2: the (k+1)-point projection is exact for polynomial data of degree <= k."""
     rng = np.random.default_rng(10 + k)
@@ -150,7 +150,7 @@ def turb_state(k, nc, seed=9079, mach=0.3):
     return cfg, O.project(cfg, qp)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_free_stream_preservation(k):
     nc = (4, 3, 5)
     cfg = O.make_cfg(k, nc, box=(1.0, 0.75, 1.25))
@@ -173,7 +173,7 @@ def test_conservation(k):
     np.testing.assert_allclose(O.totals(cfg, y1), t0, rtol=1e-14, atol=1e-15)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_linear_advection_special_case(k):
     """Uniform p and v: the Euler system reduces to linear advection of rho; the
     scheme keeps m = rho v and E = p/(g-1) + rho |v|^2/2 exactly, mode by mode."""
@@ -245,7 +245,7 @@ def test_rk3_amplification_factor():
     np.testing.assert_allclose(c1 / c0, 1 + z + z * z / 2 + z ** 3 / 6, rtol=1e-12)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_dt_closed_form_uniform(k):
     nc = (4, 5, 6)
     box = (1.0, 2.0, 0.5)
