@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6   # MI355X vector FP64
+FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32
 
 
 def parse():
@@ -43,6 +45,7 @@ def parse():
     p.add_argument("--no-forcing", action="store_true", help="operator only (no driving source)")
     p.add_argument("--diagnostics", action="store_true", help="also time the spectrum, PDF and Mach diagnostics")
     p.add_argument("--no-limiter", action="store_true", help="skip the limiter and isothermal-reset timings")
+    p.add_argument("--k4-n", type=int, default=64, help="mesh of the k = 4 timing (0: skip it)")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
     return p.parse_args()
@@ -214,6 +217,55 @@ def exact_riemann_cost(args, dg, torch, prec, qp_dev, n, k):
     return dict(tier=prec, stage1_ms=ms)
 
 
+# Algorithmic floating-point operations per cell of one k = 4 stage of the quadrature-form kernel
+# (N = 35, Q = 125 volume points, 150 face points; an FMA counts 2): point states 2*5*N*Q,
+# point fluxes 40*Q, volume contraction 2*3*5*N*Q, driving source 2*4*N*Q + 8*Q, face traces
+# 2*2*5*N*150, face fluxes about 60*150 (HLLC), lift 2*5*N*150, stage update 4*5*N.
+def k4_flops_per_cell(forcing):
+    N, Q, F = 35, 125, 150
+    f = 2 * 5 * N * Q + 40 * Q + 2 * 3 * 5 * N * Q + 2 * 2 * 5 * N * F + 60 * F + 2 * 5 * N * F + 4 * 5 * N
+    if forcing:
+        f += 2 * 4 * N * Q + 8 * Q
+    return f
+
+
+def k4_cost(args, dg, torch):
+    """Stage launches at k = 4 (the quadrature-form kernel) in FP64 and FP32 on a k4_n^3 mesh
+    with the same workload recipe; the bound is the vector ALU (flops per cell above)."""
+    from paper_1602_09079_amd import synth
+    n, k = args.k4_n, 4
+    out = dict(n=n, k=k, flops_per_cell=k4_flops_per_cell(not args.no_forcing))
+    qp = synth.turbulence(n, dg.gauss_nodes(k + 1), seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
+    for prec, peak in (("fp64", FP64_VECTOR_TFLOPS), ("fp32", FP32_VECTOR_TFLOPS)):
+        s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing)
+        if not args.no_forcing:
+            nvec, ahat, _ = driving_table(dg)
+            s.set_forcing(nvec, ahat)
+        y = s.project(qp.to(s.dtype))
+        w1 = torch.empty_like(y)
+        h = s.dt(y)
+        s.stage(y, y, w1, 0.0, 1.0, h)
+        torch.cuda.synchronize()
+        reps = max(3, args.steps)
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record(s.stream)
+        for _ in range(reps):
+            s.stage(y, y, w1, 0.0, 1.0, h)
+        eb.record(s.stream)
+        torch.cuda.synchronize()
+        ms = ea.elapsed_time(eb) / reps
+        tf = out["flops_per_cell"] * n ** 3 / (ms / 1e3) / 1e12
+        out[prec] = dict(stage_ms=ms, dof_updates_per_s=5 * dg.nmodes(k) * n ** 3 / (ms / 1e3),
+                         alu_TFLOPs=round(tf, 2), alu_peak_TFLOPs=peak, alu_frac=round(tf / peak, 4))
+        log(args, f"[bench] k=4 {prec} stage 1 on {n}^3: {ms:.3f} ms, {tf:.2f} TFLOP/s")
+        del s, y, w1
+        torch.cuda.empty_cache()
+    del qp
+    torch.cuda.empty_cache()
+    return out
+
+
 def limiter_cost(args, dg, torch, prec, qp_dev, n, k):
     """Stage launches of the primary tier with the positivity limiter of Sec. 2.5 on the
     stage input (the paper applies it every stage; the smooth workload never needs it, so this
@@ -373,6 +425,7 @@ def main():
     diag = diagnostics_cost(args, dg, torch, prim0, qp, n, k) if args.diagnostics else None
     ers = None if args.no_limiter else exact_riemann_cost(args, dg, torch, prim0, qp, n, k)
     shr = None if args.no_limiter else share_cost(args, dg, torch, prim0, qp, n, k)
+    k4 = None if (args.no_limiter or args.k4_n <= 0 or k == 4) else k4_cost(args, dg, torch)
     del qp
     torch.cuda.empty_cache()
     # the box's own copy bandwidth (2 GiB device-to-device, read + write bytes), the second roof
@@ -454,6 +507,8 @@ def main():
         line["exact_riemann"] = dict(ers, stage1_ms_hllc=results[ers["tier"]]["stage_ms_each"][0])
     if shr is not None:
         line["z_slab_share"] = dict(shr, whole_stage1_ms=results[shr["tier"]]["stage_ms_each"][0])
+    if k4 is not None:
+        line["k4_stage"] = k4
     print(json.dumps(line), flush=True)
 
 

@@ -1298,6 +1298,17 @@ static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
 //   src  [q][l]    w_q phi_l(xi_q) / 8
 //   trace[f][l][p] phi_l at point p of face f = 2 d + side (side 1: the + face)
 //   lift [f][p][l] (+/-) s_d w_p phi_l at that point, + on the + face
+// for (i = 0; i < n; i++) f(i), unrolled U times (U = 0: as the compiler chooses)
+template <int U, class F>
+__device__ inline void unrolled_for(int n, F &&f) {
+    if constexpr (U == 0) {
+        for (int i = 0; i < n; i++) f(i);
+    } else {
+#pragma unroll U
+        for (int i = 0; i < n; i++) f(i);
+    }
+}
+
 template <int K>
 struct QuadTab {
     static constexpr int N = Dims<K>::N, Q = Dims<K>::Q, P = Dims<K>::P;
@@ -1315,6 +1326,8 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
     constexpr int N = T::N, Q = T::Q, P = T::P, E = NF * N;
     constexpr int WORK = (3 * NF + 4) * Q;  // point fluxes [d][i][q] and sources [c][q]; later face fluxes
     static_assert(WORK >= NF * 6 * P && N <= QS_THREADS, "quadrature kernel shape");
+    // FP32: unrolled inner loops batch the table loads; FP64: the compiler's own unrolling
+    constexpr int U7 = PREC == DG_FP64 ? 0 : 7, U5 = PREC == DG_FP64 ? 0 : 5, U6 = PREC == DG_FP64 ? 0 : 6;
     __shared__ C ys[7][E];  // the cell, then its -x, +x, -y, +y, -z, +z neighbours: [i * N + l]
     __shared__ C work[WORK];
     const C *tab = static_cast<const C *>(a.tables);
@@ -1365,11 +1378,11 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         // volume points: state, the three directional fluxes, the driving source
         for (int q = lane; q < Q; q += QS_THREADS) {
             C u[NF] = {0, 0, 0, 0, 0};
-            for (int l = 0; l < N; l++) {
+            unrolled_for<U7>(N, [&](int l) {
                 const C ph = tab[T::phi + l * Q + q];
 #pragma unroll
                 for (int i = 0; i < NF; i++) u[i] += ys[0][i * N + l] * ph;
-            }
+            });
             C F[3][5];
             euler_flux3<PR>(u, g1, F);
 #pragma unroll
@@ -1393,7 +1406,7 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         __syncthreads();
         C acc[NF] = {0, 0, 0, 0, 0};
         if (lane < N) {
-            for (int q = 0; q < Q; q++) {
+            unrolled_for<U5>(Q, [&](int q) {
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
                     const C gt = tab[T::grad + (q * 3 + d) * N + lane];
@@ -1405,21 +1418,21 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
 #pragma unroll
                     for (int c = 0; c < 4; c++) acc[1 + c] -= work[(3 * NF + c) * Q + q] * st;
                 }
-            }
+            });
         }
         __syncthreads();
         // face points: the cell's trace, the neighbour's trace on the same face, the Riemann flux
         for (int j = lane; j < 6 * P; j += QS_THREADS) {
             const int f = j / P, p = j - f * P;
             C uo[NF] = {0, 0, 0, 0, 0}, un[NF] = {0, 0, 0, 0, 0};
-            for (int l = 0; l < N; l++) {
+            unrolled_for<U7>(N, [&](int l) {
                 const C to = tab[T::trace + (f * N + l) * P + p], tn = tab[T::trace + ((f ^ 1) * N + l) * P + p];
 #pragma unroll
                 for (int i = 0; i < NF; i++) {
                     uo[i] += ys[0][i * N + l] * to;
                     un[i] += ys[1 + f][i * N + l] * tn;
                 }
-            }
+            });
             C F[5];
             const bool plus = f & 1;
             const C *qL = plus ? uo : un, *qR = plus ? un : uo;
@@ -1433,11 +1446,11 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         }
         __syncthreads();
         if (lane < N) {
-            for (int fp = 0; fp < 6 * P; fp++) {
+            unrolled_for<U6>(6 * P, [&](int fp) {
                 const C lt = tab[T::lift + fp * N + lane];
 #pragma unroll
                 for (int i = 0; i < NF; i++) acc[i] += work[i * 6 * P + fp] * lt;
-            }
+            });
             const C dt = (C)dtd;
 #pragma unroll
             for (int i = 0; i < NF; i++) {
