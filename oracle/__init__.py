@@ -321,7 +321,7 @@ def gll(m):
 
 
 def limiter_points(k):
-    pts = np.zeros((3 * 3 * (k + 1) ** 2, 3))
+    pts = np.zeros((3 * 4 * (k + 1) ** 2, 3))
     n = lib().orc_limiter_points(k, _d(pts))
     return pts[:n]
 

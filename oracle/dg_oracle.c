@@ -842,14 +842,22 @@ int64_t orc_closure_correction(const orc_cfg *cfg, const double *y, const orc_cl
 /* Sec. 2.5: positivity limiter                                         */
 /* ------------------------------------------------------------------ */
 
-int orc_limiter_m(int k) { return k <= 1 ? 2 : 3; }
+/* m GLL nodes per axis, the fewest whose rule is exact for degree k (2m - 3 >= k): the paper's
+ * first weights are 1 (m = 2) for second order and 1/3 (m = 3) for third and fourth order; k = 4
+ * takes m = 4 by the same exactness condition */
+int orc_limiter_m(int k) { return k <= 1 ? 2 : (k <= 3 ? 3 : 4); }
 
 void orc_gll(int m, double *x, double *w)
 {
-    /* Gauss-Lobatto-Legendre rules with 2 and 3 points on [-1, 1] (closed forms) */
+    /* Gauss-Lobatto-Legendre rules with 2, 3 and 4 points on [-1, 1] (closed forms; the
+     * interior nodes of the 4-point rule are the roots of P_3'(x) = (15 x^2 - 3) / 2) */
     if (m == 2) {
         x[0] = -1.0; x[1] = 1.0;
         w[0] = 1.0; w[1] = 1.0;
+    } else if (m == 4) {
+        const double a = 1.0 / sqrt(5.0);
+        x[0] = -1.0; x[1] = -a; x[2] = a; x[3] = 1.0;
+        w[0] = 1.0 / 6.0; w[1] = 5.0 / 6.0; w[2] = 5.0 / 6.0; w[3] = 1.0 / 6.0;
     } else {
         x[0] = -1.0; x[1] = 0.0; x[2] = 1.0;
         w[0] = 1.0 / 3.0; w[1] = 4.0 / 3.0; w[2] = 1.0 / 3.0;
@@ -861,7 +869,7 @@ void orc_gll(int m, double *x, double *w)
 int orc_limiter_points(int k, double *pts)
 {
     int n = k + 1, m = orc_limiter_m(k), c = 0;
-    double xg[GMAX], wg[GMAX], xl[3], wl[3];
+    double xg[GMAX], wg[GMAX], xl[4], wl[4];
     orc_gauss_legendre(n, xg, wg);
     orc_gll(m, xl, wl);
     for (int a = 0; a < 3; a++)
@@ -899,7 +907,7 @@ void orc_limit(const orc_cfg *cfg, double *y, double eps, double rel, double *th
 {
     int k = cfg->k, N = orc_nmodes(k);
     size_t nc = ncells_of(cfg);
-    double pts[3 * 3 * 3 * GMAX * GMAX];
+    double pts[3 * 3 * 4 * GMAX * GMAX];
     int np = orc_limiter_points(k, pts);
     double *phi = malloc(sizeof(double) * np * N);
     for (int p = 0; p < np; p++) orc_basis(k, pts + 3 * p, phi + (size_t)p * N);
@@ -950,7 +958,7 @@ void orc_limit(const orc_cfg *cfg, double *y, double eps, double rel, double *th
 
 double orc_dt_limited(const orc_cfg *cfg, const double *y)
 {
-    double xl[3], wl[3];
+    double xl[4], wl[4];
     orc_gll(orc_limiter_m(cfg->k), xl, wl);
     double f = fmin(1.0 / (2.0 * cfg->k + 1.0), 0.5 * wl[0]);
     return orc_dt(cfg, y) * (2.0 * cfg->k + 1.0) * f;

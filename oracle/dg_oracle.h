@@ -97,7 +97,8 @@ void orc_ou_update(int32_t nmodes, const int32_t *nvec, double *theta, const dou
 
 /* ---- Sec. 2.5: positivity limiter (Zhang and Shu) ----
  * Points S = S_x u S_y u S_z: the m GLL nodes along one axis (m = 2 for k <= 1,
- * 3 for k >= 2) times the k+1 Gauss nodes along the other two.  Per cell:
+ * 3 for k = 2, 3, 4 for k = 4: the fewest with 2m - 3 >= k) times the k+1 Gauss
+ * nodes along the other two.  Per cell:
  * theta_1 = min(|(rhobar - eps)/(rhobar - rho_min)|, 1) over S scales the
  * density's modes l >= 1; then theta_2 = min over S of tau, tau = 1 where
  * P >= eps, else the root of P(qbar + tau (q - qbar)) = eps (the garbled

@@ -16,10 +16,18 @@ EPS = O.LIMIT_EPS
 
 def test_gll_rules_against_paper_and_exactness():
     gold = json.load(open(os.path.join(HERE, "golden", "gll.json")))
-    for m in (2, 3):
+    for m in (2, 3, 4):
         x, w = O.gll(m)
-        np.testing.assert_allclose(x, gold[f"m{m}"]["nodes"], rtol=0, atol=1e-16)
-        np.testing.assert_allclose(w, gold[f"m{m}"]["weights"], rtol=1e-15)
+        if m < 4:
+            np.testing.assert_allclose(x, gold[f"m{m}"]["nodes"], rtol=0, atol=1e-16)
+            np.testing.assert_allclose(w, gold[f"m{m}"]["weights"], rtol=1e-15)
+        # the general rule: interior nodes = roots of P'_{m-1}, w_j = 2 / (m (m-1) P_{m-1}(x_j)^2)
+        from numpy.polynomial import legendre as npl
+        c = np.zeros(m)
+        c[m - 1] = 1.0
+        nodes = np.concatenate(([-1.0], np.sort(npl.legroots(npl.legder(c))), [1.0]))
+        np.testing.assert_allclose(x, nodes, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(w, 2.0 / (m * (m - 1) * npl.legval(nodes, c) ** 2), rtol=1e-14)
         # exact for degree 2m - 3
         for d in range(2 * m - 2):
             exact = 0.0 if d % 2 else 2.0 / (d + 1)
@@ -27,12 +35,19 @@ def test_gll_rules_against_paper_and_exactness():
     for k, order in ((1, "2"), (2, "3"), (3, "4")):
         _, w = O.gll(2 if k <= 1 else 3)
         assert w[0] == pytest.approx(gold["first_weight_by_order"][order], rel=1e-15)
+    # one node fewer is not exact for degree 2m - 3 (m = 4: x^4 needs the fourth node)
+    x, w = O.gll(3)
+    assert abs(np.dot(w, x ** 4) - 2.0 / 5.0) > 0.1
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+def _m(k):
+    return 2 if k <= 1 else (3 if k <= 3 else 4)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_limiter_points(k):
     pts = O.limiter_points(k)
-    m = 2 if k <= 1 else 3
+    m = _m(k)
     assert pts.shape == (3 * m * (k + 1) ** 2, 3)
     xg, _ = O.gauss_legendre(k + 1)
     for a in range(3):
@@ -48,7 +63,7 @@ def _values_at(k, w, pts):
     return phi @ w
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_limiter_identity_on_positive_states(k):
     cfg = O.make_cfg(k, 6, gamma=G)
     x = O.gauss_legendre(k + 1)[0]
@@ -95,7 +110,7 @@ def test_pressure_theta_closed_form():
     assert yl[4, 3, 0, 0, 0] == pytest.approx(b * tau, rel=1e-12)
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_limiter_invariants_on_violated_states(k):
     cfg = O.make_cfg(k, (4, 3, 3), gamma=G)
     rng = np.random.default_rng(31 + k)
@@ -121,7 +136,8 @@ def test_limiter_invariants_on_violated_states(k):
 
 def test_limited_dt_factor():
     cfg = O.make_cfg(1, 4, gamma=G)
-    for k, ratio in ((1, 1.0), (2, (1 / 6) / (1 / 5)), (3, 1.0)):
+    # C min(1/(2k+1), w_hat_1/2) against C/(2k+1): w_hat_1 = 1, 1/3, 1/3, 1/6
+    for k, ratio in ((1, 1.0), (2, (1 / 6) / (1 / 5)), (3, 1.0), (4, (1 / 12) / (1 / 9))):
         cfg = O.make_cfg(k, 4, gamma=G)
         x = O.gauss_legendre(k + 1)[0]
         y = O.project(cfg, synth.turbulence(4, x, seed=1, mach=0.3).numpy())
@@ -148,12 +164,12 @@ def test_relative_targets_closed_form():
     assert th[0, 0] == pytest.approx((1.0 - rel) / (1.0 - rmin), rel=1e-14)
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_each_point_set_reproduces_the_cell_mean(k):
     """Sec. 2.5: with the GLL weights along the axis and the Gauss weights across it,
     each of S_x, S_y, S_z integrates a degree-k polynomial exactly, so the cell mean is
     a convex combination of the values on S (the property the limiter rests on)."""
-    m = 2 if k <= 1 else 3
+    m = _m(k)
     xl, wl = O.gll(m)
     xg, wg = O.gauss_legendre(k + 1)
     pts = O.limiter_points(k)
@@ -178,7 +194,7 @@ def test_each_point_set_reproduces_the_cell_mean(k):
         assert s == pytest.approx(u[0], abs=1e-13)
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_limiter_is_not_stricter_than_needed(k):
     """The scaling factors are the largest that reach the targets: where theta_2 < 1 the
     minimum pressure over S after limiting equals eps; where only theta_1 < 1 the minimum
