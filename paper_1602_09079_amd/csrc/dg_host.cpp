@@ -59,6 +59,11 @@ bool gauss_rule(int n, double *x, double *w) {
     }
 }
 
+// Gauss-Lobatto nodes per axis of the limiter's point set (Sec. 2.5): the fewest whose rule is
+// exact for degree k (2m - 3 >= k), which gives the paper's first weights 1 (second order) and
+// 1/3 (third and fourth order), and 1/6 at k = 4
+int limiter_gll_points(int k) { return k <= 1 ? 2 : (k <= 3 ? 3 : 4); }
+
 // explicit Legendre polynomials P_u and derivatives, u <= 4, times sqrt(2u+1)
 double leg(int u, double x) {
     double p;
@@ -303,7 +308,10 @@ size_t elem_bytes(const dg_ctx *c) { return c->cfg.precision == DG_FP64 ? 8 : 4;
 // C / (2k+1) (Sec. 2.4); with the positivity limiter C min(1/(2k+1), w_hat_1/2) (Sec. 2.5)
 double dt_factor(const dg_ctx *c) {
     double f = 1.0 / (2.0 * c->cfg.k + 1.0);
-    if (c->cfg.flags & DG_LIMIT) f = std::min(f, 0.5 * (c->cfg.k <= 1 ? 1.0 : 1.0 / 3.0));
+    if (c->cfg.flags & DG_LIMIT) {
+        const int m = limiter_gll_points(c->cfg.k);  // first Gauss-Lobatto weight: 1, 1/3, 1/6
+        f = std::min(f, 0.5 * (m == 2 ? 1.0 : (m == 3 ? 1.0 / 3.0 : 1.0 / 6.0)));
+    }
     return c->cfg.cfl * f;
 }
 
@@ -374,10 +382,8 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
                     DG_ZHALO))
         return DG_ERR_ARG;
     if (cfg->k > 4) return DG_ERR_UNSUPPORTED;
-    // k = 4 runs the quadrature-form kernel: FP64 and FP32 storage, no limiter (its point set
-    // would need four Gauss-Lobatto nodes per axis)
-    if (cfg->k == 4 && ((cfg->precision != DG_FP64 && cfg->precision != DG_FP32) || (cfg->flags & DG_LIMIT)))
-        return DG_ERR_UNSUPPORTED;
+    // k = 4 runs the quadrature-form kernel: FP64 and FP32 storage
+    if (cfg->k == 4 && cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
     if ((cfg->flags & DG_CLOSURE) && (cfg->flags & DG_ZHALO)) return DG_ERR_UNSUPPORTED;
     {
@@ -436,8 +442,10 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (cfg->flags & DG_LIMIT) {
         // phi_l at the limiter points: GLL nodes along one axis, Gauss nodes along the others
         const Basis B(cfg->k);
-        const int m = cfg->k <= 1 ? 2 : 3;
-        const double xl[3] = {-1.0, m == 2 ? 1.0 : 0.0, 1.0};
+        const int m = limiter_gll_points(cfg->k);
+        const double a5 = 1.0 / std::sqrt(5.0);
+        const double xl2[2] = {-1.0, 1.0}, xl3[3] = {-1.0, 0.0, 1.0}, xl4[4] = {-1.0, -a5, a5, 1.0};
+        const double *xl = m == 2 ? xl2 : (m == 3 ? xl3 : xl4);
         std::vector<double> lt;
         for (int a = 0; a < 3; a++)
             for (int r = 0; r < m; r++)

@@ -1811,10 +1811,16 @@ static hipError_t launch_limit_k(int prec, void *y, const double *tab, int np, l
                                  double eps, unsigned long long *count, hipStream_t s) {
     const long long nb = (nc + 255) / 256;
     const int N = Dims<K>::N;
-    if (prec == DG_FP64)
-        hipLaunchKernelGGL((limit_kernel<K, double>), dim3(nb), dim3(256), (np + 1) * N * 8, s, (double *)y, tab, np, nc, nx,
+    if (prec == DG_FP64) {
+        const int bytes = (np + 1) * N * 8;  // k = 4: 84 KB, above the default dynamic LDS limit
+        if (bytes > 65536) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&limit_kernel<K, double>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((limit_kernel<K, double>), dim3(nb), dim3(256), bytes, s, (double *)y, tab, np, nc, nx,
                            gamma, eps, 0.0, count);
-    else
+    } else
         hipLaunchKernelGGL((limit_kernel<K, float>), dim3(nb), dim3(256), (np + 1) * N * 4, s, (float *)y, tab, np, nc, nx,
                            gamma, eps, LIMIT_REL_FP32, count);
     return hipGetLastError();
@@ -1827,6 +1833,7 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
         case 1: return launch_limit_k<1>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         case 2: return launch_limit_k<2>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         case 3: return launch_limit_k<3>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
+        case 4: return launch_limit_k<4>(prec, y, tab, np, nc, nx, gamma, eps, count, s);
         default: return hipErrorInvalidValue;
     }
 }

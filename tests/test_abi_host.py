@@ -83,7 +83,6 @@ def test_ou_update_matches_oracle():
     (dict(k=5, n=8), dg.DG_ERR_UNSUPPORTED),
     (dict(k=4, n=8, precision="bf16"), dg.DG_ERR_UNSUPPORTED),  # k = 4: FP64 and FP32 storage only
     (dict(k=4, n=8, precision="bf16x3"), dg.DG_ERR_UNSUPPORTED),
-    (dict(k=4, n=8, flags=dg.DG_LIMIT), dg.DG_ERR_UNSUPPORTED),
     (dict(k=1, n=(8, 1, 8)), dg.DG_ERR_ARG),
     (dict(k=1, n=8, box=(1.0, 0.0, 1.0)), dg.DG_ERR_ARG),
     (dict(k=1, n=8, gamma=1.0), dg.DG_ERR_ARG),

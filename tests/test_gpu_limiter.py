@@ -53,7 +53,7 @@ def violated_state(k, n, seed):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_limiter_parity(dgm, k, prec):
     n = (20, 5, 4)
     cfg, y = violated_state(k, n, 40 + k)
@@ -96,7 +96,7 @@ def blast(k, n, pl=1000.0, pr=0.01):
     return cfg, O.project(cfg, qp)
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_limited_dt_and_steps_parity(dgm, k):
     cfg, y = blast(k, 32)
     s = dgm.Solver(k, (32, 2, 2), gamma=G, cfl=0.3, precision="fp64", limit=True)
@@ -117,7 +117,7 @@ def test_limited_dt_and_steps_parity(dgm, k):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_limiter_keeps_blast_physical(dgm, k, prec):
     cfg, y = blast(k, 32)
     plain = dgm.Solver(k, (32, 2, 2), gamma=G, cfl=0.3, precision=prec, check_range=True)
