@@ -44,7 +44,7 @@ typedef struct dg_ctx dg_ctx;
 typedef enum {
     DG_OK = 0,
     DG_ERR_ARG = 1,          /* invalid argument or configuration */
-    DG_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. k > 3) */
+    DG_ERR_UNSUPPORTED = 2,  /* valid but not built (e.g. k > 4) */
     DG_ERR_HIP = 3,          /* a HIP runtime call failed */
     DG_ERR_RANGE = 4,        /* non-physical state detected (DG_CHECK_RANGE) */
     DG_ERR_STATE = 5         /* call out of order (e.g. forcing flag without a table) */
@@ -68,7 +68,8 @@ enum {
 };
 
 typedef struct {
-    int32_t k;          /* polynomial degree; this build supports 0 (first-order finite volume), 1, 2, 3 */
+    int32_t k;          /* polynomial degree 0..4: 0 first-order finite volume, 1..3 the MFMA stage kernel,
+                           4 the quadrature-form kernel (FP64 and FP32 storage only) */
     int32_t n[3];       /* cells per axis, each >= 2 */
     double box[3];      /* box lengths (> 0); cell widths are box[a]/n[a] */
     double gamma;       /* adiabatic index, > 1 */
@@ -81,8 +82,10 @@ typedef struct {
  * upload them and allocate the context's small device slots (dt, time,
  * partial sums).  hip_stream: a hipStream_t (NULL = default stream).
  * DG_ERR_ARG and no context for: k < 0, any n < 2, box <= 0, gamma <= 1,
- * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 3,
- * DG_CLOSURE with k != 1, or a slab (5 N(k) n[0] elements) of 2 GiB or more. */
+ * cfl outside (0, 1], unknown precision or flags.  DG_ERR_UNSUPPORTED for k > 4,
+ * k = 4 with DG_BF16 or DG_BF16X3, DG_CLOSURE with k != 1, or a slab (5 N(k) n[0]
+ * elements) of 2 GiB or more.  With DG_LIMIT the limiter's point set has m = 2, 3, 3, 4
+ * Gauss-Lobatto nodes per axis for k = 1, 2, 3, 4 (Sec. 2.5). */
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out);
 
 /* Release the context and its device memory.  NULL is accepted. */
@@ -245,7 +248,9 @@ dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shi
  * dg_step), IN PLACE: the caller's y / yin is replaced by its limited value
  * (for dg_step: y^n before the time step is computed, then y^(1), y^(2)).
  * Points S: along one axis the m GLL nodes (m = 2 for k = 1, m = 3 for
- * k = 2, 3: -1, 0, 1), along the other two the k+1 Gauss nodes, for each axis.
+ * k = 2, 3: -1, 0, 1; m = 4 for k = 4: -1, -1/sqrt(5), 1/sqrt(5), 1; the fewest
+ * nodes whose rule is exact for degree k), along the other two the k+1 Gauss
+ * nodes, for each axis.
  * Per cell, eps = 1e-13: theta_1 = min(|(rhobar - eps)/(rhobar - rho_min)|, 1)
  * scales the density's modes l >= 1; then theta_2 = min over S of tau, tau = 1
  * where P >= eps (and rho > 0), else the root in (0, 1) of
@@ -255,7 +260,7 @@ dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shi
  * max(eps, 2^-20 (gamma-1) Ebar) for the pressure, above the rounding of the
  * stored weights, which would otherwise undo the limiting.  With DG_LIMIT the CFL
  * step becomes C min(1/(2k+1), w_hat_1/2) / max rate, w_hat_1 the first GLL
- * weight (1 for k = 1, 1/3 for k = 2, 3).  Computed in the storage
+ * weight (1 for k = 1, 1/3 for k = 2, 3, 1/6 for k = 4).  Computed in the storage
  * precision (FP32 for the FP32-storage tiers).
  *
  * Cells changed by the limiter since the previous call, then reset.
