@@ -1286,18 +1286,21 @@ static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// k = 4 (N = 35 modes, 125 volume points): the quadrature form of eq. (2.4)'s operator with one
-// wave per cell, no MFMA tiling.  The cell's weights and its six face neighbours' are staged in
-// LDS; lanes over the volume points form the point states and their Euler fluxes (and the
-// driving source), then lanes over the modes contract them with the weighted basis gradients;
-// lanes over the 6 x 25 face points form both traces and the Riemann flux, and lanes over the
-// modes lift it.  Each face is solved by both of its cells with the same arithmetic, so the two
-// get the same flux.  Tables (in the storage precision, built at init; s_d = 1/(4 h_d)):
+// k = 4 (N = 35 modes, 125 volume points): the quadrature form of the volume and surface
+// integrals (eqs. dg:eqn:volume_int, dg:eqn:surface_int) with one workgroup of two waves per cell,
+// no MFMA tiling.  The cell's weights and its six face neighbours' are staged in LDS; threads over
+// the volume points form the point states and their Euler fluxes (and the driving source), then
+// lanes over the modes contract them with the weighted basis gradients, each wave over half of
+// the points; threads over the 6 x 25 face points form both traces and the Riemann flux, and lanes
+// over the modes lift it, each wave over half of the faces; the two waves' sums meet in LDS.  Each
+// face is solved by both of its cells with the same arithmetic, so the two get the same flux.
+// Tables (in the storage precision, built at init; s_d = 1/(4 h_d)):
 //   phi  [l][q]    phi_l(xi_q)
 //   grad [q][d][l] s_d w_q d/dxi_d phi_l(xi_q)
 //   src  [q][l]    w_q phi_l(xi_q) / 8
 //   trace[f][l][p] phi_l at point p of face f = 2 d + side (side 1: the + face)
 //   lift [f][p][l] (+/-) s_d w_p phi_l at that point, + on the + face
+
 // for (i = 0; i < n; i++) f(i), unrolled U times (U = 0: as the compiler chooses)
 template <int U, class F>
 __device__ inline void unrolled_for(int n, F &&f) {
@@ -1315,7 +1318,7 @@ struct QuadTab {
     static constexpr int phi = 0, grad = N * Q, src = grad + 3 * Q * N, trace = src + Q * N, lift = trace + 6 * N * P,
                          total = lift + 6 * P * N;
 };
-constexpr int QS_THREADS = 64;
+constexpr int QS_THREADS = 128;  // two waves per cell: twice the waves in flight for the same LDS
 
 template <int K, int PREC, bool FORCE, int RS>
 __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
@@ -1325,16 +1328,18 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
     using T = QuadTab<K>;
     constexpr int N = T::N, Q = T::Q, P = T::P, E = NF * N;
     constexpr int WORK = (3 * NF + 4) * Q;  // point fluxes [d][i][q] and sources [c][q]; later face fluxes
-    static_assert(WORK >= NF * 6 * P && N <= QS_THREADS, "quadrature kernel shape");
+    static_assert(WORK >= NF * 6 * P && N <= 64 && QS_THREADS == 128, "quadrature kernel shape");
+    // the mode-parallel contractions split their point (face point) range between the two waves
+    constexpr int QH = (Q + 1) / 2, FH = 3 * P;
     // FP32: unrolled inner loops batch the table loads; FP64: the compiler's own unrolling
-    constexpr int U7 = PREC == DG_FP64 ? 0 : 7, U5 = PREC == DG_FP64 ? 0 : 5, U6 = PREC == DG_FP64 ? 0 : 6;
+    constexpr int U7 = PREC == DG_FP64 ? 0 : 7, U5 = PREC == DG_FP64 ? 0 : 7, U6 = PREC == DG_FP64 ? 0 : 5;
     __shared__ C ys[7][E];  // the cell, then its -x, +x, -y, +y, -z, +z neighbours: [i * N + l]
     __shared__ C work[WORK];
     const C *tab = static_cast<const C *>(a.tables);
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double dtd = a.dt;
     if (a.rate) dtd = a.dtfac / a.rate[0];
-    if (a.tacc && blockIdx.x == 0 && lane == 0) a.tacc[0] += dtd;
+    if (a.tacc && blockIdx.x == 0 && tid == 0) a.tacc[0] += dtd;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const C gam = (C)a.gamma, g1 = gam - C(1);
     const S *yin = static_cast<const S *>(a.yin);
@@ -1351,7 +1356,7 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         const int ix = (int)(cell % nx);
         const long long row = cell / nx;
         const int iy = (int)(row % ny), iz = (int)(row / ny);
-        for (int j = lane; j < 7 * E; j += QS_THREADS) {
+        for (int j = tid; j < 7 * E; j += QS_THREADS) {
             const int c = j / E, e = j - c * E;
             int x = ix, yy = iy, zz = iz;
             if (c > 0) {
@@ -1376,7 +1381,7 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         }
         __syncthreads();
         // volume points: state, the three directional fluxes, the driving source
-        for (int q = lane; q < Q; q += QS_THREADS) {
+        for (int q = tid; q < Q; q += QS_THREADS) {
             C u[NF] = {0, 0, 0, 0, 0};
             unrolled_for<U7>(N, [&](int l) {
                 const C ph = tab[T::phi + l * Q + q];
@@ -1406,7 +1411,9 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         __syncthreads();
         C acc[NF] = {0, 0, 0, 0, 0};
         if (lane < N) {
-            unrolled_for<U5>(Q, [&](int q) {
+            unrolled_for<U5>(QH, [&](int qq) {
+                const int q = wave * QH + qq;
+                if (q >= Q) return;
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
                     const C gt = tab[T::grad + (q * 3 + d) * N + lane];
@@ -1422,7 +1429,7 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         }
         __syncthreads();
         // face points: the cell's trace, the neighbour's trace on the same face, the Riemann flux
-        for (int j = lane; j < 6 * P; j += QS_THREADS) {
+        for (int j = tid; j < 6 * P; j += QS_THREADS) {
             const int f = j / P, p = j - f * P;
             C uo[NF] = {0, 0, 0, 0, 0}, un[NF] = {0, 0, 0, 0, 0};
             unrolled_for<U7>(N, [&](int l) {
@@ -1446,11 +1453,22 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
         }
         __syncthreads();
         if (lane < N) {
-            unrolled_for<U6>(6 * P, [&](int fp) {
+            unrolled_for<U6>(FH, [&](int ff) {
+                const int fp = wave * FH + ff;
                 const C lt = tab[T::lift + fp * N + lane];
 #pragma unroll
                 for (int i = 0; i < NF; i++) acc[i] += work[i * 6 * P + fp] * lt;
             });
+        }
+        __syncthreads();  // the face fluxes are read; the second wave's sums go through LDS
+        if (wave == 1 && lane < N) {
+#pragma unroll
+            for (int i = 0; i < NF; i++) work[i * N + lane] = acc[i];
+        }
+        __syncthreads();
+        if (wave == 0 && lane < N) {
+#pragma unroll
+            for (int i = 0; i < NF; i++) acc[i] += work[i * N + lane];
             const C dt = (C)dtd;
 #pragma unroll
             for (int i = 0; i < NF; i++) {
