@@ -271,7 +271,9 @@ dg_status dg_limiter_stats(dg_ctx *ctx, int64_t *count);
 int32_t dg_nmodes(int32_t k);                      /* N(k) = (k+1)(k+2)(k+3)/6, Sec. 2.1 */
 dg_status dg_gauss_nodes(int32_t n, double *xi);   /* n-point Gauss-Legendre nodes on [-1,1], 1 <= n <= 5, ascending */
 
-/* Last error message of ctx ("" if none); a static string for ctx == NULL. */
+/* Last error message of ctx ("" if none).  ctx == NULL: why the calling thread's last dg_init
+ * failed (the rejected argument, or the failing HIP call's error name and text), or a fixed
+ * message if it has not failed.  The string stays valid until the thread's next dg_init. */
 const char *dg_error_string(const dg_ctx *ctx);
 
 /* ---------------------------------------------------------------------------

@@ -291,6 +291,8 @@ std::vector<char> build_quad_tables(int k, int prec, const double s[3]) {
 }
 
 const char *kNoCtx = "invalid or NULL dg_ctx";
+// why the calling thread's last dg_init failed (no context survives to hold it)
+thread_local std::string g_init_err;
 
 dg_status hip_fail(dg_ctx *c, hipError_t e, const char *what) {
     if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -366,36 +368,47 @@ dg_status dg_gauss_nodes(int32_t n, double *xi) {
     return DG_OK;
 }
 
-const char *dg_error_string(const dg_ctx *ctx) { return ctx ? ctx->err.c_str() : kNoCtx; }
+const char *dg_error_string(const dg_ctx *ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_init_err.empty() ? kNoCtx : g_init_err.c_str();
+}
 
 dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
-    if (!cfg || !out) return DG_ERR_ARG;
+    g_init_err.clear();
+    auto reject = [](dg_status st, const char *why) {
+        g_init_err = std::string("dg_init: ") + why;
+        return st;
+    };
+    if (!cfg || !out) return reject(DG_ERR_ARG, "NULL cfg or out");
     *out = nullptr;
-    if (cfg->k < 0) return DG_ERR_ARG;
+    if (cfg->k < 0) return reject(DG_ERR_ARG, "k < 0");
     for (int a = 0; a < 3; a++)
-        if (cfg->n[a] < 2 || !(cfg->box[a] > 0.0) || !std::isfinite(cfg->box[a])) return DG_ERR_ARG;
-    if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return DG_ERR_ARG;
-    if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return DG_ERR_ARG;
-    if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return DG_ERR_ARG;
+        if (cfg->n[a] < 2 || !(cfg->box[a] > 0.0) || !std::isfinite(cfg->box[a]))
+            return reject(DG_ERR_ARG, "n < 2 or box not positive and finite");
+    if (!(cfg->gamma > 1.0) || !std::isfinite(cfg->gamma)) return reject(DG_ERR_ARG, "gamma <= 1");
+    if (!(cfg->cfl > 0.0 && cfg->cfl <= 1.0)) return reject(DG_ERR_ARG, "cfl outside (0, 1]");
+    if (cfg->precision < DG_FP64 || cfg->precision > DG_BF16X3) return reject(DG_ERR_ARG, "unknown precision");
     if (cfg->flags &
         ~(uint32_t)(DG_FORCING | DG_CLOSURE | DG_CHECK_RANGE | DG_LIMIT | DG_ISOTHERMAL | DG_EXACT_RIEMANN |
                     DG_ZHALO))
-        return DG_ERR_ARG;
-    if (cfg->k > 4) return DG_ERR_UNSUPPORTED;
+        return reject(DG_ERR_ARG, "unknown flags");
+    if (cfg->k > 4) return reject(DG_ERR_UNSUPPORTED, "k > 4");
     // k = 4 runs the quadrature-form kernel: FP64 and FP32 storage
-    if (cfg->k == 4 && cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_ERR_UNSUPPORTED;
-    if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return DG_ERR_UNSUPPORTED;
-    if ((cfg->flags & DG_CLOSURE) && (cfg->flags & DG_ZHALO)) return DG_ERR_UNSUPPORTED;
+    if (cfg->k == 4 && cfg->precision != DG_FP64 && cfg->precision != DG_FP32)
+        return reject(DG_ERR_UNSUPPORTED, "k = 4 takes FP64 or FP32 storage only");
+    if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return reject(DG_ERR_UNSUPPORTED, "DG_CLOSURE needs k = 1");
+    if ((cfg->flags & DG_CLOSURE) && (cfg->flags & DG_ZHALO))
+        return reject(DG_ERR_UNSUPPORTED, "DG_CLOSURE with DG_ZHALO");
     {
         // the stage kernel addresses one (z, y) slab of 5 N(k) rows of n[0] cells with 32-bit offsets
         const double slab_bytes = 5.0 * nmodes_of(cfg->k) * cfg->n[0] * (cfg->precision == DG_FP64 ? 8.0 : 4.0);
-        if (slab_bytes >= 2147483648.0) return DG_ERR_UNSUPPORTED;
+        if (slab_bytes >= 2147483648.0) return reject(DG_ERR_UNSUPPORTED, "a (z, y) row of the state is 2 GiB or more");
     }
     const long long ncells = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
-    if ((long long)cfg->n[0] > (1LL << 30) || ncells > (1LL << 40)) return DG_ERR_ARG;
+    if ((long long)cfg->n[0] > (1LL << 30) || ncells > (1LL << 40)) return reject(DG_ERR_ARG, "mesh too large");
 
     dg_ctx *c = new (std::nothrow) dg_ctx();
-    if (!c) return DG_ERR_HIP;
+    if (!c) return reject(DG_ERR_HIP, "out of host memory");
     c->cfg = *cfg;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->N = nmodes_of(cfg->k);
@@ -409,6 +422,12 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         s[a] = 1.0 / (4.0 * c->h[a]);  // (dx^2/4) / |K| of eqs. dg:eqn:volume_int and dg:eqn:surface_int
     }
     auto fail = [&](dg_status st) {
+        if (st == DG_ERR_HIP) {
+            const hipError_t e = hipGetLastError();
+            g_init_err = std::string("dg_init: HIP call failed: ") + hipGetErrorName(e) + ", " + hipGetErrorString(e);
+        } else {
+            g_init_err = "dg_init: the stage kernel's LDS exceeds the device's";
+        }
         dg_destroy(c);
         return st;
     };

@@ -213,7 +213,8 @@ class Solver:
         self._ctx = _vp()
         st = lib().dg_init(ctypes.byref(self.cfg), _vp(self.stream.cuda_stream), ctypes.byref(self._ctx))
         if st != DG_OK:
-            raise DGError(st, "dg_init failed")
+            why = lib().dg_error_string(None)
+            raise DGError(st, f"dg_init failed ({why.decode() if why else ''})")
         self.N = nmodes(k)
         self.nq = k + 1
         self._work = None

@@ -94,6 +94,8 @@ def test_ou_update_matches_oracle():
 ])
 def test_config_validation(kw, status):
     assert dg.init_status(dg.make_config(**kw)) == status
+    why = dg.lib().dg_error_string(None).decode()
+    assert why.startswith("dg_init: ") and len(why) > len("dg_init: "), why  # the reason is kept
 
 
 def test_mlp_host_helpers():
