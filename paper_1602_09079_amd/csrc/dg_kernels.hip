@@ -346,10 +346,10 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
         const C tiny = (sizeof(C) == 8 ? C(1e-300) : C(1e-30));
         C p = C(0.5) * (pL + pR) - C(0.125) * du * (rL + rR) * (cL + cR);
         p = p > tiny ? p : tiny;
-        // Newton converges quadratically: once a step changes p by less than tol2 (relative), one
-        // more step brings it to rounding, then stop
-        const C tol2 = sizeof(C) == 8 ? C(1e-8) : C(1e-4);
-        bool last = false;
+        // Newton converges quadratically: the error after a step is about the square of the step
+        // (relative), so a step below tol2 (about the square root of the unit roundoff, with a
+        // margin for the curvature of f) leaves p at rounding, and the iteration stops there
+        const C tol2 = sizeof(C) == 8 ? C(1e-9) : C(2.5e-5);
         for (int it = 0; it < 24; it++) {
             C dfL, dfR;
             const C f = wave(p, rL, pL, cL, dfL) + wave(p, rR, pR, cR, dfR) + du;
@@ -357,8 +357,7 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
             pn = pn > tiny ? pn : C(0.1) * p;
             const C ch = __builtin_fabs(pn - p) * PR::rcp(pn + p);
             p = pn;
-            if (last) break;
-            last = ch <= tol2;
+            if (ch <= tol2) break;
         }
         C d0, d1;
         const C us = C(0.5) * (uL + uR) + C(0.5) * (wave(p, rR, pR, cR, d1) - wave(p, rL, pL, cL, d0));
