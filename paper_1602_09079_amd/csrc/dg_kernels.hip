@@ -350,17 +350,21 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
         // (relative), so a step below tol2 (about the square root of the unit roundoff, with a
         // margin for the curvature of f) leaves p at rounding, and the iteration stops there
         const C tol2 = sizeof(C) == 8 ? C(1e-9) : C(2.5e-5);
+        C fl = 0, fr = 0, sl = 0, sr = 0, pold = p;  // the last evaluation: f_L, f_R, their slopes, at pold
         for (int it = 0; it < 24; it++) {
             C dfL, dfR;
-            const C f = wave(p, rL, pL, cL, dfL) + wave(p, rR, pR, cR, dfR) + du;
-            C pn = p - f * PR::rcp(dfL + dfR);
+            const C a = wave(p, rL, pL, cL, dfL), b = wave(p, rR, pR, cR, dfR);
+            C pn = p - (a + b + du) * PR::rcp(dfL + dfR);
             pn = pn > tiny ? pn : C(0.1) * p;
             const C ch = __builtin_fabs(pn - p) * PR::rcp(pn + p);
+            fl = a; fr = b; sl = dfL; sr = dfR; pold = p;
             p = pn;
             if (ch <= tol2) break;
         }
-        C d0, d1;
-        const C us = C(0.5) * (uL + uR) + C(0.5) * (wave(p, rR, pR, cR, d1) - wave(p, rL, pL, cL, d0));
+        // u* from f_R(p*) - f_L(p*), each one step of size below tol2 from its last evaluation: the
+        // first-order update is exact to rounding
+        const C dp = p - pold;
+        const C us = C(0.5) * (uL + uR) + C(0.5) * ((fr + sr * dp) - (fl + sl * dp));
         from_left = C(0) <= us;
         const C rK = from_left ? rL : rR, uK = from_left ? uL : uR, pK = from_left ? pL : pR;
         const C cK = from_left ? cL : cR, sg = from_left ? C(-1) : C(1);
