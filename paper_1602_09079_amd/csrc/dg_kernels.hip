@@ -1334,8 +1334,8 @@ __global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
     static_assert(WORK >= NF * 6 * P && N <= 64 && QS_THREADS == 128, "quadrature kernel shape");
     // the mode-parallel contractions split their point (face point) range between the two waves
     constexpr int QH = (Q + 1) / 2, FH = 3 * P;
-    // FP32: unrolled inner loops batch the table loads; FP64: the compiler's own unrolling
-    constexpr int U7 = PREC == DG_FP64 ? 0 : 7, U5 = PREC == DG_FP64 ? 0 : 7, U6 = PREC == DG_FP64 ? 0 : 5;
+    // unrolled inner loops batch the table loads
+    constexpr int U7 = 7, U5 = 7, U6 = 5;
     __shared__ C ys[7][E];  // the cell, then its -x, +x, -y, +y, -z, +z neighbours: [i * N + l]
     __shared__ C work[WORK];
     const C *tab = static_cast<const C *>(a.tables);
