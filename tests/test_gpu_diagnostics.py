@@ -52,7 +52,7 @@ def stored(y, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k,S", [(1, 4), (2, 3), (3, 4), (3, 1), (2, 2)])
+@pytest.mark.parametrize("k,S", [(1, 4), (2, 3), (3, 4), (3, 1), (2, 2), (4, 4), (4, 3)])
 def test_sample_parity(dgm, k, S, prec):
     n = (7, 5, 3)
     cfg, y = state(k, n, 20 + k)
@@ -66,7 +66,7 @@ def test_sample_parity(dgm, k, S, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k,n,S", [(2, 8, 4), (3, 5, 3), (1, 6, 4)])
+@pytest.mark.parametrize("k,n,S", [(2, 8, 4), (3, 5, 3), (1, 6, 4), (4, 5, 4)])
 def test_velocity_spectrum_parity(dgm, k, n, S, prec):
     cfg, y = state(k, n, 30 + k, density=0.2)
     M = S * n

@@ -53,8 +53,8 @@ def hot_state(k, n, seed, mach=0.4):
     return cfg, y
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k,prec", [(k, p) for k in (1, 2, 3) for p in ("fp64", "fp32", "bf16x3")] +
+                         [(4, "fp64"), (4, "fp32")])
 def test_reset_parity(dgm, k, prec):
     n = (19, 5, 4)  # 380 cells: one full block of 256 and a ragged one
     cfg, y = hot_state(k, n, 60 + k)
@@ -122,7 +122,7 @@ def test_reset_errors(dgm):
     assert s.dissipated() == 0.0
 
 
-@pytest.mark.parametrize("prec,k", [("fp64", 1), ("fp64", 3), ("fp32", 2), ("bf16x3", 3)])
+@pytest.mark.parametrize("prec,k", [("fp64", 1), ("fp64", 3), ("fp32", 2), ("bf16x3", 3), ("fp64", 4), ("fp32", 4)])
 def test_paper_workload_parity(dgm, prec, k):
     """The paper's own turbulence set-up at a small size (Sec. 3.1, 3.2): driving on the band
     1 < |n| < 2, gamma = 1.01 with the isothermal reset (cs = 1), the positivity limiter, rms

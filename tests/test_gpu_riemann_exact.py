@@ -78,7 +78,7 @@ def test_rhs_parity_exact(dgm, k, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("k", [1, 3, 4])
 def test_rhs_parity_exact_shock_tube(dgm, k, prec):
     cfg, y = shock_tube(k, 20)
     ys = y if prec == "fp64" else y.astype(np.float32).astype(np.float64)
@@ -88,7 +88,7 @@ def test_rhs_parity_exact_shock_tube(dgm, k, prec):
     assert np.all(err <= TOL_RHS[prec]), err
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_limited_blast_steps_exact(dgm, k):
     n = 32
     cfg = O.make_cfg(k, (n, 2, 2), gamma=G, cfl=0.3, riemann="exact")
