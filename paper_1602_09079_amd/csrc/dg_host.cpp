@@ -850,11 +850,16 @@ dg_status dg_set_forcing(dg_ctx *c, int32_t nmodes, const int32_t *nvec, const d
         c->err = "dg_set_forcing: context was created without DG_FORCING";
         return DG_ERR_STATE;
     }
-    // device mode table per mode: n_x, n_y, n_z (as doubles), then Re/Im of the three components
+    // device mode table per mode: n_x, n_y, n_z (as doubles), then Re/Im of the three components;
+    // sorted by n_x so that the cache kernel forms one x phase per distinct n_x
+    std::vector<int> order(nmodes);
+    for (int m = 0; m < nmodes; m++) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return nvec[3 * p] < nvec[3 * q]; });
     std::vector<double> t((size_t)MAX_FORCING_MODES * 9, 0.0);
-    for (int m = 0; m < nmodes; m++) {
-        for (int a = 0; a < 3; a++) t[9 * m + a] = (double)nvec[3 * m + a];
-        for (int j = 0; j < 6; j++) t[9 * m + 3 + j] = ahat[6 * m + j];
+    for (int j = 0; j < nmodes; j++) {
+        const int m = order[j];
+        for (int a = 0; a < 3; a++) t[9 * j + a] = (double)nvec[3 * m + a];
+        for (int i = 0; i < 6; i++) t[9 * j + 3 + i] = ahat[6 * m + i];
     }
     if (!c->fmodes) HIPCHK(c, hipMalloc(&c->fmodes, t.size() * sizeof(double)));
     if (!c->acache)

@@ -1634,53 +1634,90 @@ hipError_t launch_project(int k, int prec, const void *qp, void *y, const double
 // ------------------------------------------------------------------ driving acceleration cache (Sec. 3.1)
 
 // a_c(x_q) = sum_m Re(ahat_{m,c} exp(2 pi i n_m . x_q / L)) at every volume point of every
-// cell, in the layout the stage kernel reads (see accel_load); the phase is reduced to one
-// turn in FP64 and its sine and cosine taken in FP64.  Rows past the last point are zero.
+// cell, in the layout the stage kernel reads (see accel_load).  One workgroup per (row of cells,
+// y node, z node): the y and z part of each mode's phase is shared by the whole row, so
+// P_{m,c} = ahat_{m,c} exp(2 pi i (n_y Y + n_z Z)) is formed once into LDS; each thread then takes
+// points along x, where the modes (sorted by n_x on the host) need one exp(2 pi i n_x X) per
+// distinct n_x.  Phases are reduced to one turn and their sine and cosine taken in FP64.  Rows of
+// the layout past the last point are zero.
+constexpr int ACC_THREADS = 256;
+
 template <int K, class S>
-__global__ void accel_cache_kernel(const double *__restrict__ modes, int nmodes, int nx, int ny, int nz, long long nc,
-                                   GaussNodes xg, int z0, int nzg, S *__restrict__ out) {
+__global__ __launch_bounds__(ACC_THREADS) void accel_cache_kernel(const double *__restrict__ modes, int nmodes,
+                                                                  int nx, int ny, int nz, GaussNodes xg, int z0,
+                                                                  int nzg, S *__restrict__ out) {
     constexpr int n = K + 1, Q = n * n * n, RT1 = (Q + 15) / 16;
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nc * RT1 * 16) return;
-    const long long cell = id / (RT1 * 16);
-    const int rho = (int)(id - cell * (RT1 * 16));
-    const int t = rho / 16, rr = rho % 16;
     constexpr bool F64 = sizeof(S) == 8;
-    const int g = F64 ? rr % 4 : rr / 4, r = F64 ? rr / 4 : rr % 4;  // result lane group and register of the row
-    const int ix = (int)(cell % nx);
-    const long long slab = cell / nx;
-    const int iy = (int)(slab % ny), iz = (int)(slab / ny);
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (rho < Q) {
-        const int qa = rho % n, qb = (rho / n) % n, qc = rho / (n * n);
-        const double X = (ix + 0.5 * (1.0 + xg.x[qa])) / nx, Y = (iy + 0.5 * (1.0 + xg.x[qb])) / ny,
-                     Z = (z0 + iz + 0.5 * (1.0 + xg.x[qc])) / nzg;
-        for (int m = 0; m < nmodes; m++) {
+    __shared__ double P[MAX_FORCING_MODES][3][2];
+    const long long items = (long long)ny * nz * n * n;
+    const long long aslab = (long long)RT1 * 16 * 3 * nx;
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const long long row = it / (n * n);
+        const int qbc = (int)(it - row * (n * n)), qb = qbc % n, qc = qbc / n;
+        const int iy = (int)(row % ny), iz = (int)(row / ny);
+        const double Y = (iy + 0.5 * (1.0 + xg.x[qb])) / ny, Z = (z0 + iz + 0.5 * (1.0 + xg.x[qc])) / nzg;
+        for (int m = threadIdx.x; m < nmodes; m += ACC_THREADS) {
             const double *md = modes + 9 * m;
-            double ph = md[0] * X + md[1] * Y + md[2] * Z;
+            double ph = md[1] * Y + md[2] * Z;
             ph -= floor(ph);
             double sn, cs;
             sincospi(2.0 * ph, &sn, &cs);
 #pragma unroll
-            for (int c = 0; c < 3; c++) acc[c] += md[3 + 2 * c] * cs - md[4 + 2 * c] * sn;
+            for (int c = 0; c < 3; c++) {
+                const double re = md[3 + 2 * c], im = md[4 + 2 * c];
+                P[m][c][0] = re * cs - im * sn;
+                P[m][c][1] = re * sn + im * cs;
+            }
         }
-    }
-    const long long aslab = (long long)RT1 * 16 * 3 * nx;
+        __syncthreads();
+        S *orow = out + row * aslab;
+        for (int j = threadIdx.x; j < n * nx; j += ACC_THREADS) {
+            const int qa = j / nx, ix = j - qa * nx;  // consecutive threads: consecutive cells
+            const double X = (ix + 0.5 * (1.0 + xg.x[qa])) / nx;
+            double acc[3] = {0.0, 0.0, 0.0};
+            double er = 1.0, ei = 0.0, nprev = 0.0;
+            for (int m = 0; m < nmodes; m++) {
+                const double n0 = modes[9 * m];
+                if (m == 0 || n0 != nprev) {
+                    double ph = n0 * X;
+                    ph -= floor(ph);
+                    sincospi(2.0 * ph, &ei, &er);
+                    nprev = n0;
+                }
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[slab * aslab + (((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r] = (S)acc[c];
+                for (int c = 0; c < 3; c++) acc[c] += P[m][c][0] * er - P[m][c][1] * ei;
+            }
+            const int rho = qa + n * qb + n * n * qc;
+            const int t = rho / 16, rr = rho % 16;
+            const int g = F64 ? rr % 4 : rr / 4, r = F64 ? rr / 4 : rr % 4;  // result lane group and register
+#pragma unroll
+            for (int c = 0; c < 3; c++) orow[(((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r] = (S)acc[c];
+        }
+        if (qbc == 0 && RT1 * 16 > Q) {  // the padding rows of the last tile
+            for (int j = threadIdx.x; j < (RT1 * 16 - Q) * nx; j += ACC_THREADS) {
+                const int rho = Q + j / nx, ix = j % nx;
+                const int t = rho / 16, rr = rho % 16;
+                const int g = F64 ? rr % 4 : rr / 4, r = F64 ? rr / 4 : rr % 4;
+#pragma unroll
+                for (int c = 0; c < 3; c++) orow[(((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r] = S(0);
+            }
+        }
+        __syncthreads();  // P is rewritten for the next item
+    }
 }
 
 template <int K>
 static hipError_t launch_accel_k(int prec, const double *modes, int nmodes, int nx, int ny, int nz, long long nc,
                                  const GaussNodes &xg, int z0, int nzg, void *out, hipStream_t s) {
-    constexpr int Q = (K + 1) * (K + 1) * (K + 1), RT1 = (Q + 15) / 16;
-    const long long nb = (nc * RT1 * 16 + 255) / 256;
+    (void)nc;
+    const long long items = (long long)ny * nz * (K + 1) * (K + 1);
+    const long long nb = items < (1LL << 30) ? items : (1LL << 30);
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((accel_cache_kernel<K, double>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
-                           z0, nzg, (double *)out);
+        hipLaunchKernelGGL((accel_cache_kernel<K, double>), dim3(nb), dim3(ACC_THREADS), 0, s, modes, nmodes, nx, ny,
+                           nz, xg, z0, nzg, (double *)out);
     else
-        hipLaunchKernelGGL((accel_cache_kernel<K, float>), dim3(nb), dim3(256), 0, s, modes, nmodes, nx, ny, nz, nc, xg,
-                           z0, nzg, (float *)out);
+        hipLaunchKernelGGL((accel_cache_kernel<K, float>), dim3(nb), dim3(ACC_THREADS), 0, s, modes, nmodes, nx, ny,
+                           nz, xg, z0, nzg, (float *)out);
     return hipGetLastError();
 }
 
