@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6   # MI355X vector FP64
 FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32
+FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 matrix cores
 
 
 def parse():
@@ -273,6 +274,57 @@ def k4_cost(args, dg, torch):
     return out
 
 
+CLOSURE_SHAPE = (140, 128, 128, 20)
+CLOSURE_FLOPS_PER_CELL = 2 * (140 * 128 + 128 * 128 + 128 * 20)  # the three dense layers
+
+
+def closure_cost(args, dg, torch):
+    """The learned closure's inference in the stage (k = 1 on 64^3, FP32, driving on; random
+    Xavier weights of the 140-128-128-20 network, no cell falling back): stage 1 with and
+    without it; the difference is the closure's cost, against the FP32 matrix-core peak."""
+    import numpy as np
+
+    from paper_1602_09079_amd import synth
+    k, n = 1, 64
+    qp = synth.turbulence(n, dg.gauss_nodes(k + 1), seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
+    nvec, ahat, _ = driving_table(dg)
+    out = dict(k=k, n=n, tier="fp32", flops_per_cell=CLOSURE_FLOPS_PER_CELL)
+    for name, closure in (("plain", False), ("closure", True)):
+        s = dg.Solver(k, n, precision="fp32", cfl=0.3, forcing=True, closure=closure)
+        s.set_forcing(nvec, ahat)
+        if closure:
+            p = synth.xavier_params(CLOSURE_SHAPE, seed=4)
+            s.set_closure(p, np.zeros(140), np.ones(140), np.full(20, 1e-3), np.full(20, 1e30))
+        y = s.project(qp)
+        w1 = torch.empty_like(y)
+        h = s.dt(y)
+        s.stage(y, y, w1, 0.0, 1.0, h)
+        torch.cuda.synchronize()
+        reps = max(10, 4 * args.steps)
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record(s.stream)
+        for _ in range(reps):
+            s.stage(y, y, w1, 0.0, 1.0, h)
+        eb.record(s.stream)
+        torch.cuda.synchronize()
+        out[f"stage1_ms_{name}"] = ea.elapsed_time(eb) / reps
+        if closure:
+            out["fallbacks"] = s.closure_fallbacks()
+        del s, y, w1
+        torch.cuda.empty_cache()
+    d = out["stage1_ms_closure"] - out["stage1_ms_plain"]
+    out["closure_ms"] = d
+    tf = CLOSURE_FLOPS_PER_CELL * n ** 3 / (d / 1e3) / 1e12 if d > 0 else None
+    out["closure_TFLOPs"] = tf
+    out["closure_frac_of_fp32_matrix_peak"] = tf / FP32_MATRIX_TFLOPS if tf else None
+    log(args, f"[bench] closure inference k=1 {n}^3: stage 1 {out['stage1_ms_plain']:.3f} ms plain, "
+              f"{out['stage1_ms_closure']:.3f} ms with the closure")
+    del qp
+    torch.cuda.empty_cache()
+    return out
+
+
 def limiter_cost(args, dg, torch, prec, qp_dev, n, k):
     """Stage launches of the primary tier with the positivity limiter of Sec. 2.5 on the
     stage input (the paper applies it every stage; the smooth workload never needs it, so this
@@ -433,6 +485,7 @@ def main():
     ers = None if args.no_limiter else exact_riemann_cost(args, dg, torch, prim0, qp, n, k)
     shr = None if args.no_limiter else share_cost(args, dg, torch, prim0, qp, n, k)
     k4 = None if (args.no_limiter or args.k4_n <= 0 or k == 4) else k4_cost(args, dg, torch)
+    clo = None if args.no_limiter else closure_cost(args, dg, torch)
     del qp
     torch.cuda.empty_cache()
     # the box's own copy bandwidth (2 GiB device-to-device, read + write bytes), the second roof
@@ -517,6 +570,8 @@ def main():
         line["z_slab_share"] = dict(shr, whole_stage1_ms=results[shr["tier"]]["stage_ms_each"][0])
     if k4 is not None:
         line["k4_stage"] = k4
+    if clo is not None:
+        line["closure_inference"] = clo
     print(json.dumps(line), flush=True)
 
 
