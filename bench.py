@@ -274,6 +274,45 @@ def k4_cost(args, dg, torch):
     return out
 
 
+def k0_cost(args, dg, torch):
+    """Stage launches at k = 0 (first-order finite volume, one thread per cell) in FP64 and FP32
+    on the benchmark's 256^3 mesh with the same recipe; HBM roof: stage 1 reads and writes one
+    state, 2 x 5 values per cell."""
+    from paper_1602_09079_amd import synth
+    k, n = 0, args.n
+    qp = synth.turbulence(n, dg.gauss_nodes(1), seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
+    nvec, ahat, _ = driving_table(dg)
+    out = dict(n=n, k=k)
+    for prec in ("fp64", "fp32"):
+        s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing)
+        if not args.no_forcing:
+            s.set_forcing(nvec, ahat)
+        y = s.project(qp.to(s.dtype))
+        w1 = torch.empty_like(y)
+        h = s.dt(y)
+        s.stage(y, y, w1, 0.0, 1.0, h)
+        torch.cuda.synchronize()
+        reps = max(10, 4 * args.steps)
+        ea = torch.cuda.Event(enable_timing=True)
+        eb = torch.cuda.Event(enable_timing=True)
+        ea.record(s.stream)
+        for _ in range(reps):
+            s.stage(y, y, w1, 0.0, 1.0, h)
+        eb.record(s.stream)
+        torch.cuda.synchronize()
+        ms = ea.elapsed_time(eb) / reps
+        elem = 8 if prec == "fp64" else 4
+        gbs = 2 * 5 * n ** 3 * elem / (ms / 1e3) / 1e9
+        out[prec] = dict(stage_ms=ms, dof_updates_per_s=5 * n ** 3 / (ms / 1e3), algorithmic_GBs=round(gbs, 1),
+                         hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        log(args, f"[bench] k=0 {prec} stage 1 on {n}^3: {ms:.3f} ms, {gbs:.0f} GB/s algorithmic")
+        del s, y, w1
+        torch.cuda.empty_cache()
+    del qp
+    torch.cuda.empty_cache()
+    return out
+
+
 CLOSURE_SHAPE = (140, 128, 128, 20)
 CLOSURE_FLOPS_PER_CELL = 2 * (140 * 128 + 128 * 128 + 128 * 20)  # the three dense layers
 
@@ -486,6 +525,7 @@ def main():
     shr = None if args.no_limiter else share_cost(args, dg, torch, prim0, qp, n, k)
     k4 = None if (args.no_limiter or args.k4_n <= 0 or k == 4) else k4_cost(args, dg, torch)
     clo = None if args.no_limiter else closure_cost(args, dg, torch)
+    k0 = None if (args.no_limiter or k == 0) else k0_cost(args, dg, torch)
     del qp
     torch.cuda.empty_cache()
     # the box's own copy bandwidth (2 GiB device-to-device, read + write bytes), the second roof
@@ -572,6 +612,8 @@ def main():
         line["k4_stage"] = k4
     if clo is not None:
         line["closure_inference"] = clo
+    if k0 is not None:
+        line["k0_stage"] = k0
     print(json.dumps(line), flush=True)
 
 

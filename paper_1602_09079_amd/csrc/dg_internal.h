@@ -93,6 +93,7 @@ struct GaussNodes {
 };
 // elements of the driving acceleration cache per (z, y) row of cells: 3 components x 16 ceil(Q/16) points x nx
 inline long long accel_slab_elems(int k, int nx) {
+    if (k == 0) return 3LL * nx;  // k = 0: [component][x], the cell centre only
     const int Q = (k + 1) * (k + 1) * (k + 1);
     return (long long)((Q + 15) / 16) * 16 * 3 * nx;
 }

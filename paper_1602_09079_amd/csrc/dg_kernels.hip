@@ -1249,12 +1249,12 @@ __global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
     axis_term(std::integral_constant<int, 1>{}, 0, 1, 0);
     axis_term(std::integral_constant<int, 2>{}, 0, 0, 1);
     if constexpr (FORCE) {
-        // the driving acceleration at the cell centre, from the k = 0 cache layout (point 0 of tile 0)
-        const S *ac = static_cast<const S *>(a.acache) + row * (16LL * 3 * nx) + (long long)ix * 4;
+        // the driving acceleration at the cell centre, from the k = 0 cache layout [component][x]
+        const S *ac = static_cast<const S *>(a.acache) + row * (3LL * nx) + ix;
         C sE = 0;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            const C av = (C)ac[(long long)c * 16 * nx];
+            const C av = (C)ac[(long long)c * nx];
             R[1 + c] -= q[0] * av;
             sE += q[1 + c] * av;
         }
@@ -1639,7 +1639,8 @@ hipError_t launch_project(int k, int prec, const void *qp, void *y, const double
 // P_{m,c} = ahat_{m,c} exp(2 pi i (n_y Y + n_z Z)) is formed once into LDS; each thread then takes
 // points along x, where the modes (sorted by n_x on the host) need one exp(2 pi i n_x X) per
 // distinct n_x.  Phases are reduced to one turn and their sine and cosine taken in FP64.  Rows of
-// the layout past the last point are zero.
+// the layout past the last point are zero.  k = 0 (the finite-volume kernel) takes a compact
+// layout instead: per row of cells [component][x], the cell centre only.
 constexpr int ACC_THREADS = 256;
 
 template <int K, class S>
@@ -1650,7 +1651,7 @@ __global__ __launch_bounds__(ACC_THREADS) void accel_cache_kernel(const double *
     constexpr bool F64 = sizeof(S) == 8;
     __shared__ double P[MAX_FORCING_MODES][3][2];
     const long long items = (long long)ny * nz * n * n;
-    const long long aslab = (long long)RT1 * 16 * 3 * nx;
+    const long long aslab = K == 0 ? 3LL * nx : (long long)RT1 * 16 * 3 * nx;
     for (long long it = blockIdx.x; it < items; it += gridDim.x) {
         const long long row = it / (n * n);
         const int qbc = (int)(it - row * (n * n)), qb = qbc % n, qc = qbc / n;
@@ -1687,13 +1688,18 @@ __global__ __launch_bounds__(ACC_THREADS) void accel_cache_kernel(const double *
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[c] += P[m][c][0] * er - P[m][c][1] * ei;
             }
+            if constexpr (K == 0) {  // the finite-volume kernel's compact layout [component][x]
+#pragma unroll
+                for (int c = 0; c < 3; c++) orow[(long long)c * nx + ix] = (S)acc[c];
+                continue;
+            }
             const int rho = qa + n * qb + n * n * qc;
             const int t = rho / 16, rr = rho % 16;
             const int g = F64 ? rr % 4 : rr / 4, r = F64 ? rr / 4 : rr % 4;  // result lane group and register
 #pragma unroll
             for (int c = 0; c < 3; c++) orow[(((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r] = (S)acc[c];
         }
-        if (qbc == 0 && RT1 * 16 > Q) {  // the padding rows of the last tile
+        if (K > 0 && qbc == 0 && RT1 * 16 > Q) {  // the padding rows of the last tile
             for (int j = threadIdx.x; j < (RT1 * 16 - Q) * nx; j += ACC_THREADS) {
                 const int rho = Q + j / nx, ix = j % nx;
                 const int t = rho / 16, rr = rho % 16;
