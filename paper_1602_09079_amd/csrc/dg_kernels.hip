@@ -1188,24 +1188,31 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
 
 // k = 0: one weight per field, and the scheme is first-order Godunov finite volume:
 // R = sum_a (Fhat(q, q_{+a}) - Fhat(q_{-a}, q)) / h_a minus the source at the cell centre (the
-// single Gauss point).  One thread per cell; the six neighbours' weights are read directly (each
-// face is solved by both of its cells), no products, no LDS.
-constexpr int FV_THREADS = 256;
+// single Gauss point).  One thread per cell, workgroups of 64 x 4 cells in x and y: each cell
+// solves its +x and +y faces and shares them through LDS with the cell that needs them as its -x
+// or -y face (the same inputs and arithmetic, so the same bits as solving it there); faces on the
+// tile's low edges and the z faces are solved by both of their cells.  No products.
+constexpr int FV_TX = 64, FV_TY = 4, FV_THREADS = FV_TX * FV_TY;
 
 template <int PREC, bool FORCE, int RS>
 __global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
     using PR = Prec<PREC>;
     using S = typename PR::S;
     using C = typename PR::C;
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ C fx[FV_TY][FV_TX][NF], fy[FV_TY][FV_TX][NF];  // each cell's +x and +y face fluxes
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int tx = threadIdx.x % FV_TX, ty = threadIdx.x / FV_TX;
+    const int ntx = (nx + FV_TX - 1) / FV_TX, nty = (ny + FV_TY - 1) / FV_TY;
+    const long long bid = blockIdx.x;
+    const int bx = (int)(bid % ntx);
+    const long long bzy = bid / ntx;
+    const int by = (int)(bzy % nty), iz = (int)(bzy / nty);
+    const int ix = bx * FV_TX + tx, iy = by * FV_TY + ty;
+    const bool act = ix < nx && iy < ny;
     double dtd = a.dt;
     if (a.rate) dtd = a.dtfac / a.rate[0];
     if (a.tacc && blockIdx.x == 0 && threadIdx.x == 0) a.tacc[0] += dtd;
-    if (cell >= a.ncells) return;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int ix = (int)(cell % nx);
-    const long long row = cell / nx;
-    const int iy = (int)(row % ny), iz = (int)(row / ny);
+    const long long row = (long long)iz * ny + iy;
     const S *yin = static_cast<const S *>(a.yin);
     auto load = [&](int x, int yy, int zz, C q[5]) {
         x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
@@ -1232,22 +1239,60 @@ __global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
         else
             hllc<PR, AX>(qL, qR, gam, F);
     };
-    C q[5], R[5] = {0, 0, 0, 0, 0};
-    load(ix, iy, iz, q);
-    auto axis_term = [&](auto axis_c, int dx, int dy, int dz) {
-        constexpr int AX = decltype(axis_c)::value;
+    C q[5] = {1, 0, 0, 0, 1}, R[5] = {0, 0, 0, 0, 0};
+    C Fpx[5], Fpy[5];
+    if (act) {
+        load(ix, iy, iz, q);
+        C qn[5];
+        load(ix + 1, iy, iz, qn);
+        flux(std::integral_constant<int, 0>{}, q, qn, Fpx);
+        load(ix, iy + 1, iz, qn);
+        flux(std::integral_constant<int, 1>{}, q, qn, Fpy);
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            fx[ty][tx][i] = Fpx[i];
+            fy[ty][tx][i] = Fpy[i];
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    C Fmx[5], Fmy[5];
+    if (tx > 0) {  // the -x neighbour is the thread to the left (same row, ix - 1 >= 0)
+#pragma unroll
+        for (int i = 0; i < NF; i++) Fmx[i] = fx[ty][tx - 1][i];
+    } else {
+        C qm[5];
+        load(ix - 1, iy, iz, qm);
+        flux(std::integral_constant<int, 0>{}, qm, q, Fmx);
+    }
+    if (ty > 0) {  // the -y neighbour is the thread below (iy - 1 >= 0)
+#pragma unroll
+        for (int i = 0; i < NF; i++) Fmy[i] = fy[ty - 1][tx][i];
+    } else {
+        C qm[5];
+        load(ix, iy - 1, iz, qm);
+        flux(std::integral_constant<int, 1>{}, qm, q, Fmy);
+    }
+    {
+        const C ih = (C)(1.0 / a.h[0]);
+#pragma unroll
+        for (int i = 0; i < NF; i++) R[i] += (Fpx[i] - Fmx[i]) * ih;
+    }
+    {
+        const C ih = (C)(1.0 / a.h[1]);
+#pragma unroll
+        for (int i = 0; i < NF; i++) R[i] += (Fpy[i] - Fmy[i]) * ih;
+    }
+    {
         C qm[5], qp[5], Fm[5], Fp[5];
-        load(ix - dx, iy - dy, iz - dz, qm);
-        load(ix + dx, iy + dy, iz + dz, qp);
-        flux(axis_c, qm, q, Fm);
-        flux(axis_c, q, qp, Fp);
-        const C ih = (C)(1.0 / a.h[AX]);
+        load(ix, iy, iz - 1, qm);
+        load(ix, iy, iz + 1, qp);
+        flux(std::integral_constant<int, 2>{}, qm, q, Fm);
+        flux(std::integral_constant<int, 2>{}, q, qp, Fp);
+        const C ih = (C)(1.0 / a.h[2]);
 #pragma unroll
         for (int i = 0; i < NF; i++) R[i] += (Fp[i] - Fm[i]) * ih;
-    };
-    axis_term(std::integral_constant<int, 0>{}, 1, 0, 0);
-    axis_term(std::integral_constant<int, 1>{}, 0, 1, 0);
-    axis_term(std::integral_constant<int, 2>{}, 0, 0, 1);
+    }
     if constexpr (FORCE) {
         // the driving acceleration at the cell centre, from the k = 0 cache layout [component][x]
         const S *ac = static_cast<const S *>(a.acache) + row * (3LL * nx) + ix;
@@ -1278,7 +1323,7 @@ __global__ __launch_bounds__(FV_THREADS) void fv_stage_kernel(StageArgs a) {
 
 template <int PREC>
 static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
-    const long long nb = (a.ncells + FV_THREADS - 1) / FV_THREADS;
+    const long long nb = (long long)((a.nx + FV_TX - 1) / FV_TX) * ((a.ny + FV_TY - 1) / FV_TY) * a.nz;
     if (a.riemann == 1) {
         if (a.forcing) hipLaunchKernelGGL((fv_stage_kernel<PREC, true, 1>), dim3(nb), dim3(FV_THREADS), 0, s, a);
         else hipLaunchKernelGGL((fv_stage_kernel<PREC, false, 1>), dim3(nb), dim3(FV_THREADS), 0, s, a);
