@@ -33,9 +33,11 @@ class Forcing(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # DG_ORACLE_LIB: an instrumented build of the same source (the sanitizer test uses it)
+        path = os.environ.get("DG_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         src = os.path.join(_HERE, "dg_oracle.c")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        if "DG_ORACLE_LIB" not in os.environ and (
+                not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src)):
             _build.build()
         L = ctypes.CDLL(path)
         L.orc_nmodes.restype = ctypes.c_int

@@ -142,6 +142,121 @@ def test_hllc_rotation_and_mirror_symmetry():
         np.testing.assert_allclose(Fm, want, rtol=1e-12, atol=1e-13)
 
 
+def _prim(q, axis, g=G):
+    rho = q[0]
+    v = q[1:4] / rho
+    p = (g - 1) * (q[4] - 0.5 * rho * v.dot(v))
+    return rho, v, p, v[axis], math.sqrt(g * p / rho)
+
+
+def _subsonic_pairs(rng, count):
+    """Random subsonic left/right states: |u| well below c on both sides, so S_L < 0 < S_R."""
+    out = []
+    while len(out) < count:
+        qL = cons(rng.uniform(0.3, 2.5), rng.uniform(-0.6, 0.6, 3), rng.uniform(0.3, 2.5))
+        qR = cons(rng.uniform(0.3, 2.5), rng.uniform(-0.6, 0.6, 3), rng.uniform(0.3, 2.5))
+        out.append((qL, qR))
+    return out
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_hllc_star_region_defining_conditions(axis):
+    """The star-region flux of HLLC (Sec. 2.3 names HLLC as the numerical flux; Toro, Riemann
+    Solvers and Numerical Methods for Fluid Dynamics, ch. 10) checked against the conditions
+    that define it, not against its formula.  From the oracle's flux F, the star state of the
+    upwind side K follows from the Rankine-Hugoniot condition across the S_K wave:
+    U*_K = U_K + (F - F_K) / S_K.  HLLC's star region then has
+      - one normal velocity S* = m*_n / rho* that also carries the mass flux, F_rho = rho* S*;
+      - the tangential velocities of side K;
+      - one pressure p* = F_n - rho* S*^2 on both sides of the contact, equal to
+        p_K + rho_K (S_K - u_K)(S* - u_K) for K = L and for K = R;
+      - the flux of a state moving with S* under pressure p*:
+        F = (rho* S*, rho* S* v* + p* n, S* (E* + p*));
+    and with the other side's star state built from the same conditions, the integral form
+    (S* - S_L) U*_L + (S_R - S*) U*_R = S_R U_R - S_L U_L - (F_R - F_L) holds.
+    Subsonic pairs (S_L < 0 < S_R) with S* != u_K on both branches (S* >= 0: left star,
+    S* < 0: right star); Davis wave speeds as in the reading of Sec. 2.3."""
+    rng = np.random.default_rng(300 + axis)
+    tang = [j for j in range(3) if j != axis]
+    branches = set()
+    for qL, qR in _subsonic_pairs(rng, 60):
+        rl, vl, pl, ul, cl = _prim(qL, axis)
+        rr, vr, pr, ur, cr = _prim(qR, axis)
+        SL, SR = min(ul - cl, ur - cr), max(ul + cl, ur + cr)
+        assert SL < 0 < SR
+        F = O.hllc(qL, qR, axis, G)
+        FL, FR = O.euler_flux(qL, axis, G), O.euler_flux(qR, axis, G)
+        # which star state the flux belongs to: try the left one, else the right one
+        UsL = qL + (F - FL) / SL
+        UsR = qR + (F - FR) / SR
+        left = abs(F[0] / UsL[0] - UsL[1 + axis] / UsL[0]) < 1e-9
+        K = "L" if left else "R"
+        q, Us, SK, uK, pK, rK, vK = (qL, UsL, SL, ul, pl, rl, vl) if left else (qR, UsR, SR, ur, pr, rr, vr)
+        rs = Us[0]
+        assert rs > 0
+        Ss = Us[1 + axis] / rs
+        branches.add((K, Ss >= 0))
+        assert (Ss >= 0) == left, "the upwind star state is the one on the side of the contact at the face"
+        assert SL < Ss < SR
+        assert abs(Ss - uK) > 1e-3, "the case must exercise S* != u_K"
+        # mass flux carried by the contact velocity
+        assert F[0] == pytest.approx(rs * Ss, rel=1e-12, abs=1e-13)
+        # tangential velocities of side K, and their momentum fluxes
+        for j in tang:
+            assert Us[1 + j] / rs == pytest.approx(vK[j], rel=1e-12, abs=1e-13)
+            assert F[1 + j] == pytest.approx(rs * Ss * vK[j], rel=1e-12, abs=1e-13)
+        # one pressure across the contact: p* from the flux, and the HLLC pressure of both sides
+        ps = F[1 + axis] - rs * Ss * Ss
+        assert ps == pytest.approx(pl + rl * (SL - ul) * (Ss - ul), rel=1e-11)
+        assert ps == pytest.approx(pr + rr * (SR - ur) * (Ss - ur), rel=1e-11)
+        # energy flux of the star state
+        assert F[4] == pytest.approx(Ss * (Us[4] + ps), rel=1e-11, abs=1e-12)
+        # the other side's star state from the same conditions (mass and energy Rankine-Hugoniot
+        # across its outer wave, velocity S*, its own tangential velocities, pressure p*)
+        qo, So, Fo, vo = (qR, SR, FR, vr) if left else (qL, SL, FL, vl)
+        ro = qo[0] * (So - Fo[0] / qo[0]) / (So - Ss)
+        Uo = np.zeros(5)
+        Uo[0] = ro
+        Uo[1 + axis] = ro * Ss
+        for j in tang:
+            Uo[1 + j] = ro * vo[j]
+        Uo[4] = (So * qo[4] - Fo[4] + Ss * ps) / (So - Ss)
+        UL, UR = (Us, Uo) if left else (Uo, Us)
+        lhs = (Ss - SL) * UL + (SR - Ss) * UR
+        rhs = SR * qR - SL * qL - (FR - FL)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-12)
+    assert branches == {("L", True), ("R", False)}, branches
+
+
+def test_k0_is_first_order_godunov_fv():
+    """k = 0 (one weight per field, Table 1): the volume term vanishes (the basis gradient is
+    zero) and the surface term of eq. dg:eqn:surface_int reduces to the first-order Godunov
+    finite-volume update R_K = sum_a (F(q_K, q_{K+a}) - F(q_{K-a}, q_K)) / h_a with the
+    numerical flux of Sec. 2.3 at the face.  Built here cell by cell from the oracle's
+    pointwise HLLC on a random positive state of an anisotropic mesh."""
+    nc = (5, 4, 3)
+    box = (1.0, 0.8, 1.5)
+    cfg = O.make_cfg(0, nc, box=box)
+    rng = np.random.default_rng(77)
+    y = np.zeros((5, 1, nc[2], nc[1], nc[0]))
+    for iz, iy, ix in itertools.product(range(nc[2]), range(nc[1]), range(nc[0])):
+        y[:, 0, iz, iy, ix] = rand_state(rng)
+    r = O.rhs(cfg, y)
+    h = [box[a] / nc[a] for a in range(3)]
+    want = np.zeros_like(y)
+    for iz, iy, ix in itertools.product(range(nc[2]), range(nc[1]), range(nc[0])):
+        q = y[:, 0, iz, iy, ix]
+        acc = np.zeros(5)
+        for a in range(3):
+            d = [0, 0, 0]
+            d[a] = 1
+            up = y[:, 0, (iz + d[2]) % nc[2], (iy + d[1]) % nc[1], (ix + d[0]) % nc[0]]
+            dn = y[:, 0, (iz - d[2]) % nc[2], (iy - d[1]) % nc[1], (ix - d[0]) % nc[0]]
+            acc += (O.hllc(q, up, a, G) - O.hllc(dn, q, a, G)) / h[a]
+        want[:, 0, iz, iy, ix] = acc
+    np.testing.assert_allclose(r, want, rtol=1e-12, atol=1e-12)
+
+
 # ------------------------------------------------------------------ operator
 
 def turb_state(k, nc, seed=9079, mach=0.3):
