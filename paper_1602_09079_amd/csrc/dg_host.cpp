@@ -244,6 +244,71 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     return blob;
 }
 
+// Tables of the k = 3 BF16-tier stage kernel (stage_k3.hip), in its fragment order (K3_T1 ..
+// K3_T4, 1 KiB each): lane L feeds row L % 16 and contraction indices 8 (L / 16) + j, j = 0..7.
+// Products with the weights: index 8g + s is the mode of slot s of lane group g (k3_slot_mode),
+// s < 5; mode 0 (the mean, added apart) and indices 8g + 5..7 are zero.  Products over points:
+// index 8g + j is the result register j % 4 of lane group g of the preceding product, i.e. point
+// 4g + j % 4 of the node (volume) or face, and j / 4 selects the first or second table of the
+// chunk (x / y derivative; z derivative / source; - face / + face).  Result row 4g' + r' of row
+// tile rt is slot 4 rt + r' of lane group g' (row tile 1: r' = 0 only).
+std::vector<char> build_tables_k3(int prec, const double s[3]) {
+    const Basis B(3);
+    std::vector<double> t((size_t)K3_NFRAG * 64 * 8, 0.0);
+    auto at = [&](int frag, int lane, int j) -> double & { return t[((size_t)frag * 64 + lane) * 8 + j]; };
+    auto rowmode = [](int rt, int row) {
+        const int gg = row / 4, rr = row % 4;
+        return rt == 0 ? k3_slot_mode(gg, rr) : (rr == 0 ? k3_slot_mode(gg, 4) : -1);
+    };
+    double xi[3];
+    for (int lane = 0; lane < 64; lane++) {
+        const int row = lane % 16, g = lane / 16;
+        for (int j = 0; j < 8; j++) {
+            const int m = j < 5 ? k3_slot_mode(g, j) : -1;
+            const int pnt = 4 * g + (j % 4), half = j / 4;
+            for (int tn = 0; tn < 4; tn++) {
+                if (m > 0) {  // T1: phi at the node's volume points
+                    B.point(16 * tn + row, xi);
+                    at(K3_T1 + tn, lane, j) = B.phi(m, xi);
+                }
+                const int q = 16 * tn + pnt;
+                B.point(q, xi);
+                const int ma = rowmode(0, row);  // T2A: x and y derivatives, first row tile
+                at(K3_T2A + tn, lane, j) = -s[half] * B.dphi(ma, half, xi) * B.weight(q);
+                for (int rt = 0; rt < 2; rt++) {  // T2B: z derivative, then the source
+                    const int mb = rowmode(rt, row);
+                    if (mb < 0) continue;
+                    at(K3_T2B + 2 * tn + rt, lane, j) =
+                        half == 0 ? -s[2] * B.dphi(mb, 2, xi) * B.weight(q) : -B.phi(mb, xi) * B.weight(q) / 8.0;
+                }
+            }
+            for (int f = 0; f < 6; f++)  // T3: phi at the face's points
+                if (m > 0) {
+                    B.face_point(f, row, xi);
+                    at(K3_T3 + f, lane, j) = B.phi(m, xi);
+                }
+            for (int ax = 0; ax < 3; ax++)  // T4: lift with the outward sign, - face then + face
+                for (int rt = 0; rt < 2; rt++) {
+                    const int mb = rowmode(rt, row);
+                    if (mb < 0) continue;
+                    const int f = 2 * ax + half;
+                    B.face_point(f, pnt, xi);
+                    at(K3_T4 + 2 * ax + rt, lane, j) = s[ax] * (half ? 1.0 : -1.0) * B.phi(mb, xi) * B.face_weight(pnt);
+                }
+        }
+    }
+    const int ntab = prec == DG_BF16X3 ? 2 : 1;
+    std::vector<char> blob((size_t)K3_SET * ntab, 0);
+    uint16_t *hi = reinterpret_cast<uint16_t *>(blob.data());
+    uint16_t *lo = reinterpret_cast<uint16_t *>(blob.data() + K3_SET);
+    for (size_t i = 0; i < t.size(); i++) {
+        const uint16_t h = bf16_rne((float)t[i]);
+        hi[i] = h;
+        if (ntab == 2) lo[i] = bf16_rne((float)(t[i] - (double)bf16_to_float(h)));
+    }
+    return blob;
+}
+
 // Tables of the quadrature-form stage kernel (k = 4), in the storage precision, in the kernel's
 // order: phi [l][q], grad [q][d][l] = s_d w_q dphi_l/dxi_d, src [q][l] = w_q phi_l / 8,
 // trace [f][l][p], lift [f][p][l] = (+/-) s_d w_p phi_l (+ on the + face of axis d = f / 2).
@@ -431,10 +496,15 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         dg_destroy(c);
         return st;
     };
+    // k = 3 in the BF16-product tiers: the kernel of stage_k3.hip
+    c->k3x = cfg->k == 3 && (cfg->precision == DG_BF16 || cfg->precision == DG_BF16X3);
     if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
         std::vector<char> blob;
         if (cfg->k == 4) {
             blob = build_quad_tables(cfg->k, cfg->precision, s);
+        } else if (c->k3x) {
+            c->lay = make_layout(cfg->k, cfg->precision);
+            blob = build_tables_k3(cfg->precision, s);
         } else {
             c->lay = make_layout(cfg->k, cfg->precision);
             blob = build_tables(c->lay, s);
@@ -507,7 +577,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             return fail(DG_ERR_HIP);
         // separate y-face trace and flux regions when both fit, else one shared region
         const int exb = (int)stage_exchange_bytes(cfg->precision);
-        c->ex_off = (int)c->lay.bytes();
+        c->ex_off = c->k3x ? K3_SET * (cfg->precision == DG_BF16X3 ? 2 : 1) : (int)c->lay.bytes();
         c->ex_off2 = c->ex_off + exb;
         c->lds = c->ex_off + 2 * exb;
         if (c->lds > maxlds) {
@@ -515,22 +585,28 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             c->lds = c->ex_off + exb;
         }
         if (c->lds > maxlds) return fail(DG_ERR_UNSUPPORTED);
+        if (c->k3x && c->ex_off2 == c->ex_off) return fail(DG_ERR_UNSUPPORTED);  // it needs both regions
         const int erb = (int)stage_endrow_bytes(cfg->precision, cfg->k);
         if (erb > 0 && c->lds + erb <= maxlds) {
             c->ex_off3 = c->lds;
             c->lds += erb;
         }
     }
-    if (set_stage_attributes(cfg->k, cfg->precision, c->lds) != hipSuccess) return fail(DG_ERR_HIP);
+    if ((c->k3x ? set_stage_k3_attributes(cfg->precision, c->lds)
+                : set_stage_attributes(cfg->k, cfg->precision, c->lds)) != hipSuccess)
+        return fail(DG_ERR_HIP);
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return fail(DG_ERR_HIP);
-    if (stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    if ((c->k3x ? stage_k3_occupancy(cfg->precision, c->lds, &per_cu)
+                : stage_occupancy(cfg->k, cfg->precision, c->lds, &per_cu)) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
     // z chunk length: the resident item slots take the items in rounds, and an item costs its
     // planes plus about one plane of start-up (the -z face of its first plane, the look-ahead
     // that is not yet overlapped); pick the length (at most 32) that minimises
     // rounds x (length + 1), the longer one on ties
-    const long long nbx = (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
+    const long long nbx = c->k3x ? (cfg->n[0] + K3_BLK - 1) / K3_BLK : (cfg->n[0] + BLK_INNER - 1) / BLK_INNER;
     const int rows = stage_rows_per_item(cfg->precision);
     const int items_per_wg = rows == 1 ? stage_block_threads(cfg->precision) / 64 : 1;  // one item per wave or per workgroup
     const long long nyg = (cfg->n[1] + rows - 1) / rows;
@@ -565,6 +641,8 @@ dg_status dg_destroy(dg_ctx *c) {
                     c->restrict_tab[2], c->restrict_tab[3]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);  // release what was allocated; a failure here has no remedy
+    if (c->dtab) (void)hipFree(c->dtab);
+    if (c->dcs) (void)hipFree(c->dcs);
     if (c->diag_bins) (void)hipFree(c->diag_bins);
     if (c->diag_partials) (void)hipFree(c->diag_partials);
     if (c->fft) (void)hipfftDestroy(static_cast<hipfftHandle>(c->fft));
@@ -643,7 +721,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.nx = c->cfg.n[0];
     s.ny = c->cfg.n[1];
     s.nz = c->cfg.n[2];
-    s.nbx = (c->cfg.n[0] + BLK_INNER - 1) / BLK_INNER;
+    s.nbx = c->k3x ? (c->cfg.n[0] + K3_BLK - 1) / K3_BLK : (c->cfg.n[0] + BLK_INNER - 1) / BLK_INNER;
     s.zlen = c->zlen;
     {
         const int rows = stage_rows_per_item(c->cfg.precision);
@@ -661,7 +739,13 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.halo_hi = c->halo_hi;
     s.acache = c->acache;
     for (int i = 0; i < 3; i++) s.h[i] = c->h[i];
-    HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
+    s.dtab = c->dtab;
+    s.dcs = c->dcs;
+    s.dks = c->dks;
+    if (c->k3x)
+        HIPCHK(c, launch_stage_k3(c->cfg.precision, s, c->grid, c->lds, c->stream));
+    else
+        HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
     return DG_OK;
 }
 
@@ -860,6 +944,56 @@ dg_status dg_set_forcing(dg_ctx *c, int32_t nmodes, const int32_t *nvec, const d
         const int m = order[j];
         for (int a = 0; a < 3; a++) t[9 * j + a] = (double)nvec[3 * m + a];
         for (int i = 0; i < 6; i++) t[9 * j + 3 + i] = ahat[6 * m + i];
+    }
+    if (c->k3x) {
+        // the k = 3 kernel forms the acceleration as a product: wave vectors with n_x >= 0
+        // (n -> -n with the conjugate amplitude gives the same real field), their y, z and in-cell
+        // x phases per (z, y) row in a table, the x phase of the cell per x
+        int nxmax = 0;
+        for (int j = 0; j < nmodes; j++) {
+            if (t[9 * j] < 0.0) {
+                for (int a = 0; a < 3; a++) t[9 * j + a] = -t[9 * j + a];
+                for (int cc = 0; cc < 3; cc++) t[9 * j + 4 + 2 * cc] = -t[9 * j + 4 + 2 * cc];
+            }
+            nxmax = std::max(nxmax, (int)t[9 * j]);
+        }
+        if (2 * (nxmax + 1) > 4 * K3_DKS) {
+            c->err = "dg_set_forcing: the k = 3 BF16 tiers take driving wave numbers |n_x| <= 3";
+            return DG_ERR_UNSUPPORTED;
+        }
+        const int dks = K3_DKS;
+        if (c->dtab && dks != c->dks) {
+            (void)hipFree(c->dtab);
+            (void)hipFree(c->dcs);
+            c->dtab = nullptr;
+            c->dcs = nullptr;
+        }
+        const int nx = c->cfg.n[0];
+        if (!c->dtab) {
+            HIPCHK(c, hipMalloc(&c->dtab, (size_t)k3_drive_row_floats(dks) * c->cfg.n[1] * c->cfg.n[2] * sizeof(float)));
+            HIPCHK(c, hipMalloc(&c->dcs, (size_t)nx * dks * 4 * sizeof(float)));
+        }
+        c->dks = dks;
+        std::vector<float> cs((size_t)nx * dks * 4);
+        for (int x = 0; x < nx; x++)
+            for (int k = 0; k < 4 * dks; k++) {
+                const int w = k / 2;
+                double ph = (double)w * x / nx;
+                ph -= std::floor(ph);
+                cs[(size_t)x * dks * 4 + k] = (float)((k & 1) ? std::sin(2.0 * M_PI * ph) : std::cos(2.0 * M_PI * ph));
+            }
+        if (!c->fmodes) HIPCHK(c, hipMalloc(&c->fmodes, t.size() * sizeof(double)));
+        HIPCHK(c, hipMemcpyAsync(c->fmodes, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->dcs, cs.data(), cs.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        GaussNodes xg{};
+        double wg[5];
+        gauss_rule(c->n, xg.x, wg);
+        HIPCHK(c, launch_drive_table_k3(c->fmodes, nmodes, dks, c->cfg.n[1], c->cfg.n[2], xg, nx, c->slab_z0,
+                                        c->slab_nz > 0 ? c->slab_nz : c->cfg.n[2], c->dtab, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->nfmodes = nmodes;
+        c->have_forcing = true;
+        return DG_OK;
     }
     if (!c->fmodes) HIPCHK(c, hipMalloc(&c->fmodes, t.size() * sizeof(double)));
     if (!c->acache)

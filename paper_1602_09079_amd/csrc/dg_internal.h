@@ -51,6 +51,31 @@ __host__ __device__ constexpr int slot_mode(int N, int g, int s) {
     return (s < mode_slots(N) && g * mode_slots(N) + s < N) ? g * mode_slots(N) + s : N;
 }
 
+// ---- the k = 3 stage kernel of the BF16-product tiers (stage_k3.hip): 16-cell x-blocks on
+// 64-byte boundaries, every product a 16x16x32 BF16 matrix-core operation.
+// Slot s (0..4) of lane group g (0..3) holds one mode, for the B operands of the products with
+// the weights (contraction index 8g + s) and for the result rows (row tile s / 4, register s % 4).
+// Slot 4 holds the four modes (0,0,w): their x and y derivatives vanish, so the volume product of
+// the x and y fluxes needs the first row tile only.
+__host__ __device__ constexpr int k3_slot_mode(int g, int s) {
+    return s == 4 ? (g == 0 ? 0 : g == 1 ? 3 : g == 2 ? 9 : 19)
+                  : (g == 0 ? (s == 0 ? 1 : s == 1 ? 2 : s == 2 ? 4 : 5)
+                     : g == 1 ? (s == 0 ? 6 : s == 1 ? 7 : s == 2 ? 8 : 10)
+                     : g == 2 ? (s == 0 ? 11 : s == 1 ? 12 : s == 2 ? 13 : 14)
+                              : (s == 0 ? 15 : s == 1 ? 16 : s == 2 ? 17 : 18));
+}
+// A-operand fragments (64 lanes x 8 BF16 = 1 KiB each) of one table set, in this order:
+// T1[t] (phi at the 16 volume points of z-node t), T3[f] (phi at the 16 points of face f),
+// T2A[t] (x and y derivative tables of z-node t), T2B[t][rt] (z derivative and source tables),
+// T4[a][rt] (lift of the - and + face of axis a).  BF16X3 appends the lo set.
+constexpr int K3_FRAG = 1024;
+constexpr int K3_T1 = 0, K3_T3 = 4, K3_T2A = 10, K3_T2B = 14, K3_T4 = 22, K3_NFRAG = 28;
+constexpr int K3_SET = K3_NFRAG * K3_FRAG;
+constexpr int K3_BLK = 16;           // cells per x-block
+constexpr int K3_DKS = 2;            // K steps (of 4) of the driving product: wave numbers |n_x| <= 3
+// driving factor table per (z, y) row of cells: [component][z-node][K step][lane] floats
+__host__ __device__ inline long long k3_drive_row_floats(int dks) { return 3LL * 4 * dks * 64; }
+
 // Stage kernel launch shape.  FP32-storage tiers: workgroups of 8 waves that own
 // 8 consecutive y rows of one x-block and sweep z together, sharing y-face traces
 // and fluxes through LDS.  FP64: workgroups of 4 independent waves.
@@ -165,10 +190,22 @@ struct StageArgs {
     int riemann;          // face flux: 0 HLLC, 1 exact Riemann solver
     const void *halo_lo;  // z slab: the plane below z = 0 and the plane above z = nz - 1 ([y][i][l][x]),
     const void *halo_hi;  // or nullptr (periodic in z)
+    // k = 3 BF16-tier kernel: the driving as a product (per-row factor table, per-x phases)
+    const float *dtab;    // [z][y] rows of k3_drive_row_floats(dks)
+    const float *dcs;     // [x][dks][4]: cos / sin of the x phases of the wave numbers n_x
+    int dks;              // K steps (of 4) of the driving product
 };
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
 hipError_t set_stage_attributes(int k, int prec, int lds_bytes);
+// the k = 3 BF16-tier kernel (stage_k3.hip)
+hipError_t launch_stage_k3(int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
+hipError_t set_stage_k3_attributes(int prec, int lds_bytes);
+hipError_t stage_k3_occupancy(int prec, int lds_bytes, int *per_cu);
+// driving factor table of the k = 3 kernel: modes [m][9] as for the cache (n as doubles, then
+// Re/Im of the three components), wave vectors with n_x >= 0
+hipError_t launch_drive_table_k3(const double *modes, int nmodes, int dks, int ny, int nz, const GaussNodes &xg,
+                                 int nx, int z0, int nzg, float *out, hipStream_t s);
 
 hipError_t launch_project(int k, int prec, const void *qp, void *y, const double *ptab, long long ncells, int nx,
                           hipStream_t s);
@@ -249,6 +286,11 @@ struct dg_ctx {
     int nparts = 0;
     double *fmodes = nullptr;      // forcing mode table [MAX_FORCING_MODES][9]
     void *acache = nullptr;        // driving acceleration at the volume points (storage type)
+    // k = 3 in the BF16-product tiers runs stage_k3_kernel (16-cell x-blocks, driving as a product)
+    bool k3x = false;
+    float *dtab = nullptr;         // its driving factor table, per (z, y) row
+    float *dcs = nullptr;          // cos / sin of the x phases, per x
+    int dks = 0;                   // K steps of the driving product
     int nfmodes = 0;
     bool have_forcing = false;
     int grid = 0;
