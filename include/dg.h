@@ -238,6 +238,17 @@ size_t dg_column_stats_workspace_bytes(int32_t cols);
 dg_status dg_column_stats(const float *x, int64_t rows, int32_t cols, double *mean, double *stdev, double *rms,
                           double *maxabs, void *work, void *hip_stream);
 
+/* dg_column_stats without a workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid allocation).  The same kernels and
+ * the same results, bit for bit; the partial sums live in a static device array of the library
+ * (1024 x 160 x 3 doubles, 3.75 MiB per GPU, held until the process ends), found once per device
+ * on its first call.  cols <= 160 (DG_ERR_ARG beyond, with the reason in dg_error_string(NULL)).
+ * Allocates nothing.  Every call on one GPU uses that GPU's one array: calls that overlap on a GPU
+ * (other streams, other threads) race and must be ordered by the caller.  Nothing in the array
+ * needs to start at zero: each call writes every partial it reads. */
+dg_status dg_column_stats_noalloc(const float *x, int64_t rows, int32_t cols, double *mean, double *stdev,
+                                  double *rms, double *maxabs, void *hip_stream);
+
 /* x[r][c] = (x[r][c] - shift[c]) / scale[c] in place.  shift, scale: DEVICE double [cols]. */
 dg_status dg_standardize(float *x, int64_t rows, int32_t cols, const double *shift, const double *scale,
                          void *hip_stream);
@@ -272,8 +283,9 @@ int32_t dg_nmodes(int32_t k);                      /* N(k) = (k+1)(k+2)(k+3)/6, 
 dg_status dg_gauss_nodes(int32_t n, double *xi);   /* n-point Gauss-Legendre nodes on [-1,1], 1 <= n <= 5, ascending */
 
 /* Last error message of ctx ("" if none).  ctx == NULL: why the calling thread's last dg_init
- * failed (the rejected argument, or the failing HIP call's error name and text), or a fixed
- * message if it has not failed.  The string stays valid until the thread's next dg_init. */
+ * or dg_column_stats_noalloc failed (the rejected argument, or the failing HIP call's error), or
+ * a fixed message if neither has failed.  The string stays valid until the thread's next call of
+ * either. */
 const char *dg_error_string(const dg_ctx *ctx);
 
 /* ---------------------------------------------------------------------------

@@ -16,6 +16,9 @@
 // (2n)^3 cells onto degree kc on n^3 cells, a fixed linear map per child cell
 // built on the host from the library's own basis and Gauss rules.
 
+#include <mutex>
+#include <string>
+
 #include "dg_internal.h"
 
 namespace dgmi {
@@ -528,4 +531,63 @@ hipError_t launch_standardize(float *x, long long rows, int cols, const double *
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ allocation-free column statistics
+
+// The scratch of dg_column_stats_noalloc: the per-chunk partial sums of the column statistics
+// (chunk, column, 3), in a file-scope device array, one copy per GPU, held until the process ends.
+// Host code never uses the array's name as an address: it takes the address that
+// hipGetSymbolAddress returns for the current device, once per device, and passes that.
+constexpr int NOALLOC_MAX_COLS = 160;   // 140 closure features, with room to spare
+constexpr int NOALLOC_CHUNKS = 1024;    // the chunking of dg_column_stats: the same bits
+static __device__ __align__(256) double scratch[(size_t)NOALLOC_CHUNKS * NOALLOC_MAX_COLS * 3];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// the current device's copy of the scratch array (looked up on the device's first call)
+static hipError_t scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace dgmi
+
+extern "C" dg_status dg_column_stats_noalloc(const float *x, int64_t rows, int32_t cols, double *mean, double *stdev,
+                                             double *rms, double *maxabs, void *hip_stream) {
+    using namespace dgmi;
+    if (!x || rows < 1 || cols < 1 || !mean || !stdev || !rms || !maxabs) {
+        set_call_error("dg_column_stats_noalloc: NULL pointer, rows < 1 or cols < 1");
+        return DG_ERR_ARG;
+    }
+    if (cols > NOALLOC_MAX_COLS) {
+        set_call_error("dg_column_stats_noalloc: cols > 160, the columns its static scratch holds "
+                       "(dg_column_stats takes up to 256 with a workspace)");
+        return DG_ERR_ARG;
+    }
+    double *part = nullptr;
+    hipError_t e = scratch_address(&part);
+    if (e == hipSuccess) {
+        const int nchunks = (int)(rows < NOALLOC_CHUNKS ? rows : NOALLOC_CHUNKS);
+        e = launch_colstats(x, rows, cols, part, nchunks, mean, stdev, rms, maxabs,
+                            reinterpret_cast<hipStream_t>(hip_stream));
+    }
+    if (e != hipSuccess) {
+        set_call_error((std::string("dg_column_stats_noalloc: ") + hipGetErrorString(e)).c_str());
+        return DG_ERR_HIP;
+    }
+    return DG_OK;
+}

@@ -433,6 +433,12 @@ dg_status dg_gauss_nodes(int32_t n, double *xi) {
     return DG_OK;
 }
 
+}  // extern "C"
+
+void dgmi::set_call_error(const char *msg) { g_init_err = msg; }
+
+extern "C" {
+
 const char *dg_error_string(const dg_ctx *ctx) {
     if (ctx) return ctx->err.c_str();
     return g_init_err.empty() ? kNoCtx : g_init_err.c_str();

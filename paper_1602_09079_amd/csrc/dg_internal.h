@@ -268,6 +268,8 @@ hipError_t launch_colstats(const float *x, long long rows, int cols, double *par
                            double *stdv, double *rms, double *maxabs, hipStream_t s);
 hipError_t launch_standardize(float *x, long long rows, int cols, const double *shift, const double *scale,
                               hipStream_t s);
+// the message dg_error_string(NULL) returns on the calling thread (calls without a context)
+void set_call_error(const char *msg);
 
 }  // namespace dgmi
 

@@ -28,7 +28,7 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_dt", "dg_step", "dg_totals", "dg_set_forcing", "dg_ou_update", "dg_nmodes", "dg_gauss_nodes",
            "dg_error_string", "dg_set_closure", "dg_closure_fallbacks", "dg_closure_features", "dg_closure_targets",
            "dg_restrict", "dg_mlp_nparams", "dg_mlp_workspace_bytes", "dg_mlp_forward", "dg_mlp_loss_grad", "dg_adam",
-           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_standardize", "dg_limiter_stats",
+           "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_column_stats_noalloc", "dg_standardize", "dg_limiter_stats",
            "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated", "dg_sample",
            "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach",
            "dg_plane_count", "dg_set_halo", "dg_set_slab"]
@@ -106,6 +106,8 @@ def lib():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]),
             "dg_column_stats_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
             "dg_column_stats": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "dg_column_stats_noalloc": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                                       _vp]),
             "dg_standardize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp]),
             "dg_limiter_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)]),
             "dg_set_isothermal": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),

@@ -106,3 +106,15 @@ def test_mlp_host_helpers():
     # invalid arguments are rejected before any device work
     assert dg.lib().dg_adam(10, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == dg.DG_ERR_ARG
     assert dg.lib().dg_column_stats(None, 10, 3, None, None, None, None, None, None) == dg.DG_ERR_ARG
+
+
+def test_column_stats_noalloc_rejects_before_device_work():
+    """The allocation-free column statistics reject NULL pointers and more columns than the static
+    scratch holds (160) before any device call, with the reason in dg_error_string(NULL)."""
+    L = dg.lib()
+    fake = 4096  # non-NULL placeholders: the checks return before any pointer is used
+    assert L.dg_column_stats_noalloc(None, 10, 3, fake, fake, fake, fake, None) == dg.DG_ERR_ARG
+    assert "NULL" in L.dg_error_string(None).decode()
+    assert L.dg_column_stats_noalloc(fake, 10, 161, fake, fake, fake, fake, None) == dg.DG_ERR_ARG
+    assert "160" in L.dg_error_string(None).decode()
+    assert L.dg_column_stats_noalloc(fake, 0, 3, fake, fake, fake, fake, None) == dg.DG_ERR_ARG
