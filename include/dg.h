@@ -392,6 +392,12 @@ size_t dg_plane_count(const dg_ctx *ctx);
  * DG_ERR_STATE. */
 dg_status dg_set_halo(dg_ctx *ctx, const void *lo, const void *hi);
 
+/* The z-chunk length of the stage sweep of k = 1..3 (the cells along z one work item of the
+ * stage kernel covers, carrying the z-face flux from cell to cell); 0 restores the length
+ * dg_init chose for the device.  The result does not depend on it, bit for bit (a test checks
+ * that); it exists for that check and for tuning.  DG_ERR_ARG unless 0 <= len <= n[2]. */
+dg_status dg_set_zchunk(dg_ctx *ctx, int32_t len);
+
 /* The slab's place in the whole mesh for the driving field: its first plane
  * is global plane z0 of nz_global (default 0 of n[2]).  Call before
  * dg_set_forcing.  DG_ERR_ARG unless 0 <= z0 and z0 + n[2] <= nz_global. */

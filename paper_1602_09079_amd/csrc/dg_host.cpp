@@ -630,6 +630,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         }
     }
     c->zlen = (int)zl;
+    c->zlen_auto = c->zlen;
     const long long nitems = nbx * nyg * ((cfg->n[2] + zl - 1) / zl);
     long long grid = (long long)per_cu * ncu;
     grid = std::min(grid, (nitems + items_per_wg - 1) / items_per_wg);
@@ -1526,6 +1527,16 @@ dg_status dg_set_halo(dg_ctx *c, const void *lo, const void *hi) {
     }
     c->halo_lo = lo;
     c->halo_hi = hi;
+    return DG_OK;
+}
+
+dg_status dg_set_zchunk(dg_ctx *c, int32_t len) {
+    if (!c) return DG_ERR_ARG;
+    if (len < 0 || len > c->cfg.n[2]) {
+        c->err = "dg_set_zchunk: need 0 <= len <= n[2]";
+        return DG_ERR_ARG;
+    }
+    c->zlen = len == 0 ? c->zlen_auto : len;
     return DG_OK;
 }
 

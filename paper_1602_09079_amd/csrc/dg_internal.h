@@ -297,6 +297,7 @@ struct dg_ctx {
     bool have_forcing = false;
     int grid = 0;
     int zlen = 1;                  // z chunk length of the stage sweep
+    int zlen_auto = 1;             // the length dg_init chose (dg_set_zchunk(ctx, 0) restores it)
     int ex_off = 0;                // LDS offsets of the y-face trace and flux regions (after the tables)
     int ex_off2 = 0;
     int ex_off3 = -1;              // LDS offset of the end-row buffers (-1: not used)

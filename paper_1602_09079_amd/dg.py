@@ -31,7 +31,7 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_column_stats_noalloc", "dg_standardize", "dg_limiter_stats",
            "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated", "dg_sample",
            "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach",
-           "dg_plane_count", "dg_set_halo", "dg_set_slab"]
+           "dg_plane_count", "dg_set_halo", "dg_set_slab", "dg_set_zchunk"]
 
 
 class DGError(RuntimeError):
@@ -122,6 +122,7 @@ def lib():
             "dg_plane_count": (ctypes.c_size_t, [_vp]),
             "dg_set_halo": (ctypes.c_int, [_vp, _vp, _vp]),
             "dg_set_slab": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+            "dg_set_zchunk": (ctypes.c_int, [_vp, ctypes.c_int32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -351,6 +352,10 @@ class Solver:
 
     def set_slab(self, z0, nz_global):
         self._check(lib().dg_set_slab(self._ctx, z0, nz_global), "dg_set_slab")
+
+    def set_zchunk(self, length):
+        """z-chunk length of the stage sweep (0: the automatic choice); results are independent of it."""
+        self._check(lib().dg_set_zchunk(self._ctx, length), "dg_set_zchunk")
 
     # ------------------------------------------------------------ diagnostics (Sec. 3.3, 4.1, 4.4)
     def sample(self, y, S=4):

@@ -60,11 +60,14 @@ def err_max_norm(g, w):
     return np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1).max()
 
 
+@pytest.mark.parametrize("n", [(37, 6, 5), (70, 7, 5)])
 @pytest.mark.parametrize("riemann", ["hllc", "exact"])
 @pytest.mark.parametrize("forcing", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_rhs_parity_k0(dgm, prec, forcing, riemann):
-    n = (37, 6, 5)  # ragged against the 256-thread blocks
+def test_rhs_parity_k0(dgm, prec, forcing, riemann, n):
+    # workgroup tiles are 64 x 4 cells (x, y): (37, 6, 5) is one ragged tile in x and a ragged
+    # second row of tiles in y; (70, 7, 5) has two tiles in x (the -x face of the second tile's
+    # first column comes from the first tile) and ny not a multiple of 4
     cfg, y = turb(n, riemann=riemann)
     s = dgm.Solver(0, n, gamma=G, precision=prec, forcing=forcing, riemann=riemann)
     frc = None
@@ -77,8 +80,8 @@ def test_rhs_parity_k0(dgm, prec, forcing, riemann):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16x3"])
-def test_steps_parity_k0(dgm, prec):
-    n = (20, 7, 6)
+@pytest.mark.parametrize("n", [(20, 7, 6), (70, 7, 5)])
+def test_steps_parity_k0(dgm, prec, n):
     cfg, y = turb(n, seed=5)
     s = dgm.Solver(0, n, gamma=G, precision=prec)
     yd = dev(y, s.dtype)

@@ -197,3 +197,52 @@ def test_edge_grids(dgm, n):
     r = s.rhs(y)
     err = rhs_err(state_host(r), O.rhs(cfg, y_or))
     assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_step_parity_several_row_groups(dgm, prec):
+    """k = 3 with ny = 19: two full groups of 8 y rows that share their y faces through LDS and a
+    ragged group of 3, two x-blocks (one ragged), with the driving; two fixed-dt steps against the
+    oracle."""
+    from paper_1602_09079_amd import dg as dgmod
+    k, n, box = 3, (20, 19, 3), (1.0, 0.9, 1.1)
+    cfg, qp, y_or = turb_case(k, n, box)
+    nvec = synth.forcing_modes(1.0, 3.0)
+    th = synth.ou_stationary_start(7, len(nvec))
+    z = synth.ou_normals(7, len(nvec), 1)[0]
+    _, ah_lib = dgmod.ou_update(nvec, th, z, 0.9, 1.0, 0.05, 1.0, 3.0)
+    _, ah_orc = O.ou_update(nvec, th, z, 0.9, 1.0, 0.05, 1.0, 3.0)
+    h = O.dt(cfg, y_or)
+    y_st = y_or.astype(np.float32).astype(np.float64)  # the state as the GPU stores it
+    s = dgm.Solver(k, n, box=box, gamma=G, precision=prec, forcing=True)
+    s.set_forcing(nvec, ah_lib)
+    y = state_dev(y_or, s.dtype)
+    s.step(y, nsteps=2, dt=h)
+    y1, _ = O.step(cfg, y_st, h, 2, frc=O.ForcingTable(nvec, ah_orc))
+    err = O.rel_l2(state_host(y), y1)
+    print(f"step k=3 ny=19 {prec}: rel L2 per field {err}")
+    assert np.all(err <= TOL_STATE[prec]), err
+    # the increment alone (y - y0), which the state norm hides, against the largest field's, as R;
+    # the six stored FP32 stages round the state at 2^-24 of |y|, about 1e-4 of this increment
+    inc = rhs_err(state_host(y) - y_st, y1 - y_st)
+    print(f"step k=3 ny=19 {prec}: increment error per field / max field norm {inc}")
+    assert np.all(inc <= {"fp32": 1e-3, "bf16x3": 1e-3, "bf16": 0.5}[prec]), inc
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("k", [1, 3])
+def test_tiling_invariance(dgm, prec, k):
+    """The same steps with three z-chunk lengths of the stage sweep (whole column, ragged chunks,
+    one cell) are bit for bit equal: the -z face flux a chunk recomputes at its start equals the
+    carried one, and no work item sees another's LDS."""
+    n, box = (33, 17, 12), (1.0, 1.0, 1.0)
+    cfg, qp, y_or = turb_case(k, n, box)
+    s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
+    outs = []
+    for zl in (12, 5, 1, 0):
+        s.set_zchunk(zl)
+        y = state_dev(y_or, s.dtype)
+        s.step(y, nsteps=2, dt=0.0)
+        outs.append(y)
+    for zl, y in zip((5, 1, 0), outs[1:]):
+        assert torch.equal(y, outs[0]), f"z chunk {zl} differs from 12"
