@@ -597,6 +597,11 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             c->ex_off3 = c->lds;
             c->lds += erb;
         }
+        if (c->k3x) {  // it also needs the end rows and the ghost-cell copies
+            if (c->ex_off3 < 0 || c->lds + K3_GHOST_BYTES > maxlds) return fail(DG_ERR_UNSUPPORTED);
+            c->ex_off4 = c->lds;
+            c->lds += K3_GHOST_BYTES;
+        }
     }
     if ((c->k3x ? set_stage_k3_attributes(cfg->precision, c->lds)
                 : set_stage_attributes(cfg->k, cfg->precision, c->lds)) != hipSuccess)
@@ -738,6 +743,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.ex_off2 = c->ex_off2;
     s.ex_single = c->ex_off2 == c->ex_off ? 1 : 0;
     s.ex_off3 = c->ex_off3;
+    s.ex_off4 = c->ex_off4;
     s.ncells = c->ncells;
     s.mode = mode;
     s.forcing = (c->cfg.flags & DG_FORCING) ? 1 : 0;

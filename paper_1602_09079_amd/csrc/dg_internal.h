@@ -80,6 +80,7 @@ __host__ __device__ inline long long k3_drive_row_floats(int dks) { return 3LL *
 // 8 consecutive y rows of one x-block and sweep z together, sharing y-face traces
 // and fluxes through LDS.  FP64: workgroups of 4 independent waves.
 constexpr int YROWS = 8;
+constexpr int K3_GHOST_BYTES = YROWS * 4 * 64 * 4;  // k = 3 x-face ghost cells: 4 copies of 64 lanes per wave
 inline int stage_block_threads(int prec) { return prec == DG_FP64 ? 256 : 64 * YROWS; }
 inline int stage_rows_per_item(int prec) { return prec == DG_FP64 ? 1 : YROWS; }
 // LDS bytes of one y-face exchange region: a slot of 5 fields x 4 values x 64 lanes per wave
@@ -180,6 +181,7 @@ struct StageArgs {
     int ex_off2;          // LDS byte offset of the y-face flux slots (== ex_off: shared, ex_single = 1)
     int ex_single;
     int ex_off3;          // LDS byte offset of the end-row buffers, or -1 when they do not fit
+    int ex_off4;          // k = 3 BF16 tiers: LDS byte offset of the x-face ghost-cell copies
     long long ncells;
     int mode;             // 0: out = R(yin); 1: out = a*y0 + b*(yin - dt*R(yin))
     int forcing;          // 1: add the driving source
@@ -301,6 +303,7 @@ struct dg_ctx {
     int ex_off = 0;                // LDS offsets of the y-face trace and flux regions (after the tables)
     int ex_off2 = 0;
     int ex_off3 = -1;              // LDS offset of the end-row buffers (-1: not used)
+    int ex_off4 = -1;              // LDS offset of the x-face ghost-cell copies (k = 3 BF16 tiers)
     // z slab of a larger periodic mesh (DG_ZHALO): halo planes and the slab's place for the driving
     const void *halo_lo = nullptr, *halo_hi = nullptr;
     int slab_z0 = 0, slab_nz = 0;

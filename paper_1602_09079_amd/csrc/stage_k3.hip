@@ -145,6 +145,10 @@ __device__ inline float shr(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + N, 0xf, 0xf, true));
 }
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
+constexpr int WAIT_LGKM0 = 0xC07F;
+
 }  // namespace
 
 template <int PREC, bool FORCE, int RS>
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     auto trace_lds = [&](int f, int e, C tr[NF][4]) {
         // vmcnt(0): the copies have landed (the compiler does not track them); the memory clobber
         // keeps the LDS reads below the wait
-        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __builtin_amdgcn_s_waitcnt(wait_vm(0));
         asm volatile("" ::: "memory");
         const C *src = ex_e + e * ERV * 64;
         B3 b;
@@ -286,6 +290,49 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             for (int s = 0; s < NSL; s++) b.v[i][s] = src[(i * (1 + NSL) + 1 + s) * 64 + lane];
         }
         trace(f, b, tr);
+    };
+    // The ghost cells of the x faces (the cell before the block and the cell after it), copied into
+    // LDS by the load unit one z step ahead, four 64-lane copies per wave: lane (g, c) copies value
+    // 4 (c % 8) + k in copy k of the cell before (c < 8) or after (c >= 8) for lane group g; value
+    // e = 6 i + m of a cell is field i's mean (m = 0) or its slot m - 1.  xgl, xgr: the two cells'
+    // byte offsets in a row.
+    C *ex_g = reinterpret_cast<C *>(lds + a.ex_off4) + wave * 4 * 64;
+    auto ghost_dma = [&](long long r, unsigned xgl, unsigned xgr) {
+        const auto rs = slab_rsrc(yin, slabn, r);
+        // lane values made opaque here: the offsets are formed at each use instead of being kept
+        // in registers across the sweep
+        unsigned cx = col < 8 ? xgl : xgr;
+        int ln = lane;
+        asm volatile("" : "+v"(cx), "+v"(ln));
+        const int gg = ln >> 4, c8 = ln & 7;
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int e0 = 4 * c8 + k;
+            const int e = e0 < NF * (1 + NSL) ? e0 : 0;  // the two spare values copy the first one again
+            const int i = e / (1 + NSL), m = e - i * (1 + NSL);
+            const unsigned row = m == 0 ? 0u : (unsigned)k3_slot_mode(gg, m - 1);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(ex_g + k * 64), 4,
+                                                     row * nxu * 4u + cx + (unsigned)i * fbytes, 0, 0, 0);
+        }
+        asm volatile("" ::: "memory");
+    };
+    // this lane's ghost cell (column 0: the cell before, column 15 of a full block: the cell after,
+    // odd-u modes negated); other lanes get values they do not use
+    auto ghost_read = [&](bool after, B3 &gb) {
+        int o = 16 * g + (after ? 8 : 0);
+        asm volatile("" : "+v"(o));
+        const C *src = ex_g + o;
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            gb.qbar[i] = src[((6 * i) % 4) * 64 + (6 * i) / 4];
+#pragma unroll
+            for (int s2 = 0; s2 < NSL; s2++) {
+                const int e = 6 * i + 1 + s2;
+                const C vv = src[(e % 4) * 64 + e / 4];
+                gb.v[i][s2] = (after && ((oddu >> s2) & 1u)) ? -vv : vv;
+            }
+        }
     };
     auto riemann = [&](auto axis_c, const C tl[NF][4], const C tr_[NF][4], C Fo[NF][4]) {
         constexpr int AX = decltype(axis_c)::value;
@@ -543,7 +590,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         // the ghost columns: column 0 reads the cell before the block, column 15 (full blocks)
         // the cell after it
         const bool gl = col == 0, gr = col == 15 && vc == K3_BLK;
-        const unsigned goff = (unsigned)(gl ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + K3_BLK) % nx) * 4u;
+        const unsigned xgl = (unsigned)(x0 == 0 ? nx - 1 : x0 - 1) * 4u, xgr = (unsigned)((x0 + K3_BLK) % nx) * 4u;
         if constexpr (FORCE) {
 #pragma unroll
             for (int s = 0; s < K3_DKS; s++) csv[s] = a.dcs[((long long)xc * K3_DKS + s) * 4 + g];
@@ -554,7 +601,9 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             return (long long)zz * ny + yy;
         };
 
-        if (act) {  // the host guarantees the end-row region (a.ex_off3 >= 0)
+        // the host guarantees the end-row and ghost regions (a.ex_off3, a.ex_off4 >= 0)
+        ghost_dma(cidx(iy, z0), xgl, xgr);
+        if (act) {
             if (wrow == 0) load_lds(cidx(iy0 - 1, z0), 0);
             if (wrow == nact - 1) load_lds(cidx(iy0 + nact, z0), 1);
         }
@@ -614,47 +663,25 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 ex_put(ex_f, wrow, Fyp);
             }
             __syncthreads();
-            // the ghost cells of this step's x faces (columns 0 and 15), requested before the copies
-            // of y0 and the next block: loads complete in order, so waiting for these waits for
-            // nothing issued after them
-            B3 gb;
-            {
-                const auto rs = slab_rsrc(yin, slabn, cidx(iy, z));
+            // the stage-combine input y0 (stages 2 and 3): slots 0..3 copied by the load unit into
+            // this wave's trace slot (free until the next step's puts), slot 4 loaded into registers;
+            // requested now, so the round trip hides behind the remaining faces
+            C y04[NF];
+            auto y0_copy = [&]() {
+                if (dma_y0 && act) {
+                    const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
 #pragma unroll
-                for (int i = 0; i < NF; i++) {
-                    const unsigned so = (unsigned)i * fbytes;
-                    gb.qbar[i] = 0.0f;
+                    for (int u = 0; u < 4; u++)
 #pragma unroll
-                    for (int s = 0; s < NSL; s++) gb.v[i][s] = 0.0f;
-                    if (gl || gr) {
-                        gb.qbar[i] = bload(0.0f, rs, goff, so);
+                        for (int i = 0; i < NF; i++)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                r0, (__attribute__((address_space(3))) void *)(ex_t + ((wrow * NF + i) * 4 + u) * 64),
+                                4, roff[u] + xoff, (int)((unsigned)i * fbytes), 0, 0);
 #pragma unroll
-                        for (int s = 0; s < NSL; s++) {
-                            const float vv = bload(0.0f, rs, roff[s] + goff, so);
-                            gb.v[i][s] = (gr && ((oddu >> s) & 1u)) ? -vv : vv;
-                        }
-                    }
+                    for (int i = 0; i < NF; i++) y04[i] = bload(0.0f, r0, roff[4] + xoff, (unsigned)i * fbytes);
                 }
-            }
-            // the trace region is free until the next step's puts: the stage-combine input y0 of this
-            // wave's slots 0..3 is copied into its slot by the load unit now, so the round trip hides
-            // behind the remaining faces
-            if (dma_y0 && act) {
-                const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
-#pragma unroll
-                for (int u = 0; u < 4; u++)
-#pragma unroll
-                    for (int i = 0; i < NF; i++)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            r0, (__attribute__((address_space(3))) void *)(ex_t + ((wrow * NF + i) * 4 + u) * 64), 4,
-                            roff[u] + xoff, (int)((unsigned)i * fbytes), 0, 0);
-            }
-            C y04[NF];  // slot 4 of y0 (stages 2 and 3), in registers
-            if (dma_y0 && act) {
-                const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
-#pragma unroll
-                for (int i = 0; i < NF; i++) y04[i] = bload(0.0f, r0, roff[4] + xoff, (unsigned)i * fbytes);
-            }
+            };
+            y0_copy();
             if (wrow > 0) ex_get(ex_f, wrow - 1, Fym);
             lift(1, cur, Fym, Fyp, acc);
             B3 nxt;
@@ -667,8 +694,22 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 {
                     C tp[NF][4], tg[NF][4];
                     {
+                        // the ghost cells from their copy in LDS.  The copies were requested in the
+                        // previous step (or before the first) and requests complete in order: the 30
+                        // loads of the next block and, in stages 2 and 3, the 25 of y0 were issued
+                        // after them
+                        if (dma_y0 && act)
+                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + NF * NSL));
+                        else
+                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL)));
+                        asm volatile("" ::: "memory");
+                        B3 gb;
+                        ghost_read(gr, gb);
                         trace(1, gb, tg);  // column 0: +x trace of the cell before; 15: -x trace after
                     }
+                    // the copies read above have been used: their slots take the next step's
+                    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+                    if (z + 1 < z1) ghost_dma(cidx(iy, z + 1), xgl, xgr);
                     trace(1, cur, tp);
                     if (vc == K3_BLK) {
                         // the 16 points of column 15's +x face, one per lane of columns 12..15
@@ -745,9 +786,11 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         // slot 4 loaded after the y faces; slots 0..3 were copied into this wave's trace slot
 #pragma unroll
                         for (int i = 0; i < NF; i++) y0v[i][4] = y04[i];
-                        // vmcnt(0): the copies into LDS have landed (the compiler does not track them);
-                        // the memory clobber keeps the LDS reads below the wait
-                        __builtin_amdgcn_s_waitcnt(0x0F70);
+                        // the copies into LDS have landed (the compiler does not track them): requests
+                        // complete in order, and the slot-4 loads and the next step's ghost copies (if
+                        // any) were issued after them; the memory clobber keeps the LDS reads below the
+                        // wait
+                        __builtin_amdgcn_s_waitcnt(wait_vm(4));
                         asm volatile("" ::: "memory");
 #pragma unroll
                         for (int i = 0; i < NF; i++)
