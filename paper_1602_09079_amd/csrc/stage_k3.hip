@@ -128,7 +128,11 @@ __device__ inline Op<X3> weights_op(const float v[NSL], const SplitConst &k) {
     unsigned h0, h1, h2, l0 = 0, l1 = 0, l2 = 0;
     split_pair<X3>(v[0], v[1], h0, l0, k);
     split_pair<X3>(v[2], v[3], h1, l1, k);
-    split_pair<X3>(v[4], 0.0f, h2, l2, k);
+    {  // slot 4 with a zero: one split
+        const bv2 h = __builtin_convertvector((fv2){v[4], 0.0f}, bv2);
+        h2 = __builtin_bit_cast(unsigned, h);
+        if constexpr (X3) l2 = pk_bf16(__builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bv2, k.m0), v[4], false), 0.0f);
+    }
     Op<X3> op;
     op.hi = __builtin_bit_cast(bf8, (u4v){h0, h1, h2, 0u});
     if constexpr (X3) op.lo = __builtin_bit_cast(bf8, (u4v){l0, l1, l2, 0u});
@@ -148,6 +152,17 @@ __device__ inline float shr(float v) {
 // s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
 constexpr int WAIT_LGKM0 = 0xC07F;
+
+// Barrier for data exchanged through LDS only: this wave's LDS accesses have completed, then the
+// workgroup meets.  Unlike __syncthreads it does not wait for outstanding global loads and stores
+// (the copies requested one step ahead stay in flight); what the load unit copies into LDS is read
+// only by the wave that requested it, after its own wait.
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 }  // namespace
 
@@ -399,12 +414,19 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
                 for (int s = 0; s < K3_DKS; s++) hn[c][s] = drow[(c * 4 * K3_DKS + s) * 64 + lane];
         }
+        // the weights' operands, formed once for the four nodes where the registers allow it (the
+        // driving source needs them for its own operands)
+        OP w5[FORCE ? 1 : NF];
+        if constexpr (!FORCE) {
+#pragma unroll
+            for (int i = 0; i < NF; i++) w5[i] = wop(b, i);
+        }
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             refresh();
             Acc d[NF];
 #pragma unroll
-            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, wop(b, i));
+            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, FORCE ? wop(b, i) : w5[i]);
             // the driving acceleration of the node (issued after the x/y chunk, below)
             Acc av[3] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
             float ha[3][K3_DKS];
@@ -649,7 +671,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     riemann(std::integral_constant<int, 1>{}, tb, tm, Fym);
                 }
             }
-            __syncthreads();
+            lds_barrier();
             {
                 C tp[NF][4], ta[NF][4];
                 trace(3, cur, tp);
@@ -662,7 +684,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 riemann(std::integral_constant<int, 1>{}, tp, ta, Fyp);
                 ex_put(ex_f, wrow, Fyp);
             }
-            __syncthreads();
+            lds_barrier();
             // the stage-combine input y0 (stages 2 and 3): slots 0..3 copied by the load unit into
             // this wave's trace slot (free until the next step's puts), slot 4 loaded into registers;
             // requested now, so the round trip hides behind the remaining faces
