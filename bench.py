@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
 FP64_VECTOR_TFLOPS = 78.6   # MI355X vector FP64
 FP32_VECTOR_TFLOPS = 157.3  # MI355X vector FP32
 FP32_MATRIX_TFLOPS = 157.3  # MI355X dense FP32 matrix cores
@@ -47,6 +48,9 @@ def parse():
     p.add_argument("--diagnostics", action="store_true", help="also time the spectrum, PDF and Mach diagnostics")
     p.add_argument("--no-limiter", action="store_true", help="skip the limiter and isothermal-reset timings")
     p.add_argument("--k4-n", type=int, default=64, help="mesh of the k = 4 timing (0: skip it)")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the other workloads (k=2 on 64^3 FP64/FP32, k=3 on 128^3 in every tier) and the "
+                        "operator-only figure")
     p.add_argument("--copy-calibration", type=float, default=0.0,
                    help="GiB: also run a plain device copy of this size (reference for counter-based traffic)")
     return p.parse_args()
@@ -64,9 +68,17 @@ def stage_bytes(N, cells, elem):
     return [2 * st, 3 * st, 3 * st]
 
 
+# Algorithmic floating-point operations per cell of one stage at k = 3 (dense contractions as
+# written, an FMA counts 2): modal -> volume points 2*5*N*Q, volume integral 2*3*5*N*Q, driving
+# source projection 2*4*N*Q, face traces 2*6*5*N*16, lift 2*6*5*N*16 (N = 20, Q = 64): 89 600;
+# the vector remainder (point fluxes, HLLC on 48 face points, update) about 7 980.
+K3_CONTRACTION_FLOPS = 89600
+K3_VECTOR_FLOPS = 7980
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dg_kernels.hip", "dg_host.cpp", "dg_internal.h"):
+    for f in ("dg_kernels.hip", "stage_k3.hip", "dg_device.h", "dg_host.cpp", "dg_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1602_09079_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -152,6 +164,28 @@ def measure_tier(args, dg, torch, prec, qp_dev, n, k):
               f"({', '.join(f'{v:.2f}' for v in out['stage_ms_each'])}), "
               f"{achieved:.0f} GB/s algorithmic, finite={finite}")
     del s, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def config_cost(args, dg, torch, k, n, tiers, forcing=True):
+    """Another workload of the same recipe (seeded turbulence surrogate at Mach 0.3, driving on
+    1 <= |n| <= 3): k, n^3 cells, each tier's dg_step rate and stage-launch roofline."""
+    from paper_1602_09079_amd import synth
+    qp = synth.turbulence(n, dg.gauss_nodes(k + 1), seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
+    sub = argparse.Namespace(**vars(args))
+    sub.no_forcing = not forcing
+    out = dict(k=k, n=n, cells=n ** 3, dof=5 * dg.nmodes(k) * n ** 3, forcing=forcing, tiers={})
+    for prec in tiers:
+        r = measure_tier(sub, dg, torch, prec, qp, n, k)
+        out["tiers"][prec] = dict(dof_updates_per_s=r["dof_updates_per_s"], ms_per_step=r["ms_per_step"],
+                                  stage_ms=r["stage_ms"], stage_ms_each=r["stage_ms_each"],
+                                  hbm_frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4))
+    if "fp64" in out["tiers"]:
+        base = out["tiers"]["fp64"]["dof_updates_per_s"]
+        out["speedup_vs_fp64"] = {p: round(v["dof_updates_per_s"] / base, 3) for p, v in out["tiers"].items()
+                                  if p != "fp64"}
+    del qp
     torch.cuda.empty_cache()
     return out
 
@@ -526,6 +560,15 @@ def main():
     k4 = None if (args.no_limiter or args.k4_n <= 0 or k == 4) else k4_cost(args, dg, torch)
     clo = None if args.no_limiter else closure_cost(args, dg, torch)
     k0 = None if (args.no_limiter or k == 0) else k0_cost(args, dg, torch)
+    opo = None
+    if not args.no_configs and not args.no_forcing:
+        # the operator alone (no driving source) on the same state, the primary tier
+        sub = argparse.Namespace(**vars(args))
+        sub.no_forcing = True
+        r = measure_tier(sub, dg, torch, prim0, qp, n, k)
+        opo = dict(tier=prim0, forcing=False, dof_updates_per_s=r["dof_updates_per_s"], ms_per_step=r["ms_per_step"],
+                   stage_ms=r["stage_ms"], stage_ms_each=r["stage_ms_each"], achieved_GBs=round(r["achieved_GBs"], 1),
+                   hbm_frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4))
     del qp
     torch.cuda.empty_cache()
     # the box's own copy bandwidth (2 GiB device-to-device, read + write bytes), the second roof
@@ -549,8 +592,13 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        # the same bytes in 64-byte segments (the first 16 floats of every 32): the stage kernels
+        # read and write 64-byte row segments, the plain copy whole 128-byte lines
+        sv, dv = src.view(-1, 32)[:, :16], dst.view(-1, 32)[:, :16]
+        for _ in range(3):
+            dv.copy_(sv)
         torch.cuda.synchronize()
-        log(args, f"[bench] copy calibration: 3 copies of {nel * 4} bytes")
+        log(args, f"[bench] copy calibration: 3 copies of {nel * 4} bytes, then 3 of {nel * 2} bytes in 64-byte segments")
         del src, dst
         torch.cuda.empty_cache()
     fp32_grade = [p for p in ("bf16x3", "fp32") if p in results]
@@ -558,14 +606,37 @@ def main():
                                                                key=lambda p: results[p]["dof_updates_per_s"])
     r = results[primary]
     N = dg.nmodes(k)
+    # achieved: algorithmic bytes over the stage kernel's average launch time (events around each
+    # launch); step_achieved_GBs: the same bytes over dg_step's time per step (CFL reduction included)
     roof = dict(bound="hbm", achieved=round(r["achieved_GBs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(r["achieved_GBs"] / HBM_PEAK_GBS, 4), traffic=None,
+                step_achieved_GBs=round(3 * r["bytes_per_stage_avg"] / (r["ms_per_step"] / 1e3) / 1e9, 1),
                 copy_GBs=round(copy_GBs, 1), frac_of_copy=round(r["achieved_GBs"] / copy_GBs, 4))
     tf = os.path.join(ROOT, "profiles", f"traffic_stage_k{k}_n{n}_{primary}.json")
     if os.path.exists(tf):
         t = json.load(open(tf))
         if t.get("source_hash") == kernel_source_hash():
             roof["traffic"] = t.get("bytes_per_launch")
+    cfgs = None
+    if not args.no_configs:
+        cfgs = {"k2_n64": config_cost(args, dg, torch, 2, 64, ("fp64", "fp32")),
+                "k3_n128": config_cost(args, dg, torch, 3, 128, ("fp64", "fp32", "bf16x3", "bf16"))}
+    # compute roof of the primary tier at k = 3: algorithmic contraction flops against the dense BF16
+    # matrix peak (BF16X3 issues three products per algorithmic one), vector flops against FP32
+    comp = None
+    if k == 3:
+        sec = r["stage_ms"] / 1e3
+        mf = K3_CONTRACTION_FLOPS * n ** 3 / sec / 1e12
+        vf = K3_VECTOR_FLOPS * n ** 3 / sec / 1e12
+        comp = dict(contraction_TFLOPs=round(mf, 2), matrix_peak_TFLOPs=BF16_MATRIX_TFLOPS if primary.startswith("bf16")
+                    else FP32_MATRIX_TFLOPS, vector_TFLOPs=round(vf, 2), vector_peak_TFLOPs=FP32_VECTOR_TFLOPS,
+                    products_per_contraction=3 if primary == "bf16x3" else 1)
+        comp["matrix_frac"] = round(mf * comp["products_per_contraction"] / comp["matrix_peak_TFLOPs"], 4)
+        cf = os.path.join(ROOT, "profiles", f"counters_stage_k{k}_n{n}_{primary}.json")
+        if os.path.exists(cf):
+            c = json.load(open(cf))
+            if c.get("source_hash") == kernel_source_hash():
+                comp["counters"] = {kk: c[kk] for kk in ("valu_busy", "mfma_busy", "wait_frac") if kk in c}
     cpu = None
     if not args.no_cpu_baseline:
         log(args, "[bench] timing the oracle on the host")
@@ -614,6 +685,12 @@ def main():
         line["closure_inference"] = clo
     if k0 is not None:
         line["k0_stage"] = k0
+    if comp is not None:
+        line["compute_roof"] = comp
+    if opo is not None:
+        line["operator_only"] = opo
+    if cfgs is not None:
+        line["configs"] = cfgs
     print(json.dumps(line), flush=True)
 
 

@@ -105,6 +105,15 @@ size_t dg_workspace_bytes(const dg_ctx *ctx);
  * y: DEVICE, dg_state_count elements (output). */
 dg_status dg_project(dg_ctx *ctx, const void *qp, void *y);
 
+/* The state in the canonical order y_c[i][l][z][y][x] (field, mode, then the mesh with x fastest:
+ * one contiguous plane of cells per (field, mode)), converted to (import) or from (export) the
+ * order y[z][y][i][l][x] that every other entry point takes.  The internal order keeps a row's
+ * 5 N(k) weight rows together for the stage kernels' loads; the canonical one is the natural
+ * order of the weights w_{i,l}^K of Sec. 2.  canon, y: DEVICE, dg_state_count elements of the
+ * storage type, distinct (not in place).  DG_ERR_ARG on NULL or identical pointers. */
+dg_status dg_state_import(dg_ctx *ctx, const void *canon, void *y);
+dg_status dg_state_export(dg_ctx *ctx, const void *y, void *canon);
+
 /* r = R(y), the spatial operator of eq. dg:eqn:time (dw/dt + R = 0): the
  * volume integral (eq. dg:eqn:volume_int), the HLLC surface integral
  * (eq. dg:eqn:surface_int) and, with DG_FORCING, minus the driving source
@@ -338,8 +347,8 @@ size_t dg_spectrum_workspace_bytes(const dg_ctx *ctx, int32_t S);
  * so that sum_s P(s) is the grid mean of |v|^2; E(k) = P(s) box/(2 pi) at
  * k = 2 pi s / box.  The transforms are hipFFT real-to-complex (FP32 for the
  * FP32-storage tiers, FP64 for DG_FP64; the plan is made on the first call and
- * kept); shells are summed in FP64 with atomics (the last bits can vary between
- * calls).  out: HOST double [nbins], 1 <= nbins <= 4096, shells >= nbins are
+ * kept); shells are summed in FP64 in a fixed order (bitwise reproducible, and a
+ * shell's value does not depend on nbins).  out: HOST double [nbins], 1 <= nbins <= 4096, shells >= nbins are
  * dropped.  work: DEVICE, dg_spectrum_workspace_bytes(ctx, S).  Synchronises. */
 dg_status dg_velocity_spectrum(dg_ctx *ctx, const void *y, int32_t S, int32_t nbins, double *out, void *work);
 

@@ -230,16 +230,13 @@ class Experiment:
 
 def effective_dof_gain(e1, e8, ec):
     """Per field: the DOF factor at which the plain scheme would reach the closure's error, read off
-    the plain runs at 1x and 8x the cells (error taken as a power of the DOF between them).  Values
-    outside [1, 8] are clipped to the ladder's ends."""
+    the plain runs at 1x and 8x the cells (error taken as a power of the DOF between them).  Not
+    clipped: a value below 1 means the closure is worse than the plain scheme on that field (a
+    coarser plain mesh would match it), above 8 is extrapolated past the ladder."""
     out = []
     for a, b, c in zip(e1, e8, ec):
-        if not (b < a):
+        if not (b < a) or not (c > 0):
             out.append(float("nan"))
-        elif c >= a:
-            out.append(1.0)
-        elif c <= b:
-            out.append(8.0)
         else:
             out.append(float(8.0 ** (math.log(a / c) / math.log(a / b))))
     return out

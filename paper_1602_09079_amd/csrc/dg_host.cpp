@@ -666,6 +666,25 @@ size_t dg_state_count(const dg_ctx *c) { return c ? (size_t)NF * c->N * (size_t)
 
 size_t dg_workspace_bytes(const dg_ctx *c) { return c ? 2 * dg_state_count(c) * elem_bytes(c) : 0; }
 
+static dg_status relayout(dg_ctx *c, const void *src, void *dst, int to_canonical, const char *name) {
+    if (!c) return DG_ERR_ARG;
+    if (!src || !dst || src == dst) {
+        c->err = std::string(name) + ": NULL or identical pointers (the conversion is not in place)";
+        return DG_ERR_ARG;
+    }
+    HIPCHK(c, launch_relayout(c->cfg.precision, src, dst, NF * nmodes_of(c->cfg.k), c->cfg.n[0], c->cfg.n[1],
+                              c->cfg.n[2], to_canonical, c->stream));
+    return DG_OK;
+}
+
+dg_status dg_state_import(dg_ctx *c, const void *canon, void *y) {
+    return relayout(c, canon, y, 0, "dg_state_import");
+}
+
+dg_status dg_state_export(dg_ctx *c, const void *y, void *canon) {
+    return relayout(c, y, canon, 1, "dg_state_export");
+}
+
 dg_status dg_project(dg_ctx *c, const void *qp, void *y) {
     if (!c) return DG_ERR_ARG;
     if (!qp || !y) {

@@ -199,6 +199,8 @@ struct StageArgs {
 };
 
 hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
+hipError_t launch_relayout(int prec, const void *src, void *dst, int nfm, int nx, int ny, int nz, int to_canonical,
+                           hipStream_t s);
 hipError_t set_stage_attributes(int k, int prec, int lds_bytes);
 // the k = 3 BF16-tier kernel (stage_k3.hip)
 hipError_t launch_stage_k3(int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);

@@ -1291,6 +1291,38 @@ hipError_t launch_project(int k, int prec, const void *qp, void *y, const double
     }
 }
 
+// ------------------------------------------------------------------ state relayout at the boundary
+
+// Between the canonical order [i][l][z][y][x] and the internal order [z][y][i][l][x]: both keep x
+// fastest, so every row of nx weights moves whole.  One workgroup per row, the row's x values
+// across the threads (coalesced reads and writes); a data move bound by HBM bandwidth.
+template <class S>
+__global__ __launch_bounds__(256) void relayout_kernel(const S *__restrict__ src, S *__restrict__ dst, int nfm,
+                                                       int ny, int nz, int nx, int to_canonical) {
+    const long long rows = (long long)nfm * ny * nz;
+    for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+        // r numbers the rows in internal order: ((z ny + y) nfm + f), f = i N + l
+        const int f = (int)(r % nfm);
+        const long long zy = r / nfm;
+        const long long rc = (long long)f * ny * nz + zy;  // the same row in canonical order
+        const long long si = (to_canonical ? r : rc) * nx, di = (to_canonical ? rc : r) * nx;
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) dst[di + x] = src[si + x];
+    }
+}
+
+hipError_t launch_relayout(int prec, const void *src, void *dst, int nfm, int nx, int ny, int nz, int to_canonical,
+                           hipStream_t s) {
+    const long long rows = (long long)nfm * ny * nz;
+    const unsigned grid = (unsigned)std::min<long long>(rows, 1LL << 20);
+    if (prec == DG_FP64)
+        hipLaunchKernelGGL(relayout_kernel<double>, dim3(grid), dim3(256), 0, s, static_cast<const double *>(src),
+                           static_cast<double *>(dst), nfm, ny, nz, nx, to_canonical);
+    else
+        hipLaunchKernelGGL(relayout_kernel<float>, dim3(grid), dim3(256), 0, s, static_cast<const float *>(src),
+                           static_cast<float *>(dst), nfm, ny, nz, nx, to_canonical);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ driving acceleration cache (Sec. 3.1)
 
 // a_c(x_q) = sum_m Re(ahat_{m,c} exp(2 pi i n_m . x_q / L)) at every volume point of every

@@ -202,47 +202,71 @@ hipError_t launch_sample(int k, int S, int prec, const SampleArgs &a, const Leg1
 // (kz, ky, kx) has wave vector (kx, ky or ky - M, kz or kz - M); it stands for itself and, for
 // 0 < kx < M/2 (or kx > 0 when M is odd), for its conjugate at -n as well (weight 2).  The shell
 // is the integer nearest to |n|, found in integer arithmetic: s = r + [4 |n|^2 >= (2r + 1)^2],
-// r = floor(sqrt(|n|^2)).  Block sums in LDS, then added to bins (FP64 atomics: the order of the
-// additions, and so the last bits, can vary between runs).
+// r = floor(sqrt(|n|^2)).
+__device__ inline long long shell_of(long long n2) {
+    long long r = (long long)sqrt((double)n2);
+    while (r * r > n2) r--;
+    while ((r + 1) * (r + 1) <= n2) r++;
+    return r + (4 * n2 >= (2 * r + 1) * (2 * r + 1) ? 1 : 0);
+}
+
+// smallest kx >= 0 whose shell (with n_y^2 + n_z^2 = c) is at least s: the shell is nondecreasing
+// in kx, so the kx of one shell form one interval of a row
+__device__ inline long long first_kx(long long c, long long s) {
+    const double t = ((double)s - 0.5) * ((double)s - 0.5) - (double)c;
+    long long x = t > 0.0 ? (long long)sqrt(t) : 0;
+    while (x > 0 && shell_of((x - 1) * (x - 1) + c) >= s) x--;
+    while (shell_of(x * x + c) < s) x++;
+    return x;
+}
+
+// One workgroup per shell s < nbins, no atomics: the pairs (n_y, n_z) of the square |n_y|, |n_z| <=
+// s + 1 are dealt to the threads in a fixed order, each thread adds the kx interval of shell s of
+// each of its rows in order, and the workgroup adds the threads' sums in a fixed tree; the shell's
+// bin then takes the sum (the three velocity components in turn, in stream order).  Bitwise
+// reproducible.
 template <class C>
 __global__ __launch_bounds__(256) void shells_kernel(const C *__restrict__ spec, int M, int nbins, double scale,
                                                      double *__restrict__ bins) {
-    __shared__ double hb[DIAG_MAX_BINS];
-    for (int j = threadIdx.x; j < nbins; j += blockDim.x) hb[j] = 0.0;
-    __syncthreads();
-    const int Mh = M / 2 + 1;
-    const long long total = (long long)M * M * Mh;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        const int kx = (int)(e % Mh);
-        const long long rest = e / Mh;
-        const int ky = (int)(rest % M), kz = (int)(rest / M);
-        const long long ny = ky <= M / 2 ? ky : ky - M, nz = kz <= M / 2 ? kz : kz - M;
-        const long long n2 = (long long)kx * kx + ny * ny + nz * nz;
-        long long r0 = (long long)sqrt((double)n2);
-        while (r0 * r0 > n2) r0--;
-        while ((r0 + 1) * (r0 + 1) <= n2) r0++;
-        const long long sh = r0 + (4 * n2 >= (2 * r0 + 1) * (2 * r0 + 1) ? 1 : 0);
-        if (sh < nbins) {
-            const double re = (double)spec[2 * e], im = (double)spec[2 * e + 1];
+    __shared__ double red[256];
+    const long long s = blockIdx.x;
+    const long long Mh = M / 2 + 1;
+    const long long nlo = -((M - 1) / 2), nhi = M / 2;  // signed wave numbers of a full axis
+    const long long R = s + 1 < nhi ? s + 1 : nhi;
+    const long long side = 2 * R + 1;
+    double acc = 0.0;
+    for (long long p = threadIdx.x; p < side * side; p += blockDim.x) {
+        const long long ny = p % side - R, nz = p / side - R;
+        if (ny < nlo || nz < nlo) continue;
+        const long long c = ny * ny + nz * nz;
+        if (shell_of(c) > s) continue;
+        const long long a0 = first_kx(c, s);
+        long long a1 = first_kx(c, s + 1) - 1;
+        if (a1 > Mh - 1) a1 = Mh - 1;
+        const long long ky = ny >= 0 ? ny : ny + M, kz = nz >= 0 ? nz : nz + M;
+        const C *row = spec + 2 * ((kz * M + ky) * Mh);
+        for (long long kx = a0; kx <= a1; kx++) {
+            const double re = (double)row[2 * kx], im = (double)row[2 * kx + 1];
             const bool self_conj = kx == 0 || (M % 2 == 0 && kx == M / 2);
-            atomicAdd(&hb[sh], (re * re + im * im) * scale * (self_conj ? 1.0 : 2.0));
+            acc += (re * re + im * im) * (self_conj ? 1.0 : 2.0);
         }
     }
+    red[threadIdx.x] = acc;
     __syncthreads();
-    for (int j = threadIdx.x; j < nbins; j += blockDim.x)
-        if (hb[j] != 0.0) atomicAdd(&bins[j], hb[j]);
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bins[s] += red[0] * scale;
 }
 
 hipError_t launch_shells(int prec, const void *spec, int M, int nbins, double scale, double *bins, hipStream_t s) {
-    const long long total = (long long)M * M * (M / 2 + 1);
-    long long nb = (total + 255) / 256;
-    if (nb > 4096) nb = 4096;
     if (prec == DG_FP64)
-        hipLaunchKernelGGL(shells_kernel<double>, dim3(nb), dim3(256), 0, s, (const double *)spec, M, nbins, scale,
+        hipLaunchKernelGGL(shells_kernel<double>, dim3(nbins), dim3(256), 0, s, (const double *)spec, M, nbins, scale,
                            bins);
     else
-        hipLaunchKernelGGL(shells_kernel<float>, dim3(nb), dim3(256), 0, s, (const float *)spec, M, nbins, scale, bins);
+        hipLaunchKernelGGL(shells_kernel<float>, dim3(nbins), dim3(256), 0, s, (const float *)spec, M, nbins, scale,
+                           bins);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ EXPORTS = ["dg_init", "dg_destroy", "dg_state_count", "dg_workspace_bytes", "dg_
            "dg_column_stats_workspace_bytes", "dg_column_stats", "dg_column_stats_noalloc", "dg_standardize", "dg_limiter_stats",
            "dg_set_isothermal", "dg_isothermal_reset", "dg_dissipated", "dg_sample",
            "dg_spectrum_workspace_bytes", "dg_velocity_spectrum", "dg_density_pdf", "dg_rms_mach",
-           "dg_plane_count", "dg_set_halo", "dg_set_slab", "dg_set_zchunk"]
+           "dg_plane_count", "dg_set_halo", "dg_set_slab", "dg_set_zchunk", "dg_state_import", "dg_state_export"]
 
 
 class DGError(RuntimeError):
@@ -81,6 +81,8 @@ def lib():
             "dg_state_count": (ctypes.c_size_t, [_vp]),
             "dg_workspace_bytes": (ctypes.c_size_t, [_vp]),
             "dg_project": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_state_import": (ctypes.c_int, [_vp, _vp, _vp]),
+            "dg_state_export": (ctypes.c_int, [_vp, _vp, _vp]),
             "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp]),
             "dg_stage": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
             "dg_dt": (ctypes.c_int, [_vp, _vp, _dp]),
@@ -240,6 +242,10 @@ class Solver:
         """[z][y][i][l][x]: each row of cells holds its 5 N rows of weights contiguously."""
         return (self.n[2], self.n[1], 5, self.N, self.n[0])
 
+    def canonical_shape(self):
+        """[i][l][z][y][x]: one plane of cells per (field, mode)."""
+        return (5, self.N, self.n[2], self.n[1], self.n[0])
+
     def empty_state(self):
         import torch
         return torch.empty(self.state_shape(), dtype=self.dtype, device=self.device)
@@ -267,6 +273,21 @@ class Solver:
         self._check(lib().dg_project(self._ctx, self._ptr(qp, shape), self._ptr(y, self.state_shape())),
                     "dg_project")
         return y
+
+    def import_state(self, canon, out=None):
+        """State from the canonical order [i][l][z][y][x] into the library's order."""
+        y = self.empty_state() if out is None else out
+        self._check(lib().dg_state_import(self._ctx, self._ptr(canon, self.canonical_shape()),
+                                          self._ptr(y, self.state_shape())), "dg_state_import")
+        return y
+
+    def export_state(self, y, out=None):
+        """The library's state in the canonical order [i][l][z][y][x]."""
+        import torch
+        c = torch.empty(self.canonical_shape(), dtype=self.dtype, device=self.device) if out is None else out
+        self._check(lib().dg_state_export(self._ctx, self._ptr(y, self.state_shape()),
+                                          self._ptr(c, self.canonical_shape())), "dg_state_export")
+        return c
 
     def rhs(self, y, out=None):
         r = self.empty_state() if out is None else out

@@ -66,7 +66,7 @@ def test_sample_parity(dgm, k, S, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("k,n,S", [(2, 8, 4), (3, 5, 3), (1, 6, 4), (4, 5, 4)])
+@pytest.mark.parametrize("k,n,S", [(2, 8, 4), (3, 5, 3), (1, 6, 4), (4, 5, 4), (3, 25, 4)])
 def test_velocity_spectrum_parity(dgm, k, n, S, prec):
     cfg, y = state(k, n, 30 + k, density=0.2)
     M = S * n
@@ -77,8 +77,10 @@ def test_velocity_spectrum_parity(dgm, k, n, S, prec):
     tot = want.sum()
     err = np.abs(got - want).max() / tot
     assert err <= (1e-12 if prec == "fp64" else 1e-5), err
-    # fewer shells: the same leading values
-    np.testing.assert_allclose(s.velocity_spectrum(yd, S, 5), got[:5], rtol=1e-12, atol=1e-15 * tot)
+    # shells summed in a fixed order: the same bits on a second call, and with fewer shells the
+    # same leading values
+    np.testing.assert_array_equal(s.velocity_spectrum(yd, S, M), got)
+    np.testing.assert_array_equal(s.velocity_spectrum(yd, S, 5), got[:5])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

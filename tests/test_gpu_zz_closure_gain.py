@@ -12,7 +12,10 @@ Pass bar on the test window:
   plain one, in every field (a-priori);
 * over the horizon (0.1 time units), the evolution of the corrected coarse run
   is closer to the restricted fine evolution than the plain run's, on average
-  over the five fields (a-posteriori), with the total mass conserved;
+  over the five fields (a-posteriori), and no field's evolution error exceeds
+  the plain run's by more than 2% (the training is stochastic; the density
+  row, whose correction is the smallest, may gain nothing), with the total mass
+  conserved;
 * accuracy per DOF: a plain k = 1 run with 8x the cells (the fine mesh, from
   the fine state's degree-1 modes) sets the other end of a DOF ladder; the
   closure's effective DOF gain per field is read off between the two plain
@@ -44,10 +47,12 @@ def test_closure_gains_over_plain_scheme():
     cl = test[f"alpha={res['alpha']}"]
     assert np.all(np.array(cl["rhs_err"]) < np.array(plain["rhs_err"])), (cl["rhs_err"], plain["rhs_err"])
     assert np.mean(cl["err"]) < np.mean(plain["err"]), (cl["err"], plain["err"])
+    assert np.all(np.array(cl["err"]) <= 1.02 * np.array(plain["err"])), (cl["err"], plain["err"])
     assert cl["fallback_rate"] < 0.05
     # the DOF ladder: plain k = 1 with 8x the cells is closer to the reference in every field, and the
-    # closure's effective DOF gain is read off between the two plain runs (reported, not a bar)
+    # closure's effective DOF gain is read off between the two plain runs (reported unclipped: below 1
+    # where the closure loses); it gains on some field
     assert np.all(np.array(test["plain_8x_dof"]["err"]) < np.array(plain["err"]))
     g = np.array(res["effective_dof_gain"])
-    assert np.all((g >= 1.0) & (g <= 8.0)) and np.max(g) > 1.0, g
+    assert np.all(np.isfinite(g)) and np.max(g) > 1.0, g
     assert cl["totals_drift"][0] < 1e-5  # mass: the driving adds momentum and energy, never mass

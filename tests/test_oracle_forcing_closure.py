@@ -260,3 +260,12 @@ def test_closure_network_and_zero_sum_means():
     np.testing.assert_allclose(got[:, 1:], c[:, 1:], rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(got[:, 0], c[:, 0] - c[:, 0].mean(axis=1, keepdims=True), rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(got[:, 0].sum(axis=1), 0.0, atol=1e-12)
+
+
+def test_effective_dof_gain_reads_the_ladder_unclipped():
+    """Host logic of the closure report: the plain errors at 1x and 8x the cells fix a power law in
+    the DOF; the closure's error maps to a DOF factor, below 1 when it loses to the plain scheme."""
+    from paper_1602_09079_amd.closure import effective_dof_gain
+    g = effective_dof_gain([1.0, 1.0, 1.0, 1.0, 1.0], [0.5, 0.5, 0.5, 0.25, 1.0], [0.5, 1.0, 2.0, 0.5, 0.9])
+    assert np.allclose(g[:4], [8.0, 1.0, 0.125, 8.0 ** 0.5])
+    assert np.isnan(g[4])  # no ladder when the finer plain run is not better
