@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdgmi.so")
+# DGMI_LIB: another build of the same library to load (the tests use it for an instrumented build)
+LIB_PATH = os.environ.get("DGMI_LIB") or os.path.join(HERE, "libdgmi.so")
 
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_RANGE, DG_ERR_STATE = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
