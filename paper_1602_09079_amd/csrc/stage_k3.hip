@@ -290,6 +290,20 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             for (int r = 0; r < 4; r++) tr[i][r] = t[r] + b.qbar[i];
         }
     };
+    // two faces of one block from one operand per field
+    auto trace2 = [&](int f1, int f2, const B3 &b, C tr1[NF][4], C tr2[NF][4]) {
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            const OP op = wop(b, i);
+            const Acc t1 = mma(Acc{0, 0, 0, 0}, K3_T3 + f1, op);
+            const Acc t2 = mma(Acc{0, 0, 0, 0}, K3_T3 + f2, op);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                tr1[i][r] = t1[r] + b.qbar[i];
+                tr2[i][r] = t2[r] + b.qbar[i];
+            }
+        }
+    };
     // the trace on face f of the end row copied into LDS buffer e
     auto trace_lds = [&](int f, int e, C tr[NF][4]) {
         // vmcnt(0): the copies have landed (the compiler does not track them); the memory clobber
@@ -712,7 +726,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             // neighbour's +x trace in the adjacent lane), the +x flux from the right neighbour's
             // -x flux, and for a full block the face on its high edge
             {
-                C tl[NF][4], Fxp[NF][4];
+                C tl[NF][4], Fxp[NF][4], tm[NF][4];
                 {
                     C tp[NF][4], tg[NF][4];
                     {
@@ -732,7 +746,12 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     // the copies read above have been used: their slots take the next step's
                     __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
                     if (z + 1 < z1) ghost_dma(cidx(iy, z + 1), xgl, xgr);
-                    trace(1, cur, tp);
+                    // BF16: both x traces of the block from one operand (BF16X3 has not the registers
+                    // to keep the second across the edge face)
+                    if constexpr (X3)
+                        trace(1, cur, tp);
+                    else
+                        trace2(1, 0, cur, tp, tm);
                     if (vc == K3_BLK) {
                         // the 16 points of column 15's +x face, one per lane of columns 12..15
                         C ql[5], qr[5], fo[5];
@@ -766,11 +785,8 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         }
                 }
                 C Fxm[NF][4];
-                {
-                    C tm[NF][4];
-                    trace(0, cur, tm);
-                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fxm);
-                }
+                if constexpr (X3) trace(0, cur, tm);
+                riemann(std::integral_constant<int, 0>{}, tl, tm, Fxm);
                 // the + face flux of a column is the - face flux of its right neighbour; column 15
                 // of a full block keeps the flux of its high edge
                 const bool edge = vc == K3_BLK && col == 15;
