@@ -323,16 +323,18 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // The ghost cells of the x faces (the cell before the block and the cell after it), copied into
     // LDS by the load unit one z step ahead, four 64-lane copies per wave: lane (g, c) copies value
     // 4 (c % 8) + k in copy k of the cell before (c < 8) or after (c >= 8) for lane group g; value
-    // e = 6 i + m of a cell is field i's mean (m = 0) or its slot m - 1.  xgl, xgr: the two cells'
-    // byte offsets in a row.
+    // e = 6 i + m of a cell is field i's mean (m = 0) or its slot m - 1.  x0: the block's first
+    // cell (wave-uniform).
     C *ex_g = reinterpret_cast<C *>(lds + a.ex_off4) + wave * 4 * 64;
-    auto ghost_dma = [&](long long r, unsigned xgl, unsigned xgr) {
+    auto ghost_dma = [&](long long r, int x0) {
         const auto rs = slab_rsrc(yin, slabn, r);
+        const int xr = x0 + K3_BLK;
+        const unsigned xgl = (unsigned)(x0 == 0 ? nx - 1 : x0 - 1) * 4u, xgr = (unsigned)(xr >= nx ? xr - nx : xr) * 4u;
         // lane values made opaque here: the offsets are formed at each use instead of being kept
         // in registers across the sweep
-        unsigned cx = col < 8 ? xgl : xgr;
         int ln = lane;
-        asm volatile("" : "+v"(cx), "+v"(ln));
+        asm volatile("" : "+v"(ln));
+        const unsigned cx = (ln & 15) < 8 ? xgl : xgr;
         const int gg = ln >> 4, c8 = ln & 7;
         asm volatile("" ::: "memory");
 #pragma unroll
@@ -626,7 +628,6 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         // the ghost columns: column 0 reads the cell before the block, column 15 (full blocks)
         // the cell after it
         const bool gl = col == 0, gr = col == 15 && vc == K3_BLK;
-        const unsigned xgl = (unsigned)(x0 == 0 ? nx - 1 : x0 - 1) * 4u, xgr = (unsigned)((x0 + K3_BLK) % nx) * 4u;
         if constexpr (FORCE) {
 #pragma unroll
             for (int s = 0; s < K3_DKS; s++) csv[s] = a.dcs[((long long)xc * K3_DKS + s) * 4 + g];
@@ -638,7 +639,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         };
 
         // the host guarantees the end-row and ghost regions (a.ex_off3, a.ex_off4 >= 0)
-        ghost_dma(cidx(iy, z0), xgl, xgr);
+        ghost_dma(cidx(iy, z0), x0);
         if (act) {
             if (wrow == 0) load_lds(cidx(iy0 - 1, z0), 0);
             if (wrow == nact - 1) load_lds(cidx(iy0 + nact, z0), 1);
@@ -671,18 +672,21 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             const float *drow = FORCE ? a.dtab + cidx(iy, z) * k3_drive_row_floats(K3_DKS) : nullptr;
             volume(cur, acc, drow);
             // y faces shared by the rows of the workgroup: each face flux is solved once, by the
-            // row below it; the faces at the group's ends use the neighbour rows' weights
-            C Fym[NF][4];  // -y face flux of this row
+            // row below it; the faces at the group's ends use the neighbour rows' weights.  Row 0
+            // solves its -y face itself and parks the flux in its own trace slot (which no other
+            // row reads), so that nothing is held in registers across the two barriers
             C Fyp[NF][4];  // +y face flux of this row
             {
                 C tm[NF][4];
                 trace(2, cur, tm);
-                ex_put(ex_t, wrow, tm);
                 if (wrow == 0) {
-                    C tb[NF][4];
+                    C tb[NF][4], f0[NF][4];
                     trace_lds(3, 0, tb);
                     if (z + 1 < z1) load_lds(cidx(iy0 - 1, z + 1), 0);  // reads consumed above
-                    riemann(std::integral_constant<int, 1>{}, tb, tm, Fym);
+                    riemann(std::integral_constant<int, 1>{}, tb, tm, f0);
+                    ex_put(ex_t, 0, f0);
+                } else {
+                    ex_put(ex_t, wrow, tm);
                 }
             }
             lds_barrier();
@@ -700,9 +704,9 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             }
             lds_barrier();
             // the stage-combine input y0 (stages 2 and 3): slots 0..3 copied by the load unit into
-            // this wave's trace slot (free until the next step's puts), slot 4 loaded into registers;
-            // requested now, so the round trip hides behind the remaining faces
-            C y04[NF];
+            // this wave's trace slot (free until the next step's puts), requested now, so the round
+            // trip hides behind the remaining faces; slot 4 is loaded into registers before the last
+            // lift (held from here it would be spilled)
             auto y0_copy = [&]() {
                 if (dma_y0 && act) {
                     const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
@@ -713,15 +717,17 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(
                                 r0, (__attribute__((address_space(3))) void *)(ex_t + ((wrow * NF + i) * 4 + u) * 64),
                                 4, roff[u] + xoff, (int)((unsigned)i * fbytes), 0, 0);
-#pragma unroll
-                    for (int i = 0; i < NF; i++) y04[i] = bload(0.0f, r0, roff[4] + xoff, (unsigned)i * fbytes);
                 }
             };
+            C Fym[NF][4];  // -y face flux of this row: the +y flux of the row below, or row 0's own
+            ex_get(wrow > 0 ? ex_f : ex_t, wrow > 0 ? wrow - 1 : 0, Fym);
+            // the reads above have returned before the copy of y0 overwrites this wave's trace slot
+            __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
             y0_copy();
-            if (wrow > 0) ex_get(ex_f, wrow - 1, Fym);
             lift(1, cur, Fym, Fyp, acc);
             B3 nxt;
             loadz(iy, z + 1, nxt);
+            C y044 = C(0);  // slot 4 of field 4 of y0 (stages 2 and 3)
             // x faces: own traces, the ghost cells' traces, the -x face of every column (its left
             // neighbour's +x trace in the adjacent lane), the +x flux from the right neighbour's
             // -x flux, and for a full block the face on its high edge
@@ -732,10 +738,10 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     {
                         // the ghost cells from their copy in LDS.  The copies were requested in the
                         // previous step (or before the first) and requests complete in order: the 30
-                        // loads of the next block and, in stages 2 and 3, the 25 of y0 were issued
-                        // after them
+                        // loads of the next block and, in stages 2 and 3, the 20 copies of y0 were
+                        // issued after them
                         if (dma_y0 && act)
-                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + NF * NSL));
+                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + NF * 4));
                         else
                             __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL)));
                         asm volatile("" ::: "memory");
@@ -743,9 +749,20 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         ghost_read(gr, gb);
                         trace(1, gb, tg);  // column 0: +x trace of the cell before; 15: -x trace after
                     }
-                    // the copies read above have been used: their slots take the next step's
+                    // the copies read above have been used: until the combine, their slots take slot 4
+                    // of y0 for fields 0..3 (stages 2 and 3); field 4's is loaded into a register
                     __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
-                    if (z + 1 < z1) ghost_dma(cidx(iy, z + 1), xgl, xgr);
+                    if (dma_y0 && act) {
+                        const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                r0, (__attribute__((address_space(3))) void *)(ex_g + i * 64), 4, roff[4] + xoff,
+                                (int)((unsigned)i * fbytes), 0, 0);
+                        asm volatile("" ::: "memory");
+                        y044 = bload(0.0f, r0, roff[4] + xoff, 4u * fbytes);
+                    }
                     // BF16: both x traces of the block from one operand (BF16X3 has not the registers
                     // to keep the second across the edge face)
                     if constexpr (X3)
@@ -821,19 +838,19 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     const C ca = (C)a.a, cb = (C)a.b;
                     C y0v[NF][NSL];
                     if (dma_y0) {
-                        // slot 4 loaded after the y faces; slots 0..3 were copied into this wave's trace slot
-#pragma unroll
-                        for (int i = 0; i < NF; i++) y0v[i][4] = y04[i];
-                        // the copies into LDS have landed (the compiler does not track them): requests
-                        // complete in order, and the slot-4 loads and the next step's ghost copies (if
-                        // any) were issued after them; the memory clobber keeps the LDS reads below the
-                        // wait
-                        __builtin_amdgcn_s_waitcnt(wait_vm(4));
+                        // slots 0..3 were copied into this wave's trace slot after the y faces, slot 4 of
+                        // fields 0..3 into its ghost slots after the ghost cells were read; vmcnt(0):
+                        // the copies have landed (the compiler does not track them); the memory clobber
+                        // keeps the LDS reads below the wait
+                        __builtin_amdgcn_s_waitcnt(wait_vm(0));
                         asm volatile("" ::: "memory");
 #pragma unroll
                         for (int i = 0; i < NF; i++)
 #pragma unroll
                             for (int s = 0; s < 4; s++) y0v[i][s] = ex_t[((wrow * NF + i) * 4 + s) * 64 + lane];
+#pragma unroll
+                        for (int i = 0; i < 4; i++) y0v[i][4] = ex_g[i * 64 + lane];
+                        y0v[4][4] = y044;
                     } else {
 #pragma unroll
                         for (int i = 0; i < NF; i++)
@@ -848,6 +865,11 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                             bstore(res, ro, roff[s] + xoff, (unsigned)i * fbytes);
                         }
                 }
+            }
+            // the next step's ghost cells, now that the combine has read slot 4 of y0 from their slots
+            if (z + 1 < z1) {
+                __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+                ghost_dma(cidx(iy, z + 1), x0);
             }
             cur = nxt;
         }
