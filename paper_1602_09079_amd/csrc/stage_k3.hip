@@ -192,6 +192,14 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     // this lane's byte offset in a fragment; the empty asm keeps fragment reads where they are used
     int toff = lane * 16;
     auto refresh = [&]() { asm volatile("" : "+v"(toff)); };
+    // LDS accesses address one lane base plus immediate offsets: the lane index is made opaque at
+    // each use, so that the compiler does not hoist a register per element out of the sweep (and
+    // spill them: a spill reload waits for every load in flight)
+    auto lane_base = [&]() {
+        int o = lane;
+        asm volatile("" : "+v"(o));
+        return o;
+    };
     auto mma = [&](Acc c, int frag, const OP &b) -> Acc {
         const bf8 ah = *reinterpret_cast<const bf8 *>(lds + frag * K3_FRAG + toff);
         if constexpr (X3) {
@@ -310,13 +318,13 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         // keeps the LDS reads below the wait
         __builtin_amdgcn_s_waitcnt(wait_vm(0));
         asm volatile("" ::: "memory");
-        const C *src = ex_e + e * ERV * 64;
+        const C *src = ex_e + e * ERV * 64 + lane_base();
         B3 b;
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            b.qbar[i] = src[(i * (1 + NSL)) * 64 + lane];
+            b.qbar[i] = src[(i * (1 + NSL)) * 64];
 #pragma unroll
-            for (int s = 0; s < NSL; s++) b.v[i][s] = src[(i * (1 + NSL) + 1 + s) * 64 + lane];
+            for (int s = 0; s < NSL; s++) b.v[i][s] = src[(i * (1 + NSL) + 1 + s) * 64];
         }
         trace(f, b, tr);
     };
@@ -587,16 +595,18 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     C *ex_f = reinterpret_cast<C *>(lds + a.ex_off2);
     const bool dma_y0 = a.mode != 0 && a.a != 0.0;  // stages 2 and 3 read y0
     auto ex_put = [&](C *ex, int slot, const C vv[NF][4]) {
+        C *p = ex + slot * NF * 4 * 64 + lane_base();
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) ex[((slot * NF + i) * 4 + r) * 64 + lane] = vv[i][r];
+            for (int r = 0; r < 4; r++) p[(i * 4 + r) * 64] = vv[i][r];
     };
     auto ex_get = [&](const C *ex, int slot, C vv[NF][4]) {
+        const C *p = ex + slot * NF * 4 * 64 + lane_base();
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) vv[i][r] = ex[((slot * NF + i) * 4 + r) * 64 + lane];
+            for (int r = 0; r < 4; r++) vv[i][r] = p[(i * 4 + r) * 64];
     };
 
     // ---------------- work items: (x-block, group of YROWS rows, z chunk), x-block fastest
@@ -844,12 +854,14 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         // keeps the LDS reads below the wait
                         __builtin_amdgcn_s_waitcnt(wait_vm(0));
                         asm volatile("" ::: "memory");
+                        const C *y0s = ex_t + wrow * NF * 4 * 64 + lane_base();
+                        const C *y0g = ex_g + lane_base();
 #pragma unroll
                         for (int i = 0; i < NF; i++)
 #pragma unroll
-                            for (int s = 0; s < 4; s++) y0v[i][s] = ex_t[((wrow * NF + i) * 4 + s) * 64 + lane];
+                            for (int s = 0; s < 4; s++) y0v[i][s] = y0s[(i * 4 + s) * 64];
 #pragma unroll
-                        for (int i = 0; i < 4; i++) y0v[i][4] = ex_g[i * 64 + lane];
+                        for (int i = 0; i < 4; i++) y0v[i][4] = y0g[i * 64];
                         y0v[4][4] = y044;
                     } else {
 #pragma unroll
