@@ -438,10 +438,9 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
                 for (int s = 0; s < K3_DKS; s++) hn[c][s] = drow[(c * 4 * K3_DKS + s) * 64 + lane];
         }
-        // the weights' operands, formed once for the four nodes where the registers allow it (the
-        // driving source needs them for its own operands)
-        OP w5[FORCE ? 1 : NF];
-        if constexpr (!FORCE) {
+        // the weights' operands, formed once for the four nodes
+        OP w5[NF];
+        {
 #pragma unroll
             for (int i = 0; i < NF; i++) w5[i] = wop(b, i);
         }
@@ -450,7 +449,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             refresh();
             Acc d[NF];
 #pragma unroll
-            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, FORCE ? wop(b, i) : w5[i]);
+            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, w5[i]);
             // the driving acceleration of the node (issued after the x/y chunk, below)
             Acc av[3] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
             float ha[3][K3_DKS];
@@ -773,12 +772,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         asm volatile("" ::: "memory");
                         y044 = bload(0.0f, r0, roff[4] + xoff, 4u * fbytes);
                     }
-                    // BF16: both x traces of the block from one operand (BF16X3 has not the registers
-                    // to keep the second across the edge face)
-                    if constexpr (X3)
-                        trace(1, cur, tp);
-                    else
-                        trace2(1, 0, cur, tp, tm);
+                    trace2(1, 0, cur, tp, tm);  // both x traces of the block from one operand
                     if (vc == K3_BLK) {
                         // the 16 points of column 15's +x face, one per lane of columns 12..15
                         C ql[5], qr[5], fo[5];
@@ -812,7 +806,6 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         }
                 }
                 C Fxm[NF][4];
-                if constexpr (X3) trace(0, cur, tm);
                 riemann(std::integral_constant<int, 0>{}, tl, tm, Fxm);
                 // the + face flux of a column is the - face flux of its right neighbour; column 15
                 // of a full block keeps the flux of its high edge
