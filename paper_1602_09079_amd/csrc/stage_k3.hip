@@ -314,9 +314,12 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     };
     // the trace on face f of the end row copied into LDS buffer e
     auto trace_lds = [&](int f, int e, C tr[NF][4]) {
-        // vmcnt(0): the copies have landed (the compiler does not track them); the memory clobber
-        // keeps the LDS reads below the wait
-        __builtin_amdgcn_s_waitcnt(wait_vm(0));
+        // the copies have landed (the compiler does not track them): requests complete in order,
+        // and the 30 loads of a block and 4 ghost copies, at least, were issued after them (one
+        // step ahead: the next block's loads and the end-of-step ghost copies; before the first
+        // step: the first block's and the one before it); the memory clobber keeps the LDS reads
+        // below the wait
+        __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + 4));
         asm volatile("" ::: "memory");
         const C *src = ex_e + e * ERV * 64 + lane_base();
         B3 b;
@@ -685,9 +688,10 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             // solves its -y face itself and parks the flux in its own trace slot (which no other
             // row reads), so that nothing is held in registers across the two barriers
             C Fyp[NF][4];  // +y face flux of this row
+            C tp[NF][4];   // +y trace, formed with the -y one from the same operands
             {
                 C tm[NF][4];
-                trace(2, cur, tm);
+                trace2(2, 3, cur, tm, tp);
                 if (wrow == 0) {
                     C tb[NF][4], f0[NF][4];
                     trace_lds(3, 0, tb);
@@ -700,8 +704,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             }
             lds_barrier();
             {
-                C tp[NF][4], ta[NF][4];
-                trace(3, cur, tp);
+                C ta[NF][4];
                 if (wrow == nact - 1) {
                     trace_lds(2, 1, ta);
                     if (z + 1 < z1) load_lds(cidx(iy0 + nact, z + 1), 1);  // reads consumed above
