@@ -16,6 +16,7 @@
 // (2n)^3 cells onto degree kc on n^3 cells, a fixed linear map per child cell
 // built on the host from the library's own basis and Gauss rules.
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -25,11 +26,33 @@ namespace dgmi {
 
 typedef float f4c __attribute__((ext_vector_type(4)));
 
+// closure inference: 8 waves per workgroup; the weight fragments in LDS (floats)
+constexpr int CL_THREADS = 512;
+constexpr int CL_W1F = 8 * 35 * 64;     // layer 1: 8 output tiles x 35 K steps
+constexpr int CL_W2F = 8 * 4 * 8 * 64;  // layer 2: 32 K steps x 8 output tiles
+constexpr int CL_W3F = 8 * 4 * 2 * 64;  // layer 3: 32 K steps x 2 output tiles (rows 20..31 zero)
+constexpr int CL_LDS = (CL_W1F + CL_W2F + CL_W3F) * 4;
+
 __device__ inline f4c mfma4(float a, float b, f4c c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// tanh for the inference activations from the identity tanh x = sign(x) (1 - e) / (1 + e),
+// e = exp(-2|x|) in (0, 1] (no overflow), with the hardware base-2 exponential and reciprocal:
+// absolute error a few 1e-7, which the FP32 accumulations that follow do not resolve
+__device__ inline float tanh_act(float x) {
+    const float e = __builtin_amdgcn_exp2f(-2.0f * 1.4426950408889634f * __builtin_fabsf(x));
+    return __builtin_copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+}
 
 // ------------------------------------------------------------------ inference
 
-// One wave evaluates 16 consecutive cells (the MFMA columns).  MFMA lane
+// A persistent grid of one 8-wave workgroup per compute unit: the workgroup
+// first copies the three weight matrices into LDS in the order the MFMA A
+// operand takes them (a fragment of 64 floats per K step and output tile,
+// lane l at position l: conflict-free 4-byte reads), 151 KB, then each wave
+// takes groups of 16 consecutive cells in turn.  Read from L2 for every group
+// instead, the weights cost about 600 loads per group and wave.
+//
+// A wave evaluates 16 consecutive cells (the MFMA columns).  MFMA lane
 // layout (16x16x4, FP32): lane l feeds A[l%16][l/16] and B[l/16][l%16] and
 // receives C[4(l/16) + r][l%16], r = 0..3.
 //  * layer 1: K-step s = 5 j + i (neighbour j, field i), lane group g = mode l,
@@ -40,132 +63,153 @@ __device__ inline f4c mfma4(float a, float b, f4c c) { return __builtin_amdgcn_m
 //  * output tile 0 row 4 g + r is field g, mode r; tile 1 rows 16..19 are
 //    field 4 (lane group 0).
 template <class S>
-__global__ __launch_bounds__(256) void closure_kernel(ClosureArgs a) {
+__global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
+    extern __shared__ float wl[];
+    {
+        const float *W1 = a.params;
+        const float *W2 = W1 + CL_NH * CL_NIN + CL_NH;
+        const float *W3 = W2 + CL_NH * CL_NH + CL_NH;
+        for (int e = threadIdx.x; e < CL_W1F; e += CL_THREADS) {  // [t][s][lane]
+            const int l = e & 63, s = (e >> 6) % 35, t = (e >> 6) / 35;
+            wl[e] = W1[(16 * t + (l & 15)) * CL_NIN + 4 * s + (l >> 4)];
+        }
+        for (int e = threadIdx.x; e < CL_W2F; e += CL_THREADS) {  // [t][r][u][lane]
+            const int l = e & 63, u = (e >> 6) & 7, r = (e >> 9) & 3, t = e >> 11;
+            wl[CL_W1F + e] = W2[(16 * u + (l & 15)) * CL_NH + 16 * t + 4 * (l >> 4) + r];
+        }
+        for (int e = threadIdx.x; e < CL_W3F; e += CL_THREADS) {  // [t][r][tile][lane], rows past 20 zero
+            const int l = e & 63, tile = (e >> 6) & 1, r = (e >> 7) & 3, t = e >> 9;
+            const int row = 16 * tile + (l & 15);
+            wl[CL_W1F + CL_W2F + e] = row < CL_NOUT ? W3[row * CL_NH + 16 * t + 4 * (l >> 4) + r] : 0.0f;
+        }
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
-    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int col = lane & 15;
     const int g = lane >> 4;
-    const long long cell0 = wave * 16;
-    if (cell0 >= a.ncells) return;  // wave-uniform
-    const bool live = cell0 + col < a.ncells;
-    const long long cell = live ? cell0 + col : a.ncells - 1;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int x = (int)(cell % nx);
-    const long long rr = cell / nx;
-    const int yy = (int)(rr % ny), zz = (int)(rr / ny);
-    const long long slabn = (long long)CL_ROWS * nx;  // 5 fields x 4 modes rows per slab
-    auto at = [&](int dx, int dy, int dz) -> long long {
-        int xi = x + dx, yi = yy + dy, zi = zz + dz;
-        xi = xi < 0 ? xi + nx : (xi >= nx ? xi - nx : xi);
-        yi = yi < 0 ? yi + ny : (yi >= ny ? yi - ny : yi);
-        zi = zi < 0 ? zi + nz : (zi >= nz ? zi - nz : zi);
-        return ((long long)zi * ny + yi) * slabn + xi;
-    };
-    long long base[7];
-    base[0] = at(0, 0, 0);
-    base[1] = at(-1, 0, 0);
-    base[2] = at(1, 0, 0);
-    base[3] = at(0, -1, 0);
-    base[4] = at(0, 1, 0);
-    base[5] = at(0, 0, -1);
-    base[6] = at(0, 0, 1);
-    const S *y = reinterpret_cast<const S *>(a.y);
-    const float *W1 = a.params;
-    const float *b1 = W1 + CL_NH * CL_NIN;
-    const float *W2 = b1 + CL_NH;
-    const float *b2 = W2 + CL_NH * CL_NH;
-    const float *W3 = b2 + CL_NH;
-    const float *b3 = W3 + CL_NOUT * CL_NH;
+    const long long ntasks = (a.ncells + 15) / 16;
+    for (long long wave = (long long)blockIdx.x * (CL_THREADS / 64) + (threadIdx.x >> 6); wave < ntasks;
+         wave += (long long)gridDim.x * (CL_THREADS / 64)) {
+        const long long cell0 = wave * 16;
+        const bool live = cell0 + col < a.ncells;
+        const long long cell = live ? cell0 + col : a.ncells - 1;
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x = (int)(cell % nx);
+        const long long rr = cell / nx;
+        const int yy = (int)(rr % ny), zz = (int)(rr / ny);
+        const long long slabn = (long long)CL_ROWS * nx;  // 5 fields x 4 modes rows per slab
+        auto at = [&](int dx, int dy, int dz) -> long long {
+            int xi = x + dx, yi = yy + dy, zi = zz + dz;
+            xi = xi < 0 ? xi + nx : (xi >= nx ? xi - nx : xi);
+            yi = yi < 0 ? yi + ny : (yi >= ny ? yi - ny : yi);
+            zi = zi < 0 ? zi + nz : (zi >= nz ? zi - nz : zi);
+            return ((long long)zi * ny + yi) * slabn + xi;
+        };
+        long long base[7];
+        base[0] = at(0, 0, 0);
+        base[1] = at(-1, 0, 0);
+        base[2] = at(1, 0, 0);
+        base[3] = at(0, -1, 0);
+        base[4] = at(0, 1, 0);
+        base[5] = at(0, 0, -1);
+        base[6] = at(0, 0, 1);
+        const S *y = reinterpret_cast<const S *>(a.y);
+        const float *b1 = a.params + CL_NH * CL_NIN;
+        const float *b2 = b1 + CL_NH + CL_NH * CL_NH;
+        const float *b3 = b2 + CL_NH + CL_NOUT * CL_NH;
+        // the fragments at this lane: an opaque lane base plus immediate offsets (not a register per
+        // fragment hoisted out of the loop)
+        int lb = lane;
+        asm volatile("" : "+v"(lb));
+        const float *w1l = wl + lb, *w2l = wl + CL_W1F + lb, *w3l = wl + CL_W1F + CL_W2F + lb;
 
-    // layer 1: 140 -> 128
-    f4c h1[8];
-#pragma unroll
-    for (int t = 0; t < 8; t++) h1[t] = f4c{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < 35; s++) {
-        const int j = s / 5, i = s % 5;
-        const int f = 4 * s + g;
-        const float v = (float)y[base[j] + (long long)(i * 4 + g) * nx];
-        const float b = (v - a.fmean[f]) * a.fistd[f];
-#pragma unroll
-        for (int t = 0; t < 8; t++) h1[t] = mfma4(W1[(16 * t + col) * CL_NIN + 4 * s + g], b, h1[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 8; t++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) h1[t][r] = tanhf(h1[t][r] + b1[16 * t + 4 * g + r]);
+        // layer 1: 140 -> 128
+        f4c h1[8];
+    #pragma unroll
+        for (int t = 0; t < 8; t++) h1[t] = f4c{0, 0, 0, 0};
+    #pragma unroll
+        for (int s = 0; s < 35; s++) {
+            const int j = s / 5, i = s % 5;
+            const int f = 4 * s + g;
+            const float v = (float)y[base[j] + (long long)(i * 4 + g) * nx];
+            const float b = (v - a.fmean[f]) * a.fistd[f];
+    #pragma unroll
+            for (int t = 0; t < 8; t++) h1[t] = mfma4(w1l[(t * 35 + s) * 64], b, h1[t]);
+        }
+    #pragma unroll
+        for (int t = 0; t < 8; t++)
+    #pragma unroll
+            for (int r = 0; r < 4; r++) h1[t][r] = tanh_act(h1[t][r] + b1[16 * t + 4 * g + r]);
 
-    // layer 2: 128 -> 128
-    f4c h2[8];
-#pragma unroll
-    for (int t = 0; t < 8; t++) h2[t] = f4c{0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < 8; t++)
-#pragma unroll
+        // layer 2: 128 -> 128
+        f4c h2[8];
+    #pragma unroll
+        for (int t = 0; t < 8; t++) h2[t] = f4c{0, 0, 0, 0};
+    #pragma unroll
+        for (int t = 0; t < 8; t++)
+    #pragma unroll
+            for (int r = 0; r < 4; r++) {
+    #pragma unroll
+                for (int u = 0; u < 8; u++) h2[u] = mfma4(w2l[((t * 4 + r) * 8 + u) * 64], h1[t][r], h2[u]);
+            }
+    #pragma unroll
+        for (int t = 0; t < 8; t++)
+    #pragma unroll
+            for (int r = 0; r < 4; r++) h2[t][r] = tanh_act(h2[t][r] + b2[16 * t + 4 * g + r]);
+
+        // layer 3: 128 -> 20 (rows 20..31 of tile 1 are zero)
+        f4c o[2] = {f4c{0, 0, 0, 0}, f4c{0, 0, 0, 0}};
+    #pragma unroll
+        for (int t = 0; t < 8; t++)
+    #pragma unroll
+            for (int r = 0; r < 4; r++) {
+                o[0] = mfma4(w3l[((t * 4 + r) * 2) * 64], h2[t][r], o[0]);
+                o[1] = mfma4(w3l[((t * 4 + r) * 2 + 1) * 64], h2[t][r], o[1]);
+            }
+        // output entries held by this lane: tile 0 rows 4g+r (field g), tile 1 rows 16+r (lane group 0)
+        bool bad = false;
+    #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const int kk = 16 * t + 4 * g + r;
-#pragma unroll
-            for (int u = 0; u < 8; u++) h2[u] = mfma4(W2[(16 * u + col) * CL_NH + kk], h1[t][r], h2[u]);
+            const int j0 = 4 * g + r;
+            o[0][r] += b3[j0];
+            bad |= !(__builtin_fabsf(o[0][r]) <= a.obound[j0]);  // also true for NaN
+            if (g == 0) {
+                o[1][r] += b3[16 + r];
+                bad |= !(__builtin_fabsf(o[1][r]) <= a.obound[16 + r]);
+            }
         }
-#pragma unroll
-    for (int t = 0; t < 8; t++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) h2[t][r] = tanhf(h2[t][r] + b2[16 * t + 4 * g + r]);
-
-    // layer 3: 128 -> 20 (rows 20..31 of tile 1 are zero)
-    f4c o[2] = {f4c{0, 0, 0, 0}, f4c{0, 0, 0, 0}};
-    const int row1 = 16 + col;
-#pragma unroll
-    for (int t = 0; t < 8; t++)
-#pragma unroll
+        // a cell falls back if any of its 20 outputs is out of range: OR over the 4 lane groups
+        int bi = bad ? 1 : 0;
+        bi |= __shfl_xor(bi, 16, 64);
+        bi |= __shfl_xor(bi, 32, 64);
+        bad = bi != 0;
+        S *corr = reinterpret_cast<S *>(a.corr);
+        double m0 = 0.0, m4 = 0.0;  // this lane's mean-row corrections (field g; field 4 on group 0)
+    #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const int kk = 16 * t + 4 * g + r;
-            o[0] = mfma4(W3[col * CL_NH + kk], h2[t][r], o[0]);
-            o[1] = mfma4(row1 < CL_NOUT ? W3[row1 * CL_NH + kk] : 0.0f, h2[t][r], o[1]);
+            const int j0 = 4 * g + r;
+            const float c0 = bad ? 0.0f : a.oscale[j0] * o[0][r];
+            if (live) corr[base[0] + (long long)j0 * nx] = (S)c0;
+            if (r == 0) m0 = live ? (double)(S)c0 : 0.0;
+            if (g == 0) {
+                const float c1 = bad ? 0.0f : a.oscale[16 + r] * o[1][r];
+                if (live) corr[base[0] + (long long)(16 + r) * nx] = (S)c1;
+                if (r == 0) m4 = live ? (double)(S)c1 : 0.0;
+            }
         }
-    // output entries held by this lane: tile 0 rows 4g+r (field g), tile 1 rows 16+r (lane group 0)
-    bool bad = false;
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int j0 = 4 * g + r;
-        o[0][r] += b3[j0];
-        bad |= !(__builtin_fabsf(o[0][r]) <= a.obound[j0]);  // also true for NaN
-        if (g == 0) {
-            o[1][r] += b3[16 + r];
-            bad |= !(__builtin_fabsf(o[1][r]) <= a.obound[16 + r]);
+        // per-wave sums of the mean rows over the 16 columns, fixed order
+    #pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) {
+            m0 += __shfl_xor(m0, off, 16);
+            m4 += __shfl_xor(m4, off, 16);
         }
-    }
-    // a cell falls back if any of its 20 outputs is out of range: OR over the 4 lane groups
-    int bi = bad ? 1 : 0;
-    bi |= __shfl_xor(bi, 16, 64);
-    bi |= __shfl_xor(bi, 32, 64);
-    bad = bi != 0;
-    S *corr = reinterpret_cast<S *>(a.corr);
-    double m0 = 0.0, m4 = 0.0;  // this lane's mean-row corrections (field g; field 4 on group 0)
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int j0 = 4 * g + r;
-        const float c0 = bad ? 0.0f : a.oscale[j0] * o[0][r];
-        if (live) corr[base[0] + (long long)j0 * nx] = (S)c0;
-        if (r == 0) m0 = live ? (double)(S)c0 : 0.0;
-        if (g == 0) {
-            const float c1 = bad ? 0.0f : a.oscale[16 + r] * o[1][r];
-            if (live) corr[base[0] + (long long)(16 + r) * nx] = (S)c1;
-            if (r == 0) m4 = live ? (double)(S)c1 : 0.0;
+        if (col == 0) {
+            a.partials[wave * NF + g] = m0;
+            if (g == 0) a.partials[wave * NF + 4] = m4;
         }
+        const unsigned long long fb = __ballot(bad && live && g == 0);
+        if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
     }
-    // per-wave sums of the mean rows over the 16 columns, fixed order
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-        m0 += __shfl_xor(m0, off, 16);
-        m4 += __shfl_xor(m4, off, 16);
-    }
-    if (col == 0) {
-        a.partials[wave * NF + g] = m0;
-        if (g == 0) a.partials[wave * NF + 4] = m4;
-    }
-    const unsigned long long fb = __ballot(bad && live && g == 0);
-    if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
 }
 
 // mean of the mean-row corrections per field, summed in a fixed order
@@ -188,11 +232,20 @@ __global__ __launch_bounds__(256) void closure_mean_kernel(const double *partial
 
 hipError_t launch_closure(int prec, const ClosureArgs &a, hipStream_t s) {
     const long long nwaves = (a.ncells + 15) / 16;
-    const long long nb = (nwaves + 3) / 4;
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const void *fn = prec == DG_FP64 ? reinterpret_cast<const void *>(&closure_kernel<double>)
+                                     : reinterpret_cast<const void *>(&closure_kernel<float>);
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, CL_LDS);
+    if (e != hipSuccess) return e;
+    // one workgroup per compute unit (the weights fill its LDS), no more than there are groups
+    const long long nb = std::min<long long>((nwaves + CL_THREADS / 64 - 1) / (CL_THREADS / 64), std::max(ncu, 1));
     if (prec == DG_FP64)
-        hipLaunchKernelGGL((closure_kernel<double>), dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((closure_kernel<double>), dim3(nb), dim3(CL_THREADS), CL_LDS, s, a);
     else
-        hipLaunchKernelGGL((closure_kernel<float>), dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((closure_kernel<float>), dim3(nb), dim3(CL_THREADS), CL_LDS, s, a);
     hipLaunchKernelGGL(closure_mean_kernel, dim3(1), dim3(256), 0, s, a.partials, nwaves, a.ncells, a.cmean);
     return hipGetLastError();
 }
