@@ -703,6 +703,11 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 }
             }
             lds_barrier();
+            // Issue priority: the two waves of a SIMD are rows w and w + 4.  By default the older
+            // one (w < 4) wins issue, runs ahead through the faces and then waits at the next
+            // barrier while its partner finishes alone; the younger one leads from here to the end
+            // of the step, the older one the volume term, so the two reach the barriers together
+            if (wave >= 4) __builtin_amdgcn_s_setprio(2);
             {
                 C ta[NF][4];
                 if (wrow == nact - 1) {
@@ -879,6 +884,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
                 ghost_dma(cidx(iy, z + 1), x0);
             }
+            if (wave >= 4) __builtin_amdgcn_s_setprio(0);
             cur = nxt;
         }
     }
