@@ -172,6 +172,13 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     }
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    // LDS exchange addresses: one lane base, made opaque at each use, plus immediate offsets (the
+    // compiler would otherwise hoist a register per element out of the sweep and spill them)
+    auto lane_base = [&]() {
+        int o = lane;
+        asm volatile("" : "+v"(o));
+        return o;
+    };
     const int col = lane & 15;
     const int g = lane >> 4;
     TabReader<K, PREC> T{lds, lane * KPL * PR::ESZ, lane * KPL2 * PR::ESZ};
@@ -274,13 +281,13 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
         // the LDS reads below the wait
         __builtin_amdgcn_s_waitcnt(0x0F70);
         asm volatile("" ::: "memory");
-        const C *src = ex_e + e * ERV * 64;
+        const C *src = ex_e + e * ERV * 64 + lane_base();
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            b.qbar[i] = src[(i * (1 + SPL)) * 64 + lane];
+            b.qbar[i] = src[(i * (1 + SPL)) * 64];
 #pragma unroll
             for (int s = 0; s < SPL; s++) {
-                const C v = src[(i * (1 + SPL) + 1 + s) * 64 + lane];
+                const C v = src[(i * (1 + SPL) + 1 + s) * 64];
                 if constexpr (B::RAW) {
                     b.v[i][s] = v;
                 } else {
@@ -500,16 +507,18 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
     const bool dma_y0 = DMA && !a.ex_single && a.mode != 0 && a.a != 0.0;
     C *ex_f = reinterpret_cast<C *>(lds + a.ex_off2);
     auto ex_put = [&](C *ex, int slot, const C v[NF][4]) {
+        C *p = ex + slot * NF * 4 * 64 + lane_base();
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) ex[((slot * NF + i) * 4 + r) * 64 + lane] = v[i][r];
+            for (int r = 0; r < 4; r++) p[(i * 4 + r) * 64] = v[i][r];
     };
     auto ex_get = [&](const C *ex, int slot, C v[NF][4]) {
+        const C *p = ex + slot * NF * 4 * 64 + lane_base();
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) v[i][r] = ex[((slot * NF + i) * 4 + r) * 64 + lane];
+            for (int r = 0; r < 4; r++) v[i][r] = p[(i * 4 + r) * 64];
     };
 
     // ---------------- work items: (x-block, y row or group of YROWS rows, z chunk), x-block fastest.
@@ -604,6 +613,9 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                     }
                 }
                 __syncthreads();
+                // the younger wave of each SIMD (rows w + 4) leads from here to the end of the step
+                // (by default the older one wins issue and then waits at the next barrier)
+                if (wave >= 4) __builtin_amdgcn_s_setprio(2);
                 {
                     C Fp[NF][4];
                     {
@@ -744,11 +756,12 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                         // the memory clobber keeps the LDS reads below the wait
                         __builtin_amdgcn_s_waitcnt(0x0F70);
                         asm volatile("" ::: "memory");
+                        const C *y0s = ex_t + wrow * NF * 4 * 64 + lane_base();
 #pragma unroll
                         for (int u = 0; u < EG; u++)
                             if (s0 + u < DMA_SL) {
 #pragma unroll
-                                for (int i = 0; i < NF; i++) y0v[i][u] = ex_t[((wrow * NF + i) * 4 + s0 + u) * 64 + lane];
+                                for (int i = 0; i < NF; i++) y0v[i][u] = y0s[(i * 4 + s0 + u) * 64];
                             }
                     } else if (with0) {
                         const auto r0 = slab_rsrc(y0, slabn, rz);
@@ -796,6 +809,7 @@ __global__ __launch_bounds__(stage_threads<PREC>()) __attribute__((amdgpu_waves_
                     }
                 }
             }
+            if (YSH && wave >= 4) __builtin_amdgcn_s_setprio(0);
             cur = nxt;
         }
     }
