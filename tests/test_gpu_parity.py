@@ -199,13 +199,14 @@ def test_edge_grids(dgm, n):
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("ny", [19, 17])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
-def test_step_parity_several_row_groups(dgm, prec):
-    """k = 3 with ny = 19: two full groups of 8 y rows that share their y faces through LDS and a
-    ragged group of 3, two x-blocks (one ragged), with the driving; two fixed-dt steps against the
-    oracle."""
+def test_step_parity_several_row_groups(dgm, prec, ny):
+    """k = 3 with ny = 19 or 17: two full groups of 8 y rows that share their y faces through LDS
+    and a ragged group of 3 rows or of one (whose only row takes both end rows), two x-blocks (one
+    ragged), with the driving; two fixed-dt steps against the oracle."""
     from paper_1602_09079_amd import dg as dgmod
-    k, n, box = 3, (20, 19, 3), (1.0, 0.9, 1.1)
+    k, n, box = 3, (20, ny, 3), (1.0, 0.9, 1.1)
     cfg, qp, y_or = turb_case(k, n, box)
     nvec = synth.forcing_modes(1.0, 3.0)
     th = synth.ou_stationary_start(7, len(nvec))
@@ -220,12 +221,12 @@ def test_step_parity_several_row_groups(dgm, prec):
     s.step(y, nsteps=2, dt=h)
     y1, _ = O.step(cfg, y_st, h, 2, frc=O.ForcingTable(nvec, ah_orc))
     err = O.rel_l2(state_host(y), y1)
-    print(f"step k=3 ny=19 {prec}: rel L2 per field {err}")
+    print(f"step k=3 ny={ny} {prec}: rel L2 per field {err}")
     assert np.all(err <= TOL_STATE[prec]), err
     # the increment alone (y - y0), which the state norm hides, against the largest field's, as R;
     # the six stored FP32 stages round the state at 2^-24 of |y|, about 1e-4 of this increment
     inc = rhs_err(state_host(y) - y_st, y1 - y_st)
-    print(f"step k=3 ny=19 {prec}: increment error per field / max field norm {inc}")
+    print(f"step k=3 ny={ny} {prec}: increment error per field / max field norm {inc}")
     assert np.all(inc <= {"fp32": 1e-3, "bf16x3": 1e-3, "bf16": 0.5}[prec]), inc
 
 
