@@ -26,6 +26,12 @@
 //   the A operand and cos / sin of the cell's x phase as the B operand of FP32 16x16x4 MFMAs.
 // - y faces shared by the 8 rows of a workgroup through LDS (each face solved once), the z face
 //   carried along the z sweep, as in stage_kernel.
+// - No register spills in the z sweep: loads complete in order, so a spill reload waits for every
+//   copy and prefetch in flight before it.  LDS is addressed from one opaque lane base plus
+//   immediate offsets, nothing is held in registers across the barriers, and the copies into
+//   LDS are waited for with exact counts.
+// - The two waves of a SIMD (rows w and w + 4) take turns to lead (issue priority), so that they
+//   reach the barriers together.
 
 #include <type_traits>
 
@@ -115,8 +121,9 @@ __device__ inline H4<X3> zero4() {
 }
 
 // The weights of a block of 16 cells: the means (mode 0, full precision) and the raw values of
-// the lane's five mode slots.  Their BF16 operands are formed where a product uses them: kept for
-// the whole step, the split copies would take the registers that the second wave per SIMD needs.
+// the lane's five mode slots.  Their BF16 operands are formed per use (once for the four volume
+// nodes, once per pair of faces): kept for the whole step, the split copies would take the
+// registers that the second wave per SIMD needs.
 struct Blk3 {
     float qbar[NF];
     float v[NF][NSL];
