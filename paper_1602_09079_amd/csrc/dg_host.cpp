@@ -244,8 +244,8 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
     return blob;
 }
 
-// Tables of the k = 3 BF16-tier stage kernel (stage_k3.hip), in its fragment order (K3_T1 ..
-// K3_T4, 1 KiB each): lane L feeds row L % 16 and contraction indices 8 (L / 16) + j, j = 0..7.
+// Tables of the k = 3 FP32-storage stage kernel (stage_k3.hip), in its fragment order (K3_T1 ..
+// K3_T4, 1 KiB each in BF16): lane L feeds row L % 16 and contraction indices 8 (L / 16) + j, j = 0..7.
 // Products with the weights: index 8g + s is the mode of slot s of lane group g (k3_slot_mode),
 // s < 5; mode 0 (the mean, added apart) and indices 8g + 5..7 are zero.  Products over points:
 // index 8g + j is the result register j % 4 of lane group g of the preceding product, i.e. point
@@ -296,6 +296,25 @@ std::vector<char> build_tables_k3(int prec, const double s[3]) {
                     at(K3_T4 + 2 * ax + rt, lane, j) = s[ax] * (half ? 1.0 : -1.0) * B.phi(mb, xi) * B.face_weight(pnt);
                 }
         }
+    }
+    if (prec == DG_FP32) {
+        // FP32: value j of lane l of a fragment is the A operand of step j of the chunk's eight
+        // 16x16x4 products; stored [frag][j / 4][lane][j % 4] (one 16-byte read per four steps).
+        // The second row tiles (one useful row per lane group) run as 4x4x1 products of 16
+        // blocks: block 4g + c (lanes 4(4g + c) .. + 3) holds cells 4c .. 4c + 3 and contraction
+        // index 8g + j, and its row i is row 4i of the tile, so lane l takes the value of lane
+        // 4 (l % 4) + 16 (l / 16)
+        std::vector<char> blob((size_t)K3_SET * 2, 0);
+        float *f = reinterpret_cast<float *>(blob.data());
+        for (int frag = 0; frag < K3_NFRAG; frag++) {
+            const bool tile1 = (frag >= K3_T2B && frag < K3_T4 && (frag - K3_T2B) % 2 == 1) ||
+                               (frag >= K3_T4 && (frag - K3_T4) % 2 == 1);
+            for (int lane = 0; lane < 64; lane++) {
+                const int src = tile1 ? 4 * (lane % 4) + 16 * (lane / 16) : lane;
+                for (int j = 0; j < 8; j++) f[((size_t)(2 * frag + j / 4) * 64 + lane) * 4 + j % 4] = (float)at(frag, src, j);
+            }
+        }
+        return blob;
     }
     const int ntab = prec == DG_BF16X3 ? 2 : 1;
     std::vector<char> blob((size_t)K3_SET * ntab, 0);
@@ -503,7 +522,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         return st;
     };
     // k = 3 in the BF16-product tiers: the kernel of stage_k3.hip
-    c->k3x = cfg->k == 3 && (cfg->precision == DG_BF16 || cfg->precision == DG_BF16X3);
+    c->k3x = cfg->k == 3 && cfg->precision != DG_FP64;
     if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
         std::vector<char> blob;
         if (cfg->k == 4) {
@@ -583,7 +602,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
             return fail(DG_ERR_HIP);
         // separate y-face trace and flux regions when both fit, else one shared region
         const int exb = (int)stage_exchange_bytes(cfg->precision);
-        c->ex_off = c->k3x ? K3_SET * (cfg->precision == DG_BF16X3 ? 2 : 1) : (int)c->lay.bytes();
+        c->ex_off = c->k3x ? K3_SET * (cfg->precision == DG_BF16 ? 1 : 2) : (int)c->lay.bytes();
         c->ex_off2 = c->ex_off + exb;
         c->lds = c->ex_off + 2 * exb;
         if (c->lds > maxlds) {

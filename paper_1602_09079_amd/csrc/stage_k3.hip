@@ -1,6 +1,6 @@
 // The SSP stage kernel for k = 3 (N = 20 modes, 4^3 volume points, 4^2 points per face) in the
-// tiers whose products run on the BF16 matrix cores: DG_BF16 (one product) and DG_BF16X3 (each
-// operand split x = hi + lo, three products: FP32-grade).  It evaluates the same operator as
+// tiers with FP32 storage: DG_BF16 (one BF16 product), DG_BF16X3 (each operand split x = hi + lo,
+// three BF16 products: FP32-grade) and DG_FP32 (FP32 products).  It evaluates the same operator as
 // stage_kernel in dg_kernels.hip (Bauer et al., arXiv 1602.09079, Sec. 2.3, eqs.
 // dg:eqn:volume_int and dg:eqn:surface_int, the driving source of Sec. 3.1, the Shu-Osher
 // combine of the SSP-RK3 step), organised for gfx950:
@@ -13,9 +13,11 @@
 //   trace table into the -x one).  The high edge's 16 points are gathered into 16 lanes and
 //   solved in one pass.  Ragged last blocks take their right neighbour from the wrapped column
 //   after the last valid one.
-// - Every product is a 16x16x32 BF16 MFMA (K = 32).  The volume contraction pairs the x and y
-//   fluxes of a z-node's 16 points in one K = 32 chunk and the z flux with the driving source in
-//   another; the lift pairs the - and + face of an axis.  The mode order of the result rows
+// - Every product is a K = 32 chunk: one 16x16x32 BF16 MFMA, or in FP32 eight 16x16x4 steps
+//   (steps whose operand half is zero are skipped; the second row tile, one useful row per lane
+//   group, runs as 4x4x1 products of 16 blocks, a quarter of the cost).  The volume contraction
+//   pairs the x and y fluxes of a z-node's 16 points in one K = 32 chunk and the z flux with the
+//   driving source in another; the lift pairs the - and + face of an axis.  The mode order of the result rows
 //   (k3_slot_mode) puts the four modes (0,0,w) in the second row tile, whose x and y derivative
 //   tables vanish, so the x/y chunk needs one row tile.
 // - The symmetric momentum flux m_a m_b / rho is formed and split once for both of its uses.  The
@@ -46,23 +48,32 @@ constexpr int NSL = 5;  // mode slots per lane group
 
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
-// B operand of one product: hi (and lo for BF16X3) BF16 values, 8 per lane
-template <bool X3>
+// B operand of one K = 32 chunk: 8 values per lane, as BF16 (hi, and lo for BF16X3) or, for FP32,
+// as floats (element j is the operand of the chunk's j-th 16x16x4 FP32 product)
+template <int P>
 struct Op;
 template <>
-struct Op<true> {
+struct Op<DG_BF16X3> {
     bf8 hi, lo;
 };
 template <>
-struct Op<false> {
+struct Op<DG_BF16> {
     bf8 hi;
 };
+template <>
+struct Op<DG_FP32> {
+    float v[8];
+};
 
-// half of a B operand: four values as two packed BF16 pairs (hi, and lo for BF16X3)
-template <bool X3>
+// half of a B operand: four values as two packed BF16 pairs (hi, and lo for BF16X3), or floats
+template <int P>
 struct H4 {
     unsigned hi[2];
-    unsigned lo[X3 ? 2 : 1];
+    unsigned lo[P == DG_BF16X3 ? 2 : 1];
+};
+template <>
+struct H4<DG_FP32> {
+    float v[4];
 };
 
 __device__ inline unsigned pk_bf16(float a, float b) {
@@ -93,30 +104,49 @@ __device__ inline void split_pair(float a, float b, unsigned &hi, unsigned &lo, 
         lo = pk_bf16(la, lb);
     }
 }
-template <bool X3>
-__device__ inline H4<X3> split4(const float v[4], const SplitConst &k) {
-    H4<X3> o;
-    unsigned l0 = 0, l1 = 0;
-    split_pair<X3>(v[0], v[1], o.hi[0], l0, k);
-    split_pair<X3>(v[2], v[3], o.hi[1], l1, k);
-    if constexpr (X3) {
-        o.lo[0] = l0;
-        o.lo[1] = l1;
+template <int P>
+__device__ inline H4<P> split4(const float v[4], const SplitConst &k) {
+    H4<P> o;
+    if constexpr (P == DG_FP32) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) o.v[r] = v[r];
+    } else {
+        constexpr bool X3 = P == DG_BF16X3;
+        unsigned l0 = 0, l1 = 0;
+        split_pair<X3>(v[0], v[1], o.hi[0], l0, k);
+        split_pair<X3>(v[2], v[3], o.hi[1], l1, k);
+        if constexpr (X3) {
+            o.lo[0] = l0;
+            o.lo[1] = l1;
+        }
     }
     return o;
 }
-template <bool X3>
-__device__ inline Op<X3> join(const H4<X3> &a, const H4<X3> &b) {
-    Op<X3> o;
-    o.hi = __builtin_bit_cast(bf8, (u4v){a.hi[0], a.hi[1], b.hi[0], b.hi[1]});
-    if constexpr (X3) o.lo = __builtin_bit_cast(bf8, (u4v){a.lo[0], a.lo[1], b.lo[0], b.lo[1]});
+template <int P>
+__device__ inline Op<P> join(const H4<P> &a, const H4<P> &b) {
+    Op<P> o;
+    if constexpr (P == DG_FP32) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            o.v[r] = a.v[r];
+            o.v[4 + r] = b.v[r];
+        }
+    } else {
+        o.hi = __builtin_bit_cast(bf8, (u4v){a.hi[0], a.hi[1], b.hi[0], b.hi[1]});
+        if constexpr (P == DG_BF16X3) o.lo = __builtin_bit_cast(bf8, (u4v){a.lo[0], a.lo[1], b.lo[0], b.lo[1]});
+    }
     return o;
 }
-template <bool X3>
-__device__ inline H4<X3> zero4() {
-    H4<X3> o;
-    o.hi[0] = o.hi[1] = 0u;
-    if constexpr (X3) o.lo[0] = o.lo[1] = 0u;
+template <int P>
+__device__ inline H4<P> zero4() {
+    H4<P> o;
+    if constexpr (P == DG_FP32) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) o.v[r] = 0.0f;
+    } else {
+        o.hi[0] = o.hi[1] = 0u;
+        if constexpr (P == DG_BF16X3) o.lo[0] = o.lo[1] = 0u;
+    }
     return o;
 }
 
@@ -130,19 +160,26 @@ struct Blk3 {
 };
 
 // the B operand of one field of a block: slots 0..4 at contraction indices 8g + 0..4, 5..7 zero
-template <bool X3>
-__device__ inline Op<X3> weights_op(const float v[NSL], const SplitConst &k) {
-    unsigned h0, h1, h2, l0 = 0, l1 = 0, l2 = 0;
-    split_pair<X3>(v[0], v[1], h0, l0, k);
-    split_pair<X3>(v[2], v[3], h1, l1, k);
-    {  // slot 4 with a zero: one split
-        const bv2 h = __builtin_convertvector((fv2){v[4], 0.0f}, bv2);
-        h2 = __builtin_bit_cast(unsigned, h);
-        if constexpr (X3) l2 = pk_bf16(__builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bv2, k.m0), v[4], false), 0.0f);
+template <int P>
+__device__ inline Op<P> weights_op(const float v[NSL], const SplitConst &k) {
+    Op<P> op;
+    if constexpr (P == DG_FP32) {
+#pragma unroll
+        for (int s = 0; s < 8; s++) op.v[s] = s < NSL ? v[s] : 0.0f;
+    } else {
+        constexpr bool X3 = P == DG_BF16X3;
+        unsigned h0, h1, h2, l0 = 0, l1 = 0, l2 = 0;
+        split_pair<X3>(v[0], v[1], h0, l0, k);
+        split_pair<X3>(v[2], v[3], h1, l1, k);
+        {  // slot 4 with a zero: one split
+            const bv2 h = __builtin_convertvector((fv2){v[4], 0.0f}, bv2);
+            h2 = __builtin_bit_cast(unsigned, h);
+            if constexpr (X3)
+                l2 = pk_bf16(__builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bv2, k.m0), v[4], false), 0.0f);
+        }
+        op.hi = __builtin_bit_cast(bf8, (u4v){h0, h1, h2, 0u});
+        if constexpr (X3) op.lo = __builtin_bit_cast(bf8, (u4v){l0, l1, l2, 0u});
     }
-    Op<X3> op;
-    op.hi = __builtin_bit_cast(bf8, (u4v){h0, h1, h2, 0u});
-    if constexpr (X3) op.lo = __builtin_bit_cast(bf8, (u4v){l0, l1, l2, 0u});
     return op;
 }
 
@@ -180,12 +217,12 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     using C = float;
     using Acc = f4;
     using B3 = Blk3;
-    using HH = H4<X3>;
-    using OP = Op<X3>;
+    using HH = H4<PREC>;
+    using OP = Op<PREC>;
 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
-        constexpr int bytes = K3_SET * (X3 ? 2 : 1);
+        constexpr int bytes = K3_SET * (PREC == DG_BF16 ? 1 : 2);
         const int4 *src = reinterpret_cast<const int4 *>(a.tables);
         int4 *dst = reinterpret_cast<int4 *>(lds);
         for (int j = threadIdx.x; j < bytes / 16; j += K3_THREADS) dst[j] = src[j];
@@ -207,14 +244,61 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         asm volatile("" : "+v"(o));
         return o;
     };
-    auto mma = [&](Acc c, int frag, const OP &b) -> Acc {
-        const bf8 ah = *reinterpret_cast<const bf8 *>(lds + frag * K3_FRAG + toff);
-        if constexpr (X3) {
-            const bf8 al = *reinterpret_cast<const bf8 *>(lds + K3_SET + frag * K3_FRAG + toff);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.hi, c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.lo, c, 0, 0, 0);
+    // one K = 32 chunk; FP32: steps j0 .. j1 - 1 of its eight 16x16x4 products (the others have a
+    // zero operand), the A values of steps 4h .. 4h + 3 one 16-byte read at half h of the fragment
+    auto mma = [&](Acc c, int frag, const OP &b, int j0 = 0, int j1 = 8) -> Acc {
+        if constexpr (PREC == DG_FP32) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (4 * h >= j1 || 4 * h + 4 <= j0) continue;
+                const f4 af = *reinterpret_cast<const f4 *>(lds + (2 * frag + h) * K3_FRAG + toff);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (4 * h + r >= j0 && 4 * h + r < j1)
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], b.v[4 * h + r], c, 0, 0, 0);
+            }
+            return c;
+        } else {
+            const bf8 ah = *reinterpret_cast<const bf8 *>(lds + frag * K3_FRAG + toff);
+            if constexpr (X3) {
+                const bf8 al = *reinterpret_cast<const bf8 *>(lds + K3_SET + frag * K3_FRAG + toff);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b.hi, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.lo, c, 0, 0, 0);
+            }
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.hi, c, 0, 0, 0);
         }
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b.hi, c, 0, 0, 0);
+    };
+    // the second row tile of a chunk (one useful row per lane group: slot 4).  FP32: 4x4x1 products
+    // of 16 blocks, block 4g + c (this lane: g = lane / 16, c = (lane % 16) / 4) taking cells
+    // 4c .. 4c + 3 and contraction index 8g + j; register r of lane l then holds the part from
+    // lane group l / 16 of row 4r (slot 4 of lane group r) for cell l % 16, summed by tile1_sum.
+    // A quarter of the 16x16x4 products' cost.
+    auto mma1 = [&](Acc c, int frag, const OP &b, int j0 = 0, int j1 = 8) -> Acc {
+        if constexpr (PREC == DG_FP32) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                if (4 * h >= j1 || 4 * h + 4 <= j0) continue;
+                const f4 af = *reinterpret_cast<const f4 *>(lds + (2 * frag + h) * K3_FRAG + toff);
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (4 * h + r >= j0 && 4 * h + r < j1)
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(af[r], b.v[4 * h + r], c, 0, 0, 0);
+            }
+            return c;
+        } else {
+            return mma(c, frag, b, j0, j1);
+        }
+    };
+    // FP32: the second row tile's result in register 0 (slot 4): this lane group's row summed over
+    // the four lane groups' parts (two exchange steps, each lane keeping half of what remains)
+    auto tile1_sum = [&](Acc c) -> Acc {
+        const bool hi2 = (g & 2) != 0, odd = (g & 1) != 0;
+        const C k0 = hi2 ? c[2] : c[0], k1 = hi2 ? c[3] : c[1];
+        const C s0 = hi2 ? c[0] : c[2], s1 = hi2 ? c[1] : c[3];
+        const C h0 = k0 + __shfl_xor(s0, 32), h1 = k1 + __shfl_xor(s1, 32);
+        const C keep = odd ? h1 : h0, send = odd ? h0 : h1;
+        c[0] = keep + __shfl_xor(send, 16);
+        return c;
     };
 
     const C gam = (C)a.gamma;
@@ -292,15 +376,15 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
         for (int s = 0; s < NSL; s++) {
             v[s] = b.v[i][s];
-            asm volatile("" : "+v"(v[s]));
+            if constexpr (PREC != DG_FP32) asm volatile("" : "+v"(v[s]));
         }
-        return weights_op<X3>(v, sk);
+        return weights_op<PREC>(v, sk);
     };
     // traces of a block on face f (GEMM3), mean added back in full precision
     auto trace = [&](int f, const B3 &b, C tr[NF][4]) {
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            const Acc t = mma(Acc{0, 0, 0, 0}, K3_T3 + f, wop(b, i));
+            const Acc t = mma(Acc{0, 0, 0, 0}, K3_T3 + f, wop(b, i), 0, NSL);
 #pragma unroll
             for (int r = 0; r < 4; r++) tr[i][r] = t[r] + b.qbar[i];
         }
@@ -310,8 +394,8 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
         for (int i = 0; i < NF; i++) {
             const OP op = wop(b, i);
-            const Acc t1 = mma(Acc{0, 0, 0, 0}, K3_T3 + f1, op);
-            const Acc t2 = mma(Acc{0, 0, 0, 0}, K3_T3 + f2, op);
+            const Acc t1 = mma(Acc{0, 0, 0, 0}, K3_T3 + f1, op, 0, NSL);
+            const Acc t2 = mma(Acc{0, 0, 0, 0}, K3_T3 + f2, op, 0, NSL);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 tr1[i][r] = t1[r] + b.qbar[i];
@@ -415,22 +499,23 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         mean_flux(b, axis, Fb);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            HH hm = zero4<X3>(), hp = zero4<X3>();
+            HH hm = zero4<PREC>(), hp = zero4<PREC>();
             if (Fm) {
                 C v[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) v[r] = Fm[i][r] - Fb[i];
-                hm = split4<X3>(v, sk);
+                hm = split4<PREC>(v, sk);
             }
             if (Fp) {
                 C v[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) v[r] = Fp[i][r] - Fb[i];
-                hp = split4<X3>(v, sk);
+                hp = split4<PREC>(v, sk);
             }
-            const OP op = join<X3>(hm, hp);
-            acc[i][0] = mma(acc[i][0], K3_T4 + 2 * axis, op);
-            acc[i][1] = mma(acc[i][1], K3_T4 + 2 * axis + 1, op);
+            const OP op = join<PREC>(hm, hp);
+            const int j0 = Fm ? 0 : 4, j1 = Fp ? 8 : 4;
+            acc[i][0] = mma(acc[i][0], K3_T4 + 2 * axis, op, j0, j1);
+            acc[i][1] = mma1(acc[i][1], K3_T4 + 2 * axis + 1, op, j0, j1);
         }
     };
 
@@ -459,7 +544,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             refresh();
             Acc d[NF];
 #pragma unroll
-            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, w5[i]);
+            for (int i = 0; i < NF; i++) d[i] = mma(Acc{0, 0, 0, 0}, K3_T1 + t, w5[i], 0, NSL);
             // the driving acceleration of the node (issued after the x/y chunk, below)
             Acc av[3] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
             float ha[3][K3_DKS];
@@ -499,41 +584,41 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     dx_[r] = d[1][r];
                     dy_[r] = d[2][r];
                 }
-                acc[0][0] = mma(acc[0][0], K3_T2A + t, join<X3>(split4<X3>(dx_, sk), split4<X3>(dy_, sk)));
+                acc[0][0] = mma(acc[0][0], K3_T2A + t, join<PREC>(split4<PREC>(dx_, sk), split4<PREC>(dy_, sk)));
             }
             HH hxy, hxz, hyz;
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = mx[r] * u[r] + p[r] - Fb[0][1];
-                const HH hxx = split4<X3>(tmp, sk);
+                const HH hxx = split4<PREC>(tmp, sk);
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = mx[r] * v[r] - Fb[1][1];
-                hxy = split4<X3>(tmp, sk);
-                acc[1][0] = mma(acc[1][0], K3_T2A + t, join<X3>(hxx, hxy));
+                hxy = split4<PREC>(tmp, sk);
+                acc[1][0] = mma(acc[1][0], K3_T2A + t, join<PREC>(hxx, hxy));
             }
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = my[r] * v[r] + p[r] - Fb[1][2];
-                const HH hyy = split4<X3>(tmp, sk);
-                acc[2][0] = mma(acc[2][0], K3_T2A + t, join<X3>(hxy, hyy));
+                const HH hyy = split4<PREC>(tmp, sk);
+                acc[2][0] = mma(acc[2][0], K3_T2A + t, join<PREC>(hxy, hyy));
             }
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = mx[r] * w[r] - Fb[2][1];
-                hxz = split4<X3>(tmp, sk);
+                hxz = split4<PREC>(tmp, sk);
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = my[r] * w[r] - Fb[2][2];
-                hyz = split4<X3>(tmp, sk);
-                acc[3][0] = mma(acc[3][0], K3_T2A + t, join<X3>(hxz, hyz));
+                hyz = split4<PREC>(tmp, sk);
+                acc[3][0] = mma(acc[3][0], K3_T2A + t, join<PREC>(hxz, hyz));
             }
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = ep[r] * u[r] - Fb[0][4];
-                const HH hxe = split4<X3>(tmp, sk);
+                const HH hxe = split4<PREC>(tmp, sk);
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = ep[r] * v[r] - Fb[1][4];
-                const HH hye = split4<X3>(tmp, sk);
-                acc[4][0] = mma(acc[4][0], K3_T2A + t, join<X3>(hxe, hye));
+                const HH hye = split4<PREC>(tmp, sk);
+                acc[4][0] = mma(acc[4][0], K3_T2A + t, join<PREC>(hxe, hye));
             }
             if constexpr (FORCE) {
 #pragma unroll
@@ -544,55 +629,56 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             }
             // chunk (z, source): S = (0, rho a, m.a) at the points
             auto chunk_b = [&](int i, const HH &hz, const HH &hs) {
-                const OP op = join<X3>(hz, hs);
-                acc[i][0] = mma(acc[i][0], K3_T2B + 2 * t, op);
-                acc[i][1] = mma(acc[i][1], K3_T2B + 2 * t + 1, op);
+                const OP op = join<PREC>(hz, hs);
+                const int j1 = FORCE && i > 0 ? 8 : 4;  // the source half is zero otherwise
+                acc[i][0] = mma(acc[i][0], K3_T2B + 2 * t, op, 0, j1);
+                acc[i][1] = mma1(acc[i][1], K3_T2B + 2 * t + 1, op, 0, j1);
             };
             {
                 C dz_[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) dz_[r] = d[3][r];
-                chunk_b(0, split4<X3>(dz_, sk), zero4<X3>());
+                chunk_b(0, split4<PREC>(dz_, sk), zero4<PREC>());
             }
             {
-                HH hs = zero4<X3>();
+                HH hs = zero4<PREC>();
                 if constexpr (FORCE) {
 #pragma unroll
                     for (int r = 0; r < 4; r++) tmp[r] = rho[r] * av[0][r];
-                    hs = split4<X3>(tmp, sk);
+                    hs = split4<PREC>(tmp, sk);
                 }
                 chunk_b(1, hxz, hs);
             }
             {
-                HH hs = zero4<X3>();
+                HH hs = zero4<PREC>();
                 if constexpr (FORCE) {
 #pragma unroll
                     for (int r = 0; r < 4; r++) tmp[r] = rho[r] * av[1][r];
-                    hs = split4<X3>(tmp, sk);
+                    hs = split4<PREC>(tmp, sk);
                 }
                 chunk_b(2, hyz, hs);
             }
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = mz[r] * w[r] + p[r] - Fb[2][3];
-                const HH hzz = split4<X3>(tmp, sk);
-                HH hs = zero4<X3>();
+                const HH hzz = split4<PREC>(tmp, sk);
+                HH hs = zero4<PREC>();
                 if constexpr (FORCE) {
 #pragma unroll
                     for (int r = 0; r < 4; r++) tmp[r] = rho[r] * av[2][r];
-                    hs = split4<X3>(tmp, sk);
+                    hs = split4<PREC>(tmp, sk);
                 }
                 chunk_b(3, hzz, hs);
             }
             {
 #pragma unroll
                 for (int r = 0; r < 4; r++) tmp[r] = ep[r] * w[r] - Fb[2][4];
-                const HH hze = split4<X3>(tmp, sk);
-                HH hs = zero4<X3>();
+                const HH hze = split4<PREC>(tmp, sk);
+                HH hs = zero4<PREC>();
                 if constexpr (FORCE) {
 #pragma unroll
                     for (int r = 0; r < 4; r++) tmp[r] = mx[r] * av[0][r] + my[r] * av[1][r] + mz[r] * av[2][r];
-                    hs = split4<X3>(tmp, sk);
+                    hs = split4<PREC>(tmp, sk);
                 }
                 chunk_b(4, hze, hs);
             }
@@ -841,6 +927,10 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 riemann(std::integral_constant<int, 2>{}, tp, tm, Fz);
                 lift(2, cur, nullptr, Fz, acc);
             }
+            if constexpr (PREC == DG_FP32) {
+#pragma unroll
+                for (int i = 0; i < NF; i++) acc[i][1] = tile1_sum(acc[i][1]);
+            }
             // combine and store; result slot s (row tile s / 4, register s % 4) is the mode this
             // lane loaded in slot s, so the stage input is still in registers.  The coefficients are
             // uniform: one branch-free path per kind of stage
@@ -966,6 +1056,7 @@ static hipError_t launch_k3_t(const StageArgs &a, int grid, int lds_bytes, hipSt
 hipError_t launch_stage_k3(int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
     if (prec == DG_BF16X3) return launch_k3_t<DG_BF16X3>(a, grid, lds_bytes, s);
     if (prec == DG_BF16) return launch_k3_t<DG_BF16>(a, grid, lds_bytes, s);
+    if (prec == DG_FP32) return launch_k3_t<DG_FP32>(a, grid, lds_bytes, s);
     return hipErrorInvalidValue;
 }
 
@@ -985,6 +1076,7 @@ static hipError_t set_attr_k3_t(int lds_bytes) {
 hipError_t set_stage_k3_attributes(int prec, int lds_bytes) {
     if (prec == DG_BF16X3) return set_attr_k3_t<DG_BF16X3>(lds_bytes);
     if (prec == DG_BF16) return set_attr_k3_t<DG_BF16>(lds_bytes);
+    if (prec == DG_FP32) return set_attr_k3_t<DG_FP32>(lds_bytes);
     return hipErrorInvalidValue;
 }
 
@@ -994,6 +1086,9 @@ hipError_t stage_k3_occupancy(int prec, int lds_bytes, int *per_cu) {
                                                             lds_bytes);
     if (prec == DG_BF16)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_k3_kernel<DG_BF16, true, 0>, K3_THREADS,
+                                                            lds_bytes);
+    if (prec == DG_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, stage_k3_kernel<DG_FP32, true, 0>, K3_THREADS,
                                                             lds_bytes);
     return hipErrorInvalidValue;
 }
