@@ -78,7 +78,7 @@ K3_VECTOR_FLOPS = 7980
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dg_kernels.hip", "stage_k3.hip", "dg_device.h", "dg_host.cpp", "dg_internal.h"):
+    for f in ("dg_kernels.hip", "stage_k3.hip", "stage_k4.hip", "dg_device.h", "dg_host.cpp", "dg_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1602_09079_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -272,13 +272,14 @@ def k4_flops_per_cell(forcing):
 
 
 def k4_cost(args, dg, torch):
-    """Stage launches at k = 4 (the quadrature-form kernel) in FP64 and FP32 on a k4_n^3 mesh
-    with the same workload recipe; the bound is the vector ALU (flops per cell above)."""
+    """Stage launches at k = 4 in FP64 (the quadrature-form kernel, vector ALU) and FP32 (the
+    matrix-core kernel) on a k4_n^3 mesh with the same workload recipe; the algorithmic flops per
+    cell above against the peak of the unit that does them."""
     from paper_1602_09079_amd import synth
     n, k = args.k4_n, 4
     out = dict(n=n, k=k, flops_per_cell=k4_flops_per_cell(not args.no_forcing))
     qp = synth.turbulence(n, dg.gauss_nodes(k + 1), seed=9079, mach=0.3, device="cuda", dtype=torch.float32)
-    for prec, peak in (("fp64", FP64_VECTOR_TFLOPS), ("fp32", FP32_VECTOR_TFLOPS)):
+    for prec, peak, unit in (("fp64", FP64_VECTOR_TFLOPS, "alu"), ("fp32", FP32_MATRIX_TFLOPS, "mfma")):
         s = dg.Solver(k, n, precision=prec, cfl=0.3, forcing=not args.no_forcing)
         if not args.no_forcing:
             nvec, ahat, _ = driving_table(dg)
@@ -298,8 +299,8 @@ def k4_cost(args, dg, torch):
         torch.cuda.synchronize()
         ms = ea.elapsed_time(eb) / reps
         tf = out["flops_per_cell"] * n ** 3 / (ms / 1e3) / 1e12
-        out[prec] = dict(stage_ms=ms, dof_updates_per_s=5 * dg.nmodes(k) * n ** 3 / (ms / 1e3),
-                         alu_TFLOPs=round(tf, 2), alu_peak_TFLOPs=peak, alu_frac=round(tf / peak, 4))
+        out[prec] = dict(stage_ms=ms, dof_updates_per_s=5 * dg.nmodes(k) * n ** 3 / (ms / 1e3), bound=unit,
+                         TFLOPs=round(tf, 2), peak_TFLOPs=peak, frac=round(tf / peak, 4))
         log(args, f"[bench] k=4 {prec} stage 1 on {n}^3: {ms:.3f} ms, {tf:.2f} TFLOP/s")
         del s, y, w1
         torch.cuda.empty_cache()

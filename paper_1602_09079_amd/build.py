@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgmi.so")
-SOURCES = ["dg_kernels.hip", "stage_k3.hip", "closure_kernels.hip", "diag_kernels.hip", "dg_host.cpp"]
+SOURCES = ["dg_kernels.hip", "stage_k3.hip", "stage_k4.hip", "closure_kernels.hip", "diag_kernels.hip", "dg_host.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

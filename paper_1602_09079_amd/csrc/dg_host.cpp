@@ -374,6 +374,74 @@ std::vector<char> build_quad_tables(int k, int prec, const double s[3]) {
     return blob;
 }
 
+// Tables of the k = 4 FP32 matrix-core stage kernel (stage_k4.hip), K4_NFRAG fragments of 64
+// floats in the order of dg_internal.h.  Lane L feeds row L % 16 and K index L / 16 of a 16x16x4
+// product; the last result tile (modes 32..34) runs as 4x4x1 products of 16 blocks, where lane L
+// feeds row L % 4 of its block.  Cell c's weights are the B operand with mode 4s + g at K step s
+// in lane group g; a result row R = 4g' + r of row tile rt is mode 16 rt + 4 r + g'; the point
+// and face-point products take K index g at step s to be the point in register s of lane group g
+// of the product that made it (point 16 t + 4 g + s of volume tile t; face row 16 (s / 4) + 4 g +
+// s % 4).  Padding rows: the value and trace tables repeat the last point, the tables that take
+// their results are zero there.
+std::vector<char> build_tables_k4(const double s[3]) {
+    const Basis B(4);
+    constexpr int N = 35, Q = 125, P = 25;
+    std::vector<float> f((size_t)K4_NFRAG * 64, 0.0f);
+    auto at = [&](int frag, int lane) -> float & { return f[(size_t)frag * 64 + lane]; };
+    auto rowmode = [](int lane, int rt) {
+        if (rt == 2) return 32 + lane % 4;
+        const int R = lane % 16;
+        return 16 * rt + 4 * (R % 4) + R / 4;
+    };
+    double xi[3];
+    for (int lane = 0; lane < 64; lane++) {
+        const int g = lane / 16;
+        for (int t = 0; t < 8; t++) {
+            const int qv = std::min(16 * t + lane % 16, Q - 1);  // the row's point (padding: the last)
+            B.point(qv, xi);
+            for (int st = 0; st < 9; st++) {
+                const int l = 4 * st + g;
+                if (l < N) at(K4_PHI + t * 9 + st, lane) = (float)B.phi(l, xi);
+            }
+            for (int st = 0; st < 4; st++) {
+                const int q = 16 * t + 4 * g + st;  // the K index's point
+                if (q >= Q) continue;
+                B.point(q, xi);
+                for (int rt = 0; rt < 3; rt++) {
+                    const int l = rowmode(lane, rt);
+                    if (l >= N) continue;
+                    for (int d = 0; d < 3; d++)
+                        at(K4_GRAD + ((t * 3 + d) * 3 + rt) * 4 + st, lane) =
+                            (float)(-s[d] * B.weight(q) * B.dphi(l, d, xi));
+                    at(K4_SRC + (t * 3 + rt) * 4 + st, lane) = (float)(-B.weight(q) * B.phi(l, xi) / 8.0);
+                }
+            }
+        }
+        for (int fc = 0; fc < 6; fc++) {
+            for (int ft = 0; ft < 2; ft++) {
+                B.face_point(fc, std::min(16 * ft + lane % 16, P - 1), xi);
+                for (int st = 0; st < 9; st++) {
+                    const int l = 4 * st + g;
+                    if (l < N) at(K4_TRACE + (fc * 2 + ft) * 9 + st, lane) = (float)B.phi(l, xi);
+                }
+            }
+            for (int st = 0; st < 8; st++) {
+                const int p = 16 * (st / 4) + 4 * g + st % 4;
+                if (p >= P) continue;
+                B.face_point(fc, p, xi);
+                const double c = ((fc & 1) ? 1.0 : -1.0) * s[fc / 2] * B.face_weight(p);
+                for (int rt = 0; rt < 3; rt++) {
+                    const int l = rowmode(lane, rt);
+                    if (l < N) at(K4_LIFT + (fc * 3 + rt) * 8 + st, lane) = (float)(c * B.phi(l, xi));
+                }
+            }
+        }
+    }
+    std::vector<char> blob(f.size() * 4);
+    std::memcpy(blob.data(), f.data(), blob.size());
+    return blob;
+}
+
 const char *kNoCtx = "invalid or NULL dg_ctx";
 // why the calling thread's last dg_init failed (no context survives to hold it)
 thread_local std::string g_init_err;
@@ -521,11 +589,14 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         dg_destroy(c);
         return st;
     };
-    // k = 3 in the BF16-product tiers: the kernel of stage_k3.hip
+    // k = 3 in the FP32-storage tiers: the kernel of stage_k3.hip; k = 4 in FP32: stage_k4.hip
     c->k3x = cfg->k == 3 && cfg->precision != DG_FP64;
+    c->k4m = cfg->k == 4 && cfg->precision == DG_FP32;
     if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
         std::vector<char> blob;
-        if (cfg->k == 4) {
+        if (c->k4m) {
+            blob = build_tables_k4(s);
+        } else if (cfg->k == 4) {
             blob = build_quad_tables(cfg->k, cfg->precision, s);
         } else if (c->k3x) {
             c->lay = make_layout(cfg->k, cfg->precision);
@@ -590,6 +661,16 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipMemset(c->slots, 0, 8 * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->flag, sizeof(int)) != hipSuccess) return fail(DG_ERR_HIP);
     if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
+    if (c->k4m) {  // one workgroup per compute unit (the tables fill its LDS)
+        int dev = 0, ncu = 0, per_cu = 0;
+        if (set_stage_k4_attributes() != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(DG_ERR_HIP);
+        per_cu = 1;
+        c->grid = ncu * per_cu;
+        *out = c;
+        return DG_OK;
+    }
     if (cfg->k == 0 || cfg->k == 4) {  // launch shapes set by their launchers
         c->grid = (int)std::min<long long>((ncells + 255) / 256, 1LL << 30);
         *out = c;
@@ -795,6 +876,8 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     s.dks = c->dks;
     if (c->k3x)
         HIPCHK(c, launch_stage_k3(c->cfg.precision, s, c->grid, c->lds, c->stream));
+    else if (c->k4m)
+        HIPCHK(c, launch_stage_k4(s, c->grid, c->stream));
     else
         HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
     return DG_OK;

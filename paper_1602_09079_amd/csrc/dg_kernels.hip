@@ -963,9 +963,9 @@ static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// k = 4 (N = 35 modes, 125 volume points): the quadrature form of the volume and surface
+// k = 4 (N = 35 modes, 125 volume points) in FP64: the quadrature form of the volume and surface
 // integrals (eqs. dg:eqn:volume_int, dg:eqn:surface_int) with one workgroup of two waves per cell,
-// no MFMA tiling.  The cell's weights and its six face neighbours' are staged in LDS; threads over
+// no MFMA tiling (FP32 runs the matrix-core kernel of stage_k4.hip).  The cell's weights and its six face neighbours' are staged in LDS; threads over
 // the volume points form the point states and their Euler fluxes (and the driving source), then
 // lanes over the modes contract them with the weighted basis gradients, each wave over half of
 // the points; threads over the 6 x 25 face points form both traces and the Riemann flux, and lanes
@@ -1228,8 +1228,7 @@ hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_b
     }
     if (k == 4) {
         switch (prec) {
-            case DG_FP64: return launch_quad_t<4, DG_FP64>(a, s);
-            case DG_FP32: return launch_quad_t<4, DG_FP32>(a, s);
+            case DG_FP64: return launch_quad_t<4, DG_FP64>(a, s);  // FP32: stage_k4.hip
             default: return hipErrorInvalidValue;
         }
     }
