@@ -389,8 +389,8 @@ __device__ inline double bload(double, __amdgpu_buffer_rsrc_t r, unsigned voff, 
 __device__ inline void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff = 0) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
 }
-__device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, 0, 0);
+__device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
 
 }  // namespace dgmi

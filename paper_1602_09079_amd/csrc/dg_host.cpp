@@ -328,71 +328,31 @@ std::vector<char> build_tables_k3(int prec, const double s[3]) {
     return blob;
 }
 
-// Tables of the quadrature-form stage kernel (k = 4), in the storage precision, in the kernel's
-// order: phi [l][q], grad [q][d][l] = s_d w_q dphi_l/dxi_d, src [q][l] = w_q phi_l / 8,
-// trace [f][l][p], lift [f][p][l] = (+/-) s_d w_p phi_l (+ on the + face of axis d = f / 2).
-std::vector<char> build_quad_tables(int k, int prec, const double s[3]) {
-    const Basis B(k);
-    const int N = B.N, Q = B.Q, P = B.P;
-    std::vector<double> t;
-    double xi[3];
-    for (int l = 0; l < N; l++)
-        for (int q = 0; q < Q; q++) {
-            B.point(q, xi);
-            t.push_back(B.phi(l, xi));
-        }
-    for (int q = 0; q < Q; q++) {
-        B.point(q, xi);
-        for (int d = 0; d < 3; d++)
-            for (int l = 0; l < N; l++) t.push_back(s[d] * B.weight(q) * B.dphi(l, d, xi));
-    }
-    for (int q = 0; q < Q; q++) {
-        B.point(q, xi);
-        for (int l = 0; l < N; l++) t.push_back(B.weight(q) * B.phi(l, xi) / 8.0);
-    }
-    for (int f = 0; f < 6; f++)
-        for (int l = 0; l < N; l++)
-            for (int p = 0; p < P; p++) {
-                B.face_point(f, p, xi);
-                t.push_back(B.phi(l, xi));
-            }
-    for (int f = 0; f < 6; f++)
-        for (int p = 0; p < P; p++) {
-            B.face_point(f, p, xi);
-            const double c = ((f & 1) ? 1.0 : -1.0) * s[f / 2] * B.face_weight(p);
-            for (int l = 0; l < N; l++) t.push_back(c * B.phi(l, xi));
-        }
-    std::vector<char> blob;
-    if (prec == DG_FP64) {
-        blob.resize(t.size() * 8);
-        std::memcpy(blob.data(), t.data(), blob.size());
-    } else {
-        std::vector<float> f(t.begin(), t.end());
-        blob.resize(f.size() * 4);
-        std::memcpy(blob.data(), f.data(), blob.size());
-    }
-    return blob;
-}
-
-// Tables of the k = 4 FP32 matrix-core stage kernel (stage_k4.hip), K4_NFRAG fragments of 64
-// floats in the order of dg_internal.h.  Lane L feeds row L % 16 and K index L / 16 of a 16x16x4
-// product; the last result tile (modes 32..34) runs as 4x4x1 products of 16 blocks, where lane L
-// feeds row L % 4 of its block.  Cell c's weights are the B operand with mode 4s + g at K step s
-// in lane group g; a result row R = 4g' + r of row tile rt is mode 16 rt + 4 r + g'; the point
-// and face-point products take K index g at step s to be the point in register s of lane group g
-// of the product that made it (point 16 t + 4 g + s of volume tile t; face row 16 (s / 4) + 4 g +
-// s % 4).  Padding rows: the value and trace tables repeat the last point, the tables that take
-// their results are zero there.
-std::vector<char> build_tables_k4(const double s[3]) {
+// Tables of the k = 4 matrix-core stage kernel (stage_k4.hip), K4_NFRAG fragments of 64 values
+// in the storage precision, in the order of dg_internal.h.  Lane L feeds row L % 16 and K index
+// L / 16 of a 16x16x4 product; in FP32 the last result tile (modes 32..34) runs as 4x4x1 products
+// of 16 blocks, where lane L feeds row L % 4 of its block.  Cell c's weights are the B operand with
+// mode 4s + g at K step s in lane group g.  A result lands in register r of lane group g from row
+// 4g + r (FP32) or g + 4r (FP64); the row of mode 16 rt + 4 r + g is chosen so that lane group g
+// gets the modes it holds.  The point and face-point products take K index g at step s to be the
+// point in register s of lane group g of the product that made it.  Padding rows: the value and
+// trace tables repeat the last point, the tables that take their results are zero there.
+std::vector<char> build_tables_k4(int prec, const double s[3]) {
     const Basis B(4);
     constexpr int N = 35, Q = 125, P = 25;
-    std::vector<float> f((size_t)K4_NFRAG * 64, 0.0f);
-    auto at = [&](int frag, int lane) -> float & { return f[(size_t)frag * 64 + lane]; };
-    auto rowmode = [](int lane, int rt) {
-        if (rt == 2) return 32 + lane % 4;
+    const bool f64 = prec == DG_FP64;
+    std::vector<double> f((size_t)K4_NFRAG * 64, 0.0);
+    auto at = [&](int frag, int lane) -> double & { return f[(size_t)frag * 64 + lane]; };
+    // result row R of a 16x16 tile -> (lane group, register)
+    auto grp = [&](int R) { return f64 ? R % 4 : R / 4; };
+    auto reg = [&](int R) { return f64 ? R / 4 : R % 4; };
+    auto rowmode = [&](int lane, int rt) {
+        if (rt == 2 && !f64) return 32 + lane % 4;
         const int R = lane % 16;
-        return 16 * rt + 4 * (R % 4) + R / 4;
+        return 16 * rt + 4 * reg(R) + grp(R);
     };
+    // the row of register r of lane group g
+    auto row_of = [&](int g, int r) { return f64 ? g + 4 * r : 4 * g + r; };
     double xi[3];
     for (int lane = 0; lane < 64; lane++) {
         const int g = lane / 16;
@@ -401,19 +361,18 @@ std::vector<char> build_tables_k4(const double s[3]) {
             B.point(qv, xi);
             for (int st = 0; st < 9; st++) {
                 const int l = 4 * st + g;
-                if (l < N) at(K4_PHI + t * 9 + st, lane) = (float)B.phi(l, xi);
+                if (l < N) at(K4_PHI + t * 9 + st, lane) = B.phi(l, xi);
             }
             for (int st = 0; st < 4; st++) {
-                const int q = 16 * t + 4 * g + st;  // the K index's point
+                const int q = 16 * t + row_of(g, st);  // the K index's point
                 if (q >= Q) continue;
                 B.point(q, xi);
                 for (int rt = 0; rt < 3; rt++) {
                     const int l = rowmode(lane, rt);
                     if (l >= N) continue;
                     for (int d = 0; d < 3; d++)
-                        at(K4_GRAD + ((t * 3 + d) * 3 + rt) * 4 + st, lane) =
-                            (float)(-s[d] * B.weight(q) * B.dphi(l, d, xi));
-                    at(K4_SRC + (t * 3 + rt) * 4 + st, lane) = (float)(-B.weight(q) * B.phi(l, xi) / 8.0);
+                        at(K4_GRAD + ((t * 3 + d) * 3 + rt) * 4 + st, lane) = -s[d] * B.weight(q) * B.dphi(l, d, xi);
+                    at(K4_SRC + (t * 3 + rt) * 4 + st, lane) = -B.weight(q) * B.phi(l, xi) / 8.0;
                 }
             }
         }
@@ -422,23 +381,30 @@ std::vector<char> build_tables_k4(const double s[3]) {
                 B.face_point(fc, std::min(16 * ft + lane % 16, P - 1), xi);
                 for (int st = 0; st < 9; st++) {
                     const int l = 4 * st + g;
-                    if (l < N) at(K4_TRACE + (fc * 2 + ft) * 9 + st, lane) = (float)B.phi(l, xi);
+                    if (l < N) at(K4_TRACE + (fc * 2 + ft) * 9 + st, lane) = B.phi(l, xi);
                 }
             }
             for (int st = 0; st < 8; st++) {
-                const int p = 16 * (st / 4) + 4 * g + st % 4;
+                const int p = 16 * (st / 4) + row_of(g, st % 4);
                 if (p >= P) continue;
                 B.face_point(fc, p, xi);
                 const double c = ((fc & 1) ? 1.0 : -1.0) * s[fc / 2] * B.face_weight(p);
                 for (int rt = 0; rt < 3; rt++) {
                     const int l = rowmode(lane, rt);
-                    if (l < N) at(K4_LIFT + (fc * 3 + rt) * 8 + st, lane) = (float)(c * B.phi(l, xi));
+                    if (l < N) at(K4_LIFT + (fc * 3 + rt) * 8 + st, lane) = c * B.phi(l, xi);
                 }
             }
         }
     }
-    std::vector<char> blob(f.size() * 4);
-    std::memcpy(blob.data(), f.data(), blob.size());
+    std::vector<char> blob;
+    if (f64) {
+        blob.resize(f.size() * 8);
+        std::memcpy(blob.data(), f.data(), blob.size());
+    } else {
+        std::vector<float> h(f.begin(), f.end());
+        blob.resize(h.size() * 4);
+        std::memcpy(blob.data(), h.data(), blob.size());
+    }
     return blob;
 }
 
@@ -551,7 +517,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
                     DG_ZHALO))
         return reject(DG_ERR_ARG, "unknown flags");
     if (cfg->k > 4) return reject(DG_ERR_UNSUPPORTED, "k > 4");
-    // k = 4 runs the quadrature-form kernel: FP64 and FP32 storage
+    // k = 4 runs the matrix-core kernel of stage_k4.hip: FP64 and FP32 storage
     if (cfg->k == 4 && cfg->precision != DG_FP64 && cfg->precision != DG_FP32)
         return reject(DG_ERR_UNSUPPORTED, "k = 4 takes FP64 or FP32 storage only");
     if ((cfg->flags & DG_CLOSURE) && cfg->k != 1) return reject(DG_ERR_UNSUPPORTED, "DG_CLOSURE needs k = 1");
@@ -589,15 +555,13 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         dg_destroy(c);
         return st;
     };
-    // k = 3 in the FP32-storage tiers: the kernel of stage_k3.hip; k = 4 in FP32: stage_k4.hip
+    // k = 3 in the FP32-storage tiers: the kernel of stage_k3.hip; k = 4: stage_k4.hip
     c->k3x = cfg->k == 3 && cfg->precision != DG_FP64;
-    c->k4m = cfg->k == 4 && cfg->precision == DG_FP32;
+    c->k4m = cfg->k == 4;
     if (cfg->k >= 1) {  // k = 0 runs the finite-volume kernel, which needs no product tables
         std::vector<char> blob;
         if (c->k4m) {
-            blob = build_tables_k4(s);
-        } else if (cfg->k == 4) {
-            blob = build_quad_tables(cfg->k, cfg->precision, s);
+            blob = build_tables_k4(cfg->precision, s);
         } else if (c->k3x) {
             c->lay = make_layout(cfg->k, cfg->precision);
             blob = build_tables_k3(cfg->precision, s);
@@ -663,7 +627,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
     if (hipMalloc(&c->partials, (size_t)(NF * c->nparts + 8) * sizeof(double)) != hipSuccess) return fail(DG_ERR_HIP);
     if (c->k4m) {  // one workgroup per compute unit (the tables fill its LDS)
         int dev = 0, ncu = 0, per_cu = 0;
-        if (set_stage_k4_attributes() != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        if (set_stage_k4_attributes(cfg->precision) != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return fail(DG_ERR_HIP);
         per_cu = 1;
@@ -671,7 +635,7 @@ dg_status dg_init(const dg_config *cfg, void *hip_stream, dg_ctx **out) {
         *out = c;
         return DG_OK;
     }
-    if (cfg->k == 0 || cfg->k == 4) {  // launch shapes set by their launchers
+    if (cfg->k == 0) {  // launch shape set by its launcher
         c->grid = (int)std::min<long long>((ncells + 255) / 256, 1LL << 30);
         *out = c;
         return DG_OK;
@@ -877,7 +841,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
     if (c->k3x)
         HIPCHK(c, launch_stage_k3(c->cfg.precision, s, c->grid, c->lds, c->stream));
     else if (c->k4m)
-        HIPCHK(c, launch_stage_k4(s, c->grid, c->stream));
+        HIPCHK(c, launch_stage_k4(c->cfg.precision, s, c->grid, c->stream));
     else
         HIPCHK(c, launch_stage(c->cfg.k, c->cfg.precision, s, c->grid, c->lds, c->stream));
     return DG_OK;

@@ -76,16 +76,17 @@ constexpr int K3_DKS = 2;            // K steps (of 4) of the driving product: w
 // driving factor table per (z, y) row of cells: [component][z-node][K step][lane] floats
 __host__ __device__ inline long long k3_drive_row_floats(int dks) { return 3LL * 4 * dks * 64; }
 
-// k = 4 FP32 stage kernel (stage_k4.hip): A-operand fragments of its 16x16x4 / 4x4x1 products
-// (64 floats each), in this order: PHI[t][s] (values at the 16 points of volume tile t, K step s
+// k = 4 stage kernel (stage_k4.hip): A-operand fragments of its 16x16x4 / 4x4x1 products
+// (64 values each, in the storage precision), in this order: PHI[t][s] (values at the 16 points of volume tile t, K step s
 // over the modes), GRAD[t][d][rt][s] (minus the weighted d-derivatives, result row tile rt, K step
 // s over the tile's points), SRC[t][rt][s] (minus the weighted basis / 8), TRACE[f][ft][s] (values
 // at the 16 points of face tile ft of face f), then LIFT[f][rt][s] (K step s over the face's 32
-// rows).  Everything before LIFT is staged in LDS.
+// rows).
 constexpr int K4_BLK = 14;  // cells updated per x-block (16 columns with the two halo cells)
 constexpr int K4_PHI = 0, K4_GRAD = K4_PHI + 8 * 9, K4_SRC = K4_GRAD + 8 * 3 * 3 * 4, K4_TRACE = K4_SRC + 8 * 3 * 4,
               K4_LIFT = K4_TRACE + 6 * 2 * 9, K4_NFRAG = K4_LIFT + 6 * 3 * 8;
-constexpr int K4_LDS_FRAGS = K4_LIFT, K4_LDS_BYTES = K4_LDS_FRAGS * 64 * 4;
+// LDS of the kernel: FP32 the fragments before LIFT, FP64 (8-byte values) the GRAD fragments
+constexpr int k4_lds_bytes(int prec) { return prec == DG_FP64 ? (K4_SRC - K4_GRAD) * 64 * 8 : K4_LIFT * 64 * 4; }
 
 // Stage kernel launch shape.  FP32-storage tiers: workgroups of 8 waves that own
 // 8 consecutive y rows of one x-block and sweep z together, sharing y-face traces
@@ -217,8 +218,8 @@ hipError_t set_stage_attributes(int k, int prec, int lds_bytes);
 hipError_t launch_stage_k3(int prec, const StageArgs &a, int grid, int lds_bytes, hipStream_t s);
 hipError_t set_stage_k3_attributes(int prec, int lds_bytes);
 hipError_t stage_k3_occupancy(int prec, int lds_bytes, int *per_cu);
-hipError_t launch_stage_k4(const StageArgs &a, int grid, hipStream_t s);
-hipError_t set_stage_k4_attributes();
+hipError_t launch_stage_k4(int prec, const StageArgs &a, int grid, hipStream_t s);
+hipError_t set_stage_k4_attributes(int prec);
 // driving factor table of the k = 3 kernel: modes [m][9] as for the cache (n as doubles, then
 // Re/Im of the three components), wave vectors with n_x >= 0
 hipError_t launch_drive_table_k3(const double *modes, int nmodes, int dks, int ny, int nz, const GaussNodes &xg,
@@ -307,7 +308,7 @@ struct dg_ctx {
     void *acache = nullptr;        // driving acceleration at the volume points (storage type)
     // k = 3 in the FP32-storage tiers runs stage_k3_kernel (16-cell x-blocks, driving as a product)
     bool k3x = false;
-    bool k4m = false;  // k = 4 in FP32: the matrix-core kernel of stage_k4.hip
+    bool k4m = false;  // k = 4 in FP32 / FP64: the matrix-core kernel of stage_k4.hip
     float *dtab = nullptr;         // its driving factor table, per (z, y) row
     float *dcs = nullptr;          // cos / sin of the x phases, per x
     int dks = 0;                   // K steps of the driving product

@@ -963,218 +963,6 @@ static hipError_t launch_fv_t(const StageArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// k = 4 (N = 35 modes, 125 volume points) in FP64: the quadrature form of the volume and surface
-// integrals (eqs. dg:eqn:volume_int, dg:eqn:surface_int) with one workgroup of two waves per cell,
-// no MFMA tiling (FP32 runs the matrix-core kernel of stage_k4.hip).  The cell's weights and its six face neighbours' are staged in LDS; threads over
-// the volume points form the point states and their Euler fluxes (and the driving source), then
-// lanes over the modes contract them with the weighted basis gradients, each wave over half of
-// the points; threads over the 6 x 25 face points form both traces and the Riemann flux, and lanes
-// over the modes lift it, each wave over half of the faces; the two waves' sums meet in LDS.  Each
-// face is solved by both of its cells with the same arithmetic, so the two get the same flux.
-// Tables (in the storage precision, built at init; s_d = 1/(4 h_d)):
-//   phi  [l][q]    phi_l(xi_q)
-//   grad [q][d][l] s_d w_q d/dxi_d phi_l(xi_q)
-//   src  [q][l]    w_q phi_l(xi_q) / 8
-//   trace[f][l][p] phi_l at point p of face f = 2 d + side (side 1: the + face)
-//   lift [f][p][l] (+/-) s_d w_p phi_l at that point, + on the + face
-
-// for (i = 0; i < n; i++) f(i), unrolled U times (U = 0: as the compiler chooses)
-template <int U, class F>
-__device__ inline void unrolled_for(int n, F &&f) {
-    if constexpr (U == 0) {
-        for (int i = 0; i < n; i++) f(i);
-    } else {
-#pragma unroll U
-        for (int i = 0; i < n; i++) f(i);
-    }
-}
-
-template <int K>
-struct QuadTab {
-    static constexpr int N = Dims<K>::N, Q = Dims<K>::Q, P = Dims<K>::P;
-    static constexpr int phi = 0, grad = N * Q, src = grad + 3 * Q * N, trace = src + Q * N, lift = trace + 6 * N * P,
-                         total = lift + 6 * P * N;
-};
-constexpr int QS_THREADS = 128;  // two waves per cell: twice the waves in flight for the same LDS
-
-template <int K, int PREC, bool FORCE, int RS>
-__global__ __launch_bounds__(QS_THREADS) void quad_stage_kernel(StageArgs a) {
-    using PR = Prec<PREC>;
-    using S = typename PR::S;
-    using C = typename PR::C;
-    using T = QuadTab<K>;
-    constexpr int N = T::N, Q = T::Q, P = T::P, E = NF * N;
-    constexpr int WORK = (3 * NF + 4) * Q;  // point fluxes [d][i][q] and sources [c][q]; later face fluxes
-    static_assert(WORK >= NF * 6 * P && N <= 64 && QS_THREADS == 128, "quadrature kernel shape");
-    // the mode-parallel contractions split their point (face point) range between the two waves
-    constexpr int QH = (Q + 1) / 2, FH = 3 * P;
-    // unrolled inner loops batch the table loads
-    constexpr int U7 = 7, U5 = 7, U6 = 5;
-    __shared__ C ys[7][E];  // the cell, then its -x, +x, -y, +y, -z, +z neighbours: [i * N + l]
-    __shared__ C work[WORK];
-    const C *tab = static_cast<const C *>(a.tables);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    double dtd = a.dt;
-    if (a.rate) dtd = a.dtfac / a.rate[0];
-    if (a.tacc && blockIdx.x == 0 && tid == 0) a.tacc[0] += dtd;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const C gam = (C)a.gamma, g1 = gam - C(1);
-    const S *yin = static_cast<const S *>(a.yin);
-    const S *y0 = static_cast<const S *>(a.y0);
-    S *out = static_cast<S *>(a.out);
-    auto flux = [&](auto axis_c, const C qL[5], const C qR[5], C F[5]) {
-        constexpr int AX = decltype(axis_c)::value;
-        if constexpr (RS == 1)
-            exact_rs<PR, AX>(qL, qR, gam, F);
-        else
-            hllc<PR, AX>(qL, qR, gam, F);
-    };
-    for (long long cell = blockIdx.x; cell < a.ncells; cell += gridDim.x) {
-        const int ix = (int)(cell % nx);
-        const long long row = cell / nx;
-        const int iy = (int)(row % ny), iz = (int)(row / ny);
-        for (int j = tid; j < 7 * E; j += QS_THREADS) {
-            const int c = j / E, e = j - c * E;
-            int x = ix, yy = iy, zz = iz;
-            if (c > 0) {
-                const int ax = (c - 1) >> 1, sd = (c & 1) ? -1 : 1;  // c = 1, 3, 5: the - side
-                if (ax == 0) x += sd;
-                else if (ax == 1) yy += sd;
-                else zz += sd;
-            }
-            x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-            yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-            const S *src = yin;
-            if (a.halo_lo && zz < 0) {  // across the ends of a z slab: the halo planes
-                src = static_cast<const S *>(a.halo_lo);
-                zz = 0;
-            } else if (a.halo_hi && zz >= nz) {
-                src = static_cast<const S *>(a.halo_hi);
-                zz = 0;
-            } else {
-                zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-            }
-            ys[c][e] = (C)src[(((long long)zz * ny + yy) * E + e) * nx + x];
-        }
-        __syncthreads();
-        // volume points: state, the three directional fluxes, the driving source
-        for (int q = tid; q < Q; q += QS_THREADS) {
-            C u[NF] = {0, 0, 0, 0, 0};
-            unrolled_for<U7>(N, [&](int l) {
-                const C ph = tab[T::phi + l * Q + q];
-#pragma unroll
-                for (int i = 0; i < NF; i++) u[i] += ys[0][i * N + l] * ph;
-            });
-            C F[3][5];
-            euler_flux3<PR>(u, g1, F);
-#pragma unroll
-            for (int d = 0; d < 3; d++)
-#pragma unroll
-                for (int i = 0; i < NF; i++) work[(d * NF + i) * Q + q] = F[d][i];
-            if constexpr (FORCE) {
-                const int t = q / 16, rr = q % 16;  // the driving cache's point tiles
-                const int g = PREC == DG_FP64 ? rr % 4 : rr / 4, r = PREC == DG_FP64 ? rr / 4 : rr % 4;
-                const S *ac = static_cast<const S *>(a.acache) + row * ((long long)((Q + 15) / 16) * 16 * 3 * nx);
-                C sE = 0;
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const C av = (C)ac[(((long long)(t * 3 + c) * 4 + g) * nx + ix) * 4 + r];
-                    work[(3 * NF + c) * Q + q] = u[0] * av;
-                    sE += u[1 + c] * av;
-                }
-                work[(3 * NF + 3) * Q + q] = sE;
-            }
-        }
-        __syncthreads();
-        C acc[NF] = {0, 0, 0, 0, 0};
-        if (lane < N) {
-            unrolled_for<U5>(QH, [&](int qq) {
-                const int q = wave * QH + qq;
-                if (q >= Q) return;
-#pragma unroll
-                for (int d = 0; d < 3; d++) {
-                    const C gt = tab[T::grad + (q * 3 + d) * N + lane];
-#pragma unroll
-                    for (int i = 0; i < NF; i++) acc[i] -= work[(d * NF + i) * Q + q] * gt;
-                }
-                if constexpr (FORCE) {
-                    const C st = tab[T::src + q * N + lane];
-#pragma unroll
-                    for (int c = 0; c < 4; c++) acc[1 + c] -= work[(3 * NF + c) * Q + q] * st;
-                }
-            });
-        }
-        __syncthreads();
-        // face points: the cell's trace, the neighbour's trace on the same face, the Riemann flux
-        for (int j = tid; j < 6 * P; j += QS_THREADS) {
-            const int f = j / P, p = j - f * P;
-            C uo[NF] = {0, 0, 0, 0, 0}, un[NF] = {0, 0, 0, 0, 0};
-            unrolled_for<U7>(N, [&](int l) {
-                const C to = tab[T::trace + (f * N + l) * P + p], tn = tab[T::trace + ((f ^ 1) * N + l) * P + p];
-#pragma unroll
-                for (int i = 0; i < NF; i++) {
-                    uo[i] += ys[0][i * N + l] * to;
-                    un[i] += ys[1 + f][i * N + l] * tn;
-                }
-            });
-            C F[5];
-            const bool plus = f & 1;
-            const C *qL = plus ? uo : un, *qR = plus ? un : uo;
-            switch (f >> 1) {
-                case 0: flux(std::integral_constant<int, 0>{}, qL, qR, F); break;
-                case 1: flux(std::integral_constant<int, 1>{}, qL, qR, F); break;
-                default: flux(std::integral_constant<int, 2>{}, qL, qR, F); break;
-            }
-#pragma unroll
-            for (int i = 0; i < NF; i++) work[(i * 6 + f) * P + p] = F[i];
-        }
-        __syncthreads();
-        if (lane < N) {
-            unrolled_for<U6>(FH, [&](int ff) {
-                const int fp = wave * FH + ff;
-                const C lt = tab[T::lift + fp * N + lane];
-#pragma unroll
-                for (int i = 0; i < NF; i++) acc[i] += work[i * 6 * P + fp] * lt;
-            });
-        }
-        __syncthreads();  // the face fluxes are read; the second wave's sums go through LDS
-        if (wave == 1 && lane < N) {
-#pragma unroll
-            for (int i = 0; i < NF; i++) work[i * N + lane] = acc[i];
-        }
-        __syncthreads();
-        if (wave == 0 && lane < N) {
-#pragma unroll
-            for (int i = 0; i < NF; i++) acc[i] += work[i * N + lane];
-            const C dt = (C)dtd;
-#pragma unroll
-            for (int i = 0; i < NF; i++) {
-                const long long j = (row * E + i * N + lane) * nx + ix;
-                if (a.mode == 0) {
-                    out[j] = (S)acc[i];
-                } else {
-                    const C base = (C)a.b * (ys[0][i * N + lane] - dt * acc[i]);
-                    out[j] = (S)(a.a != 0.0 ? (C)a.a * (C)y0[j] + base : base);
-                }
-            }
-        }
-        __syncthreads();  // the next cell overwrites ys and work
-    }
-}
-
-template <int K, int PREC>
-static hipError_t launch_quad_t(const StageArgs &a, hipStream_t s) {
-    const long long grid = a.ncells < (1LL << 20) ? a.ncells : (1LL << 20);
-    if (a.riemann == 1) {
-        if (a.forcing) hipLaunchKernelGGL((quad_stage_kernel<K, PREC, true, 1>), dim3(grid), dim3(QS_THREADS), 0, s, a);
-        else hipLaunchKernelGGL((quad_stage_kernel<K, PREC, false, 1>), dim3(grid), dim3(QS_THREADS), 0, s, a);
-    } else {
-        if (a.forcing) hipLaunchKernelGGL((quad_stage_kernel<K, PREC, true, 0>), dim3(grid), dim3(QS_THREADS), 0, s, a);
-        else hipLaunchKernelGGL((quad_stage_kernel<K, PREC, false, 0>), dim3(grid), dim3(QS_THREADS), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
 template <int K, int PREC>
 static hipError_t launch_stage_t(const StageArgs &a, int grid, int lds_bytes, hipStream_t s) {
     constexpr int T = stage_threads<PREC>();
@@ -1223,12 +1011,6 @@ hipError_t launch_stage(int k, int prec, const StageArgs &a, int grid, int lds_b
             case DG_FP32: return launch_fv_t<DG_FP32>(a, s);
             case DG_BF16: return launch_fv_t<DG_BF16>(a, s);
             case DG_BF16X3: return launch_fv_t<DG_BF16X3>(a, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (k == 4) {
-        switch (prec) {
-            case DG_FP64: return launch_quad_t<4, DG_FP64>(a, s);  // FP32: stage_k4.hip
             default: return hipErrorInvalidValue;
         }
     }

@@ -1,9 +1,9 @@
 // The SSP stage kernel for k = 4 (N = 35 modes, 5^3 volume points, 5^2 points per face) in FP32
-// on the matrix cores.  It evaluates the same quadrature form as quad_stage_kernel in
+// and FP64 on the matrix cores.  It evaluates the same quadrature form as quad_stage_kernel in
 // dg_kernels.hip (Bauer et al., arXiv 1602.09079, Sec. 2.3, eqs. dg:eqn:volume_int and
 // dg:eqn:surface_int, the driving source of Sec. 3.1, the Shu-Osher combine of the SSP-RK3
-// step), with the cells of an x-block as the columns of 16x16x4 FP32 MFMAs and the basis tables
-// as their A operands:
+// step), with the cells of an x-block as the columns of 16x16x4 FP32 / FP64 MFMAs and the basis
+// tables as their A operands:
 //
 // - One wave per x-block: 16 consecutive cells of a (z, y) row, columns 1..14 updated, columns 0
 //   and 15 the halo of the x faces.  Lane (g, c) holds cell c and, of every field, the modes
@@ -11,9 +11,10 @@
 // - Volume, one tile of 16 points at a time: point values (8 tiles of 16 rows over the 125
 //   points, 9 K steps), the Euler fluxes and the driving source at the lane's 4 points, then
 //   their contraction with the weighted gradients and basis (K = the tile's 16 points, 4 steps).
-// - Result rows: row 4g' + r of row tile t (t = 0, 1) is mode 16t + 4r + g', so that a lane's
-//   results are the modes it holds; the last tile (modes 32..34, one row per lane group) runs as
-//   4x4x1 products of 16 blocks (a quarter of the cost) summed across the lane groups at the end.
+// - Result rows: the mode of each row is chosen so that register r of lane group g' of row tile t
+//   is mode 16t + 4r + g', the modes the lane holds (FP32 results: row 4g' + r; FP64: row g' + 4r).
+//   FP32: the last tile (modes 32..34, one row per lane group) runs as 4x4x1 products of 16 blocks
+//   (a quarter of the cost) summed across the lane groups at the end.
 // - Faces, one tile of 16 points at a time (2 tiles over the 25 points): the traces of the cell
 //   and of its neighbour on the face, the Riemann flux at the lane's 4 points, the lift (K = the
 //   32 face rows, 8 steps).  x faces: the neighbour is the next column (DPP row shifts), each
@@ -21,9 +22,11 @@
 //   face solved by both of its cells with the same arithmetic, so that they get the same flux.
 // - Padding rows repeat the last point in the trace and value tables (a valid state) and are zero
 //   in the tables that take their results, so they add nothing.
-// - The tables of the volume products and the traces (141 KiB) sit in LDS, shared by the eight
-//   waves of the one workgroup per compute unit; the lift tables (36 KiB) are read through the
-//   caches.  The waves take x-blocks independently (no barrier after the table copy).
+// - FP32: the tables of the volume products and the traces (141 KiB) sit in LDS, shared by the
+//   eight waves (two per SIMD) of the one workgroup per compute unit, the lift tables (36 KiB) are
+//   read through the caches.  FP64: the gradient tables (144 KiB) sit in LDS, the rest is read
+//   through the caches, and one wave per SIMD holds the weights and results in 512 registers.
+//   The waves take x-blocks independently (no barrier after the table copy).
 
 #include "dg_device.h"
 
@@ -31,32 +34,57 @@ namespace dgmi {
 
 namespace {
 
-constexpr int K4_THREADS = 512;
 constexpr int K4_NM = 35, K4_E = NF * K4_NM;
+constexpr int k4_threads(int prec) { return prec == DG_FP64 ? 256 : 512; }
 
 // DPP row shifts within 16-lane rows: row_shl:1 (lane c <- lane c + 1), row_shr:1 (lane c <- c - 1)
-__device__ inline float shl1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, true));
+template <int CTRL>
+__device__ inline float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
 }
-__device__ inline float shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+template <int CTRL>
+__device__ inline double dpp(double v) {
+    const u2 h = __builtin_bit_cast(u2, v);
+    const u2 o = {(unsigned)__builtin_amdgcn_update_dpp(0, (int)h.x, CTRL, 0xf, 0xf, true),
+                  (unsigned)__builtin_amdgcn_update_dpp(0, (int)h.y, CTRL, 0xf, 0xf, true)};
+    return __builtin_bit_cast(double, o);
 }
+template <class T>
+__device__ inline T shl1(T v) {
+    return dpp<0x101>(v);
+}
+template <class T>
+__device__ inline T shr1(T v) {
+    return dpp<0x111>(v);
+}
+__device__ inline f4 mfma16(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
+__device__ inline d4 mfma16(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
+// the last row tile: FP32 4x4x1 products of 16 blocks, FP64 a full 16x16x4 product
+__device__ inline f4 mfma_last(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_4x4x1f32(x, y, c, 0, 0, 0); }
+__device__ inline d4 mfma_last(double x, double y, d4 c) { return mfma16(x, y, c); }
 
 }  // namespace
 
-template <bool FORCE, int RS>
-__global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void stage_k4_kernel(StageArgs a) {
-    using PR = Prec<DG_FP32>;
-    using C = float;
+template <int PREC, bool FORCE, int RS>
+__global__ __launch_bounds__(k4_threads(PREC))
+__attribute__((amdgpu_waves_per_eu(PREC == DG_FP64 ? 1 : 2, PREC == DG_FP64 ? 1 : 2))) void stage_k4_kernel(StageArgs a) {
+    constexpr bool F64 = PREC == DG_FP64;
+    constexpr int THREADS = k4_threads(PREC);
+    using PR = Prec<PREC>;
+    using C = typename PR::C;
+    using Acc = typename PR::Acc;
+    constexpr int ESZ = sizeof(C);
+    // the fragments staged in LDS: FP32 all before the lift tables, FP64 the gradient tables
+    constexpr int L0 = F64 ? K4_GRAD : 0, L1 = F64 ? K4_SRC : K4_LIFT;
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
-        const int4 *src = reinterpret_cast<const int4 *>(a.tables);
+        const int4 *src = reinterpret_cast<const int4 *>(static_cast<const char *>(a.tables) + (size_t)L0 * 64 * ESZ);
         int4 *dst = reinterpret_cast<int4 *>(lds);
-        for (int j = threadIdx.x; j < K4_LDS_FRAGS * 64 / 4; j += K4_THREADS) dst[j] = src[j];
+        for (int j = threadIdx.x; j < (L1 - L0) * 64 * ESZ / 16; j += THREADS) dst[j] = src[j];
         __syncthreads();
     }
-    const float *ltab = reinterpret_cast<const float *>(lds);
-    const float *gtab = static_cast<const float *>(a.tables);
+    const C *ltab = reinterpret_cast<const C *>(lds);
+    const C *gtab = static_cast<const C *>(a.tables);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & 15;
@@ -68,10 +96,10 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     if (a.tacc && blockIdx.x == 0 && threadIdx.x == 0) a.tacc[0] += dtd;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const long long slabn = (long long)K4_E * nx;  // elements per (z, y) row of cells
-    const float *yin = static_cast<const float *>(a.yin);
-    const float *y0 = static_cast<const float *>(a.y0);
-    float *out = static_cast<float *>(a.out);
-    const unsigned mstride = (unsigned)nx * 4u;  // bytes between modes
+    const C *yin = static_cast<const C *>(a.yin);
+    const C *y0 = static_cast<const C *>(a.y0);
+    C *out = static_cast<C *>(a.out);
+    const unsigned mstride = (unsigned)nx * ESZ;  // bytes between modes
 
     // A operand of one product step (a fragment: one value per lane).  The lane offset is made
     // opaque at each use, so that the compiler forms no per-fragment address to keep (and spill)
@@ -82,40 +110,39 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         asm volatile("" : "+v"(o));
         return o;
     };
-    auto A = [&](int frag) -> float { return ltab[frag * 64 + lane_off()]; };
-    const auto lrs = slab_rsrc(gtab + K4_LIFT * 64, (long long)(K4_NFRAG - K4_LIFT) * 64, 0);
-    auto AG = [&](int frag) -> float {
-        return bload(0.0f, lrs, (unsigned)lane_off() * 4u, (unsigned)(frag - K4_LIFT) * 256u);
+    const auto trs = slab_rsrc(gtab, (long long)K4_NFRAG * 64, 0);
+    auto A = [&](int frag) -> C {
+        if (frag >= L0 && frag < L1) return ltab[(frag - L0) * 64 + lane_off()];
+        return bload(C(0), trs, (unsigned)lane_off() * ESZ, (unsigned)frag * 64u * ESZ);
     };
-    auto mfma16 = [](float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); };
-    auto mfma4 = [](float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_4x4x1f32(x, y, c, 0, 0, 0); };
     // the weights of the block in row r of base (modes 4s + g of cell column col at x)
-    auto load_b = [&](const float *base, long long r, unsigned xb, C b[NF][9]) {
+    auto load_b = [&](const C *base, long long r, unsigned xb, C b[NF][9]) {
         const auto rs = slab_rsrc(base, slabn, r);
         const unsigned vo = (unsigned)g * mstride + xb;
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int s = 0; s < 9; s++) b[i][s] = bload(0.0f, rs, vo, (unsigned)(i * K4_NM + 4 * s) * mstride);
+            for (int s = 0; s < 9; s++) b[i][s] = bload(C(0), rs, vo, (unsigned)(i * K4_NM + 4 * s) * mstride);
     };
     // the neighbouring block across a y or z face (the z ends of a slab: the halo planes)
     auto load_nb = [&](int iy, int iz, unsigned xb, C b[NF][9]) {
         iy = iy < 0 ? iy + ny : (iy >= ny ? iy - ny : iy);
         if (a.halo_lo && iz < 0)
-            load_b(static_cast<const float *>(a.halo_lo), iy, xb, b);
+            load_b(static_cast<const C *>(a.halo_lo), iy, xb, b);
         else if (a.halo_hi && iz >= nz)
-            load_b(static_cast<const float *>(a.halo_hi), iy, xb, b);
+            load_b(static_cast<const C *>(a.halo_hi), iy, xb, b);
         else
             load_b(yin, (long long)(iz < 0 ? iz + nz : (iz >= nz ? iz - nz : iz)) * ny + iy, xb, b);
     };
-    // traces of a block on face f, face tile ft (face points 16 ft + 4 g + r in register r)
+    // traces of a block on face f, face tile ft (register r: face row 16 ft + 4 g + r in FP32,
+    // 16 ft + g + 4 r in FP64)
     auto trace = [&](int f, int ft, const C b[NF][9], C tr[NF][4]) {
-        f4 t[NF];
+        Acc t[NF];
 #pragma unroll
-        for (int i = 0; i < NF; i++) t[i] = f4{0, 0, 0, 0};
+        for (int i = 0; i < NF; i++) t[i] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < 9; s++) {
-            const float av = A(K4_TRACE + (f * 2 + ft) * 9 + s);
+            const C av = A(K4_TRACE + (f * 2 + ft) * 9 + s);
 #pragma unroll
             for (int i = 0; i < NF; i++) t[i] = mfma16(av, b[i][s], t[i]);
         }
@@ -143,20 +170,20 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         }
     };
     // lift of the flux at face tile ft of face f (K steps 4 ft .. 4 ft + 3)
-    auto lift = [&](int f, int ft, const C F[NF][4], f4 acc[NF][3]) {
+    auto lift = [&](int f, int ft, const C F[NF][4], Acc acc[NF][3]) {
 #pragma unroll
         for (int rt = 0; rt < 3; rt++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const float av = AG(K4_LIFT + (f * 3 + rt) * 8 + 4 * ft + r);
+                const C av = A(K4_LIFT + (f * 3 + rt) * 8 + 4 * ft + r);
 #pragma unroll
                 for (int i = 0; i < NF; i++)
-                    acc[i][rt] = rt < 2 ? mfma16(av, F[i][r], acc[i][rt]) : mfma4(av, F[i][r], acc[i][rt]);
+                    acc[i][rt] = rt < 2 ? mfma16(av, F[i][r], acc[i][rt]) : mfma_last(av, F[i][r], acc[i][rt]);
             }
     };
-    // the last row tile's result (4x4x1 blocks: register r of lane group g holds group g's part of
-    // mode 32 + r) summed over the lane groups into register 0 (mode 32 + g)
-    auto tile_sum = [&](f4 c) -> f4 {
+    // FP32: the last row tile's result (4x4x1 blocks: register r of lane group g holds group g's
+    // part of mode 32 + r) summed over the lane groups into register 0 (mode 32 + g)
+    auto tile_sum = [&](Acc c) -> Acc {
         const bool hi2 = (g & 2) != 0, odd = (g & 1) != 0;
         const C k0 = hi2 ? c[2] : c[0], k1 = hi2 ? c[3] : c[1];
         const C s0 = hi2 ? c[0] : c[2], s1 = hi2 ? c[1] : c[3];
@@ -168,8 +195,8 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 
     const int nbx = (nx + K4_BLK - 1) / K4_BLK;
     const long long nitems = (long long)nbx * ny * nz;
-    for (long long item = (long long)blockIdx.x * (K4_THREADS / 64) + wave; item < nitems;
-         item += (long long)gridDim.x * (K4_THREADS / 64)) {
+    for (long long item = (long long)blockIdx.x * (THREADS / 64) + wave; item < nitems;
+         item += (long long)gridDim.x * (THREADS / 64)) {
         const int bx = (int)(item % nbx);
         const long long row = item / nbx;
         const int iy = (int)(row % ny), iz = (int)(row / ny);
@@ -177,30 +204,31 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const bool store = col >= 1 && col <= K4_BLK && x < nx;
         x = x < 0 ? x + nx : x;
         x = x >= nx ? x % nx : x;
-        const unsigned xb = (unsigned)x * 4u;
+        const unsigned xb = (unsigned)x * ESZ;
 
         C b[NF][9];
         load_b(yin, row, xb, b);
-        f4 acc[NF][3];
+        Acc acc[NF][3];
 #pragma unroll
         for (int i = 0; i < NF; i++)
 #pragma unroll
-            for (int rt = 0; rt < 3; rt++) acc[i][rt] = f4{0, 0, 0, 0};
+            for (int rt = 0; rt < 3; rt++) acc[i][rt] = Acc{0, 0, 0, 0};
 
-        // ---- volume: one tile of 16 points at a time
-        const f4 *ac = FORCE ? reinterpret_cast<const f4 *>(a.acache) + row * (96LL * nx) : nullptr;
+        // ---- volume: one tile of 16 points at a time (register r: point 16 t + 4 g + r in FP32,
+        // 16 t + g + 4 r in FP64, the layout of the driving cache)
+        const Acc *ac = FORCE ? reinterpret_cast<const Acc *>(a.acache) + row * (96LL * nx) : nullptr;
 #pragma unroll 1
         for (int t = 0; t < 8; t++) {
-            f4 d[NF];
+            Acc d[NF];
 #pragma unroll
-            for (int i = 0; i < NF; i++) d[i] = f4{0, 0, 0, 0};
+            for (int i = 0; i < NF; i++) d[i] = Acc{0, 0, 0, 0};
 #pragma unroll
             for (int s = 0; s < 9; s++) {
-                const float av = A(K4_PHI + t * 9 + s);
+                const C av = A(K4_PHI + t * 9 + s);
 #pragma unroll
                 for (int i = 0; i < NF; i++) d[i] = mfma16(av, b[i][s], d[i]);
             }
-            f4 acv[3];
+            Acc acv[3];
             if constexpr (FORCE) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) acv[c] = ac[((t * 3 + c) * 4 + g) * nx + x];
@@ -233,10 +261,10 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 for (int rt = 0; rt < 3; rt++)
 #pragma unroll
                     for (int s = 0; s < 4; s++) {
-                        const float av = A(K4_GRAD + ((t * 3 + dd) * 3 + rt) * 4 + s);
+                        const C av = A(K4_GRAD + ((t * 3 + dd) * 3 + rt) * 4 + s);
 #pragma unroll
                         for (int i = 0; i < NF; i++)
-                            acc[i][rt] = rt < 2 ? mfma16(av, F[i][s], acc[i][rt]) : mfma4(av, F[i][s], acc[i][rt]);
+                            acc[i][rt] = rt < 2 ? mfma16(av, F[i][s], acc[i][rt]) : mfma_last(av, F[i][s], acc[i][rt]);
                     }
             }
             if constexpr (FORCE) {
@@ -252,11 +280,11 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 for (int rt = 0; rt < 3; rt++)
 #pragma unroll
                     for (int s = 0; s < 4; s++) {
-                        const float av = A(K4_SRC + (t * 3 + rt) * 4 + s);
+                        const C av = A(K4_SRC + (t * 3 + rt) * 4 + s);
 #pragma unroll
                         for (int c = 0; c < 4; c++)
                             acc[1 + c][rt] =
-                                rt < 2 ? mfma16(av, S[c][s], acc[1 + c][rt]) : mfma4(av, S[c][s], acc[1 + c][rt]);
+                                rt < 2 ? mfma16(av, S[c][s], acc[1 + c][rt]) : mfma_last(av, S[c][s], acc[1 + c][rt]);
                     }
             }
         }
@@ -315,8 +343,10 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         asm volatile("" ::: "memory");
         // ---- combine and store: result register r of row tile t is mode 16 t + 4 r + g, which
         // this lane holds in b[i][4 t + r]
+        if constexpr (!F64) {
 #pragma unroll
-        for (int i = 0; i < NF; i++) acc[i][2] = tile_sum(acc[i][2]);
+            for (int i = 0; i < NF; i++) acc[i][2] = tile_sum(acc[i][2]);
+        }
         if (store) {
             const auto ro = slab_rsrc(out, slabn, row);
             const unsigned vo = (unsigned)g * mstride + xb;
@@ -339,7 +369,7 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                         if (s == 8 && g == 3) continue;
                         const unsigned so = (unsigned)(i * K4_NM + 4 * s) * mstride;
                         const C base = cb * (b[i][s] - dt * acc[i][s / 4][s % 4]);
-                        const C res = with_y0 ? ca * bload(0.0f, r0, vo, so) + base : base;
+                        const C res = with_y0 ? ca * bload(C(0), r0, vo, so) + base : base;
                         bstore(res, ro, vo, so);
                     }
             }
@@ -347,33 +377,50 @@ __global__ __launch_bounds__(K4_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 }
 
-template <bool FORCE, int RS>
+template <int PREC, bool FORCE, int RS>
 static const void *k4_fn() {
-    return reinterpret_cast<const void *>(&stage_k4_kernel<FORCE, RS>);
+    return reinterpret_cast<const void *>(&stage_k4_kernel<PREC, FORCE, RS>);
 }
 
-hipError_t launch_stage_k4(const StageArgs &a, int grid, hipStream_t s) {
+template <int PREC>
+static hipError_t launch_k4_t(const StageArgs &a, int grid, hipStream_t s) {
+    constexpr int T = k4_threads(PREC);
+    const int lds = k4_lds_bytes(PREC);
     if (a.riemann == 1) {
         if (a.forcing)
-            hipLaunchKernelGGL((stage_k4_kernel<true, 1>), dim3(grid), dim3(K4_THREADS), K4_LDS_BYTES, s, a);
+            hipLaunchKernelGGL((stage_k4_kernel<PREC, true, 1>), dim3(grid), dim3(T), lds, s, a);
         else
-            hipLaunchKernelGGL((stage_k4_kernel<false, 1>), dim3(grid), dim3(K4_THREADS), K4_LDS_BYTES, s, a);
+            hipLaunchKernelGGL((stage_k4_kernel<PREC, false, 1>), dim3(grid), dim3(T), lds, s, a);
     } else {
         if (a.forcing)
-            hipLaunchKernelGGL((stage_k4_kernel<true, 0>), dim3(grid), dim3(K4_THREADS), K4_LDS_BYTES, s, a);
+            hipLaunchKernelGGL((stage_k4_kernel<PREC, true, 0>), dim3(grid), dim3(T), lds, s, a);
         else
-            hipLaunchKernelGGL((stage_k4_kernel<false, 0>), dim3(grid), dim3(K4_THREADS), K4_LDS_BYTES, s, a);
+            hipLaunchKernelGGL((stage_k4_kernel<PREC, false, 0>), dim3(grid), dim3(T), lds, s, a);
     }
     return hipGetLastError();
 }
 
-hipError_t set_stage_k4_attributes() {
-    const void *fns[] = {k4_fn<false, 0>(), k4_fn<true, 0>(), k4_fn<false, 1>(), k4_fn<true, 1>()};
+hipError_t launch_stage_k4(int prec, const StageArgs &a, int grid, hipStream_t s) {
+    if (prec == DG_FP32) return launch_k4_t<DG_FP32>(a, grid, s);
+    if (prec == DG_FP64) return launch_k4_t<DG_FP64>(a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <int PREC>
+static hipError_t set_attr_k4_t() {
+    const void *fns[] = {k4_fn<PREC, false, 0>(), k4_fn<PREC, true, 0>(), k4_fn<PREC, false, 1>(),
+                         k4_fn<PREC, true, 1>()};
     for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, K4_LDS_BYTES);
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, k4_lds_bytes(PREC));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t set_stage_k4_attributes(int prec) {
+    if (prec == DG_FP32) return set_attr_k4_t<DG_FP32>();
+    if (prec == DG_FP64) return set_attr_k4_t<DG_FP64>();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dgmi

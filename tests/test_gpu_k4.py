@@ -1,5 +1,5 @@
 """GPU parity of degree k = 4 (N = 35 modes, 5^3 volume and 5^2 face Gauss points per
-cell: the quadrature-form stage kernel) against the FP64 oracle: R with HLLC and
+cell: the matrix-core stage kernel) against the FP64 oracle: R with HLLC and
 with the exact Riemann solver, with and without the driving; device-CFL steps in
 FP64 and FP32; the isothermal reset and sub-cell sampling at k = 4; the
 configurations k = 4 does not take (the limiter at k = 4 is in the limiter tests)."""
