@@ -88,6 +88,7 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
     const int col = lane & 15;
     const int g = lane >> 4;
     const long long ntasks = (a.ncells + 15) / 16;
+    double s0 = 0.0, s4 = 0.0;  // this wave's sums of the mean-row corrections, in task order
     for (long long wave = (long long)blockIdx.x * (CL_THREADS / 64) + (threadIdx.x >> 6); wave < ntasks;
          wave += (long long)gridDim.x * (CL_THREADS / 64)) {
         const long long cell0 = wave * 16;
@@ -203,31 +204,41 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
             m0 += __shfl_xor(m0, off, 16);
             m4 += __shfl_xor(m4, off, 16);
         }
-        if (col == 0) {
-            a.partials[wave * NF + g] = m0;
-            if (g == 0) a.partials[wave * NF + 4] = m4;
-        }
+        s0 += m0;
+        s4 += m4;
         const unsigned long long fb = __ballot(bad && live && g == 0);
         if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
     }
-}
-
-// mean of the mean-row corrections per field, summed in a fixed order
-__global__ __launch_bounds__(256) void closure_mean_kernel(const double *partials, long long nwaves, long long ncells,
-                                                           double *cmean) {
-    __shared__ double red[256];
+    // one partial per wave of the grid; the last workgroup to finish forms the means from them in a
+    // fixed order (and resets the counter for the next launch), so no second kernel is launched
+    const long long gw = (long long)blockIdx.x * (CL_THREADS / 64) + (threadIdx.x >> 6);
+    if (col == 0) {
+        a.partials[gw * NF + g] = s0;
+        if (g == 0) a.partials[gw * NF + 4] = s4;
+    }
+    __threadfence();
+    __syncthreads();
+    __shared__ int last;
+    if (threadIdx.x == 0) last = atomicAdd(a.done, 1ull) == (unsigned long long)gridDim.x - 1 ? 1 : 0;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double *red = reinterpret_cast<double *>(wl);  // the weights are no longer read
+    const long long nparts = (long long)gridDim.x * (CL_THREADS / 64);
     for (int i = 0; i < NF; i++) {
-        double s = 0.0;
-        for (long long w = threadIdx.x; w < nwaves; w += 256) s += partials[w * NF + i];
-        red[threadIdx.x] = s;
+        double sum = 0.0;
+        for (long long w = threadIdx.x; w < nparts; w += CL_THREADS)
+            sum += __hip_atomic_load(a.partials + w * NF + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red[threadIdx.x] = sum;
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
+        for (int h = CL_THREADS / 2; h > 0; h >>= 1) {
             if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) cmean[i] = red[0] / (double)ncells;
+        if (threadIdx.x == 0) a.cmean[i] = red[0] / (double)a.ncells;
         __syncthreads();
     }
+    if (threadIdx.x == 0) __hip_atomic_store(a.done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 hipError_t launch_closure(int prec, const ClosureArgs &a, hipStream_t s) {
@@ -246,7 +257,6 @@ hipError_t launch_closure(int prec, const ClosureArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((closure_kernel<double>), dim3(nb), dim3(CL_THREADS), CL_LDS, s, a);
     else
         hipLaunchKernelGGL((closure_kernel<float>), dim3(nb), dim3(CL_THREADS), CL_LDS, s, a);
-    hipLaunchKernelGGL(closure_mean_kernel, dim3(1), dim3(256), 0, s, a.partials, nwaves, a.ncells, a.cmean);
     return hipGetLastError();
 }
 

@@ -793,6 +793,7 @@ dg_status run_stage(dg_ctx *c, const void *y0, const void *yin, void *out, doubl
         ca.obound = ca.oscale + CL_NOUT;
         ca.partials = c->clo_partials + NF;
         ca.fallbacks = c->clo_fallbacks;
+        ca.done = c->clo_fallbacks + 1;
         ca.cmean = c->clo_partials;
         ca.nx = c->cfg.n[0];
         ca.ny = c->cfg.n[1];
@@ -1177,12 +1178,13 @@ dg_status dg_set_closure(dg_ctx *c, const float *params, const float *feat_mean,
         const long long nwaves = (c->ncells + 15) / 16;
         if (hipMalloc(&c->clo, blob.size() * sizeof(float)) != hipSuccess ||
             hipMalloc(&c->corr, dg_state_count(c) * elem_bytes(c)) != hipSuccess ||
-            hipMalloc(&c->clo_partials, (size_t)(nwaves + 1) * NF * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->clo_fallbacks, sizeof(unsigned long long)) != hipSuccess) {
+            hipMalloc(&c->clo_partials, (size_t)(nwaves + 9) * NF * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->clo_fallbacks, 2 * sizeof(unsigned long long)) != hipSuccess) {
             c->err = "dg_set_closure: device allocation failed";
             return DG_ERR_HIP;
         }
         HIPCHK(c, launch_zero_u64(c->clo_fallbacks, c->stream));
+        HIPCHK(c, launch_zero_u64(c->clo_fallbacks + 1, c->stream));  // the inference's finished-workgroup count
     }
     // the copy is ordered after the work already enqueued on the stream
     HIPCHK(c, hipMemcpyAsync(c->clo, blob.data(), blob.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));

@@ -249,8 +249,9 @@ struct ClosureArgs {
     const float *fistd;    // [CL_NIN] 1 / std
     const float *oscale;   // [CL_NOUT]
     const float *obound;   // [CL_NOUT]
-    double *partials;      // [waves][5]
+    double *partials;      // [waves of the grid][5]
     unsigned long long *fallbacks;
+    unsigned long long *done;  // workgroups finished (zero between launches)
     double *cmean;         // [5]
     int nx, ny, nz;
     long long ncells;
