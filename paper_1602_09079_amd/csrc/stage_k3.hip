@@ -246,6 +246,15 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     };
     // one K = 32 chunk; FP32: steps j0 .. j1 - 1 of its eight 16x16x4 products (the others have a
     // zero operand), the A values of steps 4h .. 4h + 3 one 16-byte read at half h of the fragment
+    // LDS destination of a copy by the load unit (M0): a wave-uniform base made opaque at each use,
+    // so that the compiler adds the copy's immediate offset there instead of keeping one scalar
+    // register per copy across the sweep (they spill into vector lanes and come back by readlane)
+    typedef __attribute__((address_space(3))) C lds_c;
+    auto lds_dst = [](C *p) -> lds_c * {
+        lds_c *q = (lds_c *)p;
+        asm volatile("" : "+s"(q));
+        return q;
+    };
     auto mma = [&](Acc c, int frag, const OP &b, int j0 = 0, int j1 = 8) -> Acc {
         if constexpr (PREC == DG_FP32) {
 #pragma unroll
@@ -356,12 +365,12 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     C *ex_e = reinterpret_cast<C *>(lds + a.ex_off3);
     auto load_lds = [&](long long r, int e) {
         const auto rs = slab_rsrc(yin, slabn, r);
-        C *dst = ex_e + e * ERV * 64;
+        lds_c *dst = lds_dst(ex_e + e * ERV * 64);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
             const int so = (int)((unsigned)i * fbytes);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rs, (__attribute__((address_space(3))) void *)(dst + (i * (1 + NSL)) * 64), 4, xoff, so, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(dst + (i * (1 + NSL)) * 64),
+                                                     4, xoff, so, 0, 0);
 #pragma unroll
             for (int s = 0; s < NSL; s++)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -438,6 +447,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         asm volatile("" : "+v"(ln));
         const unsigned cx = (ln & 15) < 8 ? xgl : xgr;
         const int gg = ln >> 4, c8 = ln & 7;
+        lds_c *gdst = lds_dst(ex_g);
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             const int e = e0 < NF * (1 + NSL) ? e0 : 0;  // the two spare values copy the first one again
             const int i = e / (1 + NSL), m = e - i * (1 + NSL);
             const unsigned row = m == 0 ? 0u : (unsigned)k3_slot_mode(gg, m - 1);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(ex_g + k * 64), 4,
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(gdst + k * 64), 4,
                                                      row * nxu * 4u + cx + (unsigned)i * fbytes, 0, 0, 0);
         }
         asm volatile("" ::: "memory");
@@ -820,13 +830,14 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             auto y0_copy = [&]() {
                 if (dma_y0 && act) {
                     const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
+                    lds_c *ydst = lds_dst(ex_t + wrow * NF * 4 * 64);
 #pragma unroll
                     for (int u = 0; u < 4; u++)
 #pragma unroll
                         for (int i = 0; i < NF; i++)
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                r0, (__attribute__((address_space(3))) void *)(ex_t + ((wrow * NF + i) * 4 + u) * 64),
-                                4, roff[u] + xoff, (int)((unsigned)i * fbytes), 0, 0);
+                                r0, (__attribute__((address_space(3))) void *)(ydst + (i * 4 + u) * 64), 4,
+                                roff[u] + xoff, (int)((unsigned)i * fbytes), 0, 0);
                 }
             };
             C Fym[NF][4];  // -y face flux of this row: the +y flux of the row below, or row 0's own
@@ -864,11 +875,12 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
                     if (dma_y0 && act) {
                         const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
+                        lds_c *gdst = lds_dst(ex_g);
                         asm volatile("" ::: "memory");
 #pragma unroll
                         for (int i = 0; i < 4; i++)
                             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                r0, (__attribute__((address_space(3))) void *)(ex_g + i * 64), 4, roff[4] + xoff,
+                                r0, (__attribute__((address_space(3))) void *)(gdst + i * 64), 4, roff[4] + xoff,
                                 (int)((unsigned)i * fbytes), 0, 0);
                         asm volatile("" ::: "memory");
                         y044 = bload(0.0f, r0, roff[4] + xoff, 4u * fbytes);

@@ -92,6 +92,28 @@ def test_steps_parity_k4(dgm, prec):
     assert np.all(err <= (1e-13 if prec == "fp64" else 1e-6)), err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_several_x_blocks_k4(dgm, prec):
+    """The stage kernel updates x-blocks of 14 cells (16 columns with the cell before and the
+    cell after): (31, 5, 4) has two full blocks and a ragged one of 3 cells, so x faces on block
+    edges inside the mesh (13/14, 27/28) and at the periodic wrap (30/0) are each formed by two
+    blocks.  R with the driving, then two device-CFL steps (stages 2 and 3 read y0)."""
+    n = (31, 5, 4)
+    cfg, y = turb(n, seed=11, mach=0.5)
+    s = dgm.Solver(K, n, gamma=G, precision=prec, forcing=True)
+    nvec, al, frc = driving(dgm)
+    s.set_forcing(nvec, al)
+    r = host(s.rhs(dev(y, s.dtype)))
+    err = err_max_norm(r, O.rhs(cfg, stored(y, prec), frc))
+    assert np.all(err <= (1e-13 if prec == "fp64" else 2e-5)), err
+    yd = dev(y, s.dtype)
+    t = s.step(yd, 2)
+    want, tw = O.step(cfg, stored(y, prec), 0.0, 2, frc=frc)
+    assert t == pytest.approx(tw, rel=1e-13 if prec == "fp64" else 1e-6)
+    err = O.rel_l2(host(yd), want)
+    assert np.all(err <= (1e-13 if prec == "fp64" else 1e-6)), err
+
+
 def test_mass_conserved_k4(dgm):
     """The face fluxes of the two cells of a face agree, so the total mass changes only by
     rounding (FP64, driven, exact Riemann solver)."""
