@@ -210,11 +210,12 @@ __device__ inline void euler_flux3(const C q[5], C g1, C F[3][5]) {
 
 // HLLC numerical flux across a face normal to AXIS, left state qL, right state
 // qR (Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics, ch. 10:
-// Davis wave-speed bounds; the star flux in the form
-//   F*_K = (S* (S_K U_K - F_K) + S_K p* D*) / (S_K - S*),  D* = (0, n, S*),
-//   p* = p_K + rho_K (S_K - u_K)(S* - u_K),
-// which equals F_K + S_K (U*_K - U_K) of the star-state form).  S* >= 0 takes the
-// left star state.  Branch-free: side K is selected first, only its flux is formed.
+// Davis wave-speed bounds; the star flux F*_K = F_K + S_K (U*_K - U_K) of the star-state
+// form, written as
+//   F*_K = F_K + S_K / (S_K - S*) (S* U_K - F_K + p* D*),  D* = (0, n, S*),
+//   p* = p_K + rho_K (S_K - u_K)(S* - u_K)).  S* >= 0 takes the left star state.
+// Branch-free: side K is selected first, only its flux is formed; where the face lies
+// outside the star region the coefficient of the correction is zero.
 template <class PR, int AXIS, class C>
 __device__ inline void hllc(const C qL[5], const C qR[5], C gam, C F[5]) {
     const C g1 = gam - C(1);
@@ -241,14 +242,14 @@ __device__ inline void hllc(const C qL[5], const C qR[5], C gam, C F[5]) {
     FK[4] = (q[4] + pK) * uK;
     const bool plain = (SL >= C(0)) || (!left && SR <= C(0));
     const C pst = pK + dK * (Ss - uK);
-    const C inv = PR::rcp(SK - Ss);
-    C Fs[5];
+    const C cf = plain ? C(0) : SK * PR::rcp(SK - Ss);
+    C t[5];
 #pragma unroll
-    for (int i = 0; i < 5; i++) Fs[i] = Ss * (SK * q[i] - FK[i]);
-    Fs[1 + AXIS] += SK * pst;
-    Fs[4] += SK * pst * Ss;
+    for (int i = 0; i < 5; i++) t[i] = Ss * q[i] - FK[i];
+    t[1 + AXIS] += pst;
+    t[4] += pst * Ss;
 #pragma unroll
-    for (int i = 0; i < 5; i++) F[i] = plain ? FK[i] : Fs[i] * inv;
+    for (int i = 0; i < 5; i++) F[i] = FK[i] + cf * t[i];
 }
 
 // x^y for x > 0 in the precision of C (FP32: hardware base-2 logarithm and exponential)

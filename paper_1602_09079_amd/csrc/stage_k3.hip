@@ -432,10 +432,11 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         trace(f, b, tr);
     };
     // The ghost cells of the x faces (the cell before the block and the cell after it), copied into
-    // LDS by the load unit one z step ahead, four 64-lane copies per wave: lane (g, c) copies value
-    // 4 (c % 8) + k in copy k of the cell before (c < 8) or after (c >= 8) for lane group g; value
-    // e = 6 i + m of a cell is field i's mean (m = 0) or its slot m - 1.  x0: the block's first
-    // cell (wave-uniform).
+    // LDS by the load unit one z step ahead, four 64-lane copies per wave: lane (g, c) copies for
+    // lane group g a value of the cell before (c < 8) or after (c >= 8); with c8 = c % 8, copy k
+    // holds value c8 of field k for c8 < 6 and value 4 (c8 - 6) + k of field 4 for c8 = 6, 7, value
+    // 0 being the field's mean and value s + 1 its slot s (values 6 and 7 repeat the mean).
+    // x0: the block's first cell (wave-uniform).
     C *ex_g = reinterpret_cast<C *>(lds + a.ex_off4) + wave * 4 * 64;
     auto ghost_dma = [&](long long r, int x0) {
         const auto rs = slab_rsrc(yin, slabn, r);
@@ -446,17 +447,19 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         int ln = lane;
         asm volatile("" : "+v"(ln));
         const unsigned cx = (ln & 15) < 8 ? xgl : xgr;
-        const int gg = ln >> 4, c8 = ln & 7;
+        const int c8 = ln & 7;
+        const bool f4 = c8 >= 6;
         lds_c *gdst = lds_dst(ex_g);
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const int e0 = 4 * c8 + k;
-            const int e = e0 < NF * (1 + NSL) ? e0 : 0;  // the two spare values copy the first one again
-            const int i = e / (1 + NSL), m = e - i * (1 + NSL);
-            const unsigned row = m == 0 ? 0u : (unsigned)k3_slot_mode(gg, m - 1);
+            const int m = f4 ? 4 * (c8 - 6) + k : c8;
+            unsigned row = 0;  // the value's mode row: this lane group's slot rows
+#pragma unroll
+            for (int s2 = 0; s2 < NSL; s2++) row = m == s2 + 1 ? roff[s2] : row;
+            const unsigned fo = f4 ? 4u * fbytes : (unsigned)k * fbytes;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(gdst + k * 64), 4,
-                                                     row * nxu * 4u + cx + (unsigned)i * fbytes, 0, 0, 0);
+                                                     row + cx + fo, 0, 0, 0);
         }
         asm volatile("" ::: "memory");
     };
@@ -466,13 +469,14 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         int o = 16 * g + (after ? 8 : 0);
         asm volatile("" : "+v"(o));
         const C *src = ex_g + o;
+        // value m of field i: copy i, lane m (fields 0..3); copy m % 4, lane 6 + m / 4 (field 4)
+        auto at = [&](int i, int m) { return i < 4 ? src[i * 64 + m] : src[(m % 4) * 64 + 6 + m / 4]; };
 #pragma unroll
         for (int i = 0; i < NF; i++) {
-            gb.qbar[i] = src[((6 * i) % 4) * 64 + (6 * i) / 4];
+            gb.qbar[i] = at(i, 0);
 #pragma unroll
             for (int s2 = 0; s2 < NSL; s2++) {
-                const int e = 6 * i + 1 + s2;
-                const C vv = src[(e % 4) * 64 + e / 4];
+                const C vv = at(i, 1 + s2);
                 gb.v[i][s2] = (after && ((oddu >> s2) & 1u)) ? -vv : vv;
             }
         }
