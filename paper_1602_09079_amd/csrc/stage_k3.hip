@@ -791,23 +791,24 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             const float *drow = FORCE ? a.dtab + cidx(iy, z) * k3_drive_row_floats(K3_DKS) : nullptr;
             volume(cur, acc, drow);
             // y faces shared by the rows of the workgroup: each face flux is solved once, by the
-            // row below it; the faces at the group's ends use the neighbour rows' weights.  Row 0
-            // solves its -y face itself and parks the flux in its own trace slot (which no other
-            // row reads), so that nothing is held in registers across the two barriers
+            // row below it; the faces at the group's ends use the neighbour rows' weights.  Row 0's
+            // -y face is solved by four waves of SIMDs 1 and 2, one result register each (row 0
+            // and the top row trace the end rows, on SIMDs 0 and 3), from row 0's -y trace in its
+            // trace slot and the end row's +y trace in flux slot YROWS - 1 (no row's flux goes
+            // there); the flux goes back into row 0's trace slot, which no other row reads, so
+            // that nothing is held in registers across the two barriers
             C Fyp[NF][4];  // +y face flux of this row
             C tp[NF][4];   // +y trace, formed with the -y one from the same operands
             {
                 C tm[NF][4];
                 trace2(2, 3, cur, tm, tp);
                 if (wrow == 0) {
-                    C tb[NF][4], f0[NF][4];
+                    C tb[NF][4];
                     trace_lds(3, 0, tb);
                     if (z + 1 < z1) load_lds(cidx(iy0 - 1, z + 1), 0);  // reads consumed above
-                    riemann(std::integral_constant<int, 1>{}, tb, tm, f0);
-                    ex_put(ex_t, 0, f0);
-                } else {
-                    ex_put(ex_t, wrow, tm);
+                    ex_put(ex_f, YROWS - 1, tb);
                 }
+                ex_put(ex_t, wrow, tm);
             }
             lds_barrier();
             // Issue priority: the two waves of a SIMD are rows w and w + 4.  By default the older
@@ -824,7 +825,24 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                     ex_get(ex_t, wrow + 1 < YROWS ? wrow + 1 : wrow, ta);
                 }
                 riemann(std::integral_constant<int, 1>{}, tp, ta, Fyp);
-                ex_put(ex_f, wrow, Fyp);
+                if (wrow < YROWS - 1) ex_put(ex_f, wrow, Fyp);  // the top row's flux has no reader here
+                if (wave == 1 || wave == 2 || wave == 5 || wave == 6) {  // row 0's -y face, register r
+                    const int r = wave == 1 ? 0 : (wave == 5 ? 1 : (wave == 2 ? 2 : 3));
+                    C *pt = ex_t + r * 64 + lane_base();
+                    const C *pb = ex_f + ((YROWS - 1) * NF * 4 + r) * 64 + lane_base();
+                    C qL[5], qR[5], F[5];
+#pragma unroll
+                    for (int i = 0; i < NF; i++) {
+                        qL[i] = pb[i * 4 * 64];
+                        qR[i] = pt[i * 4 * 64];
+                    }
+                    if constexpr (RS == 1)
+                        exact_rs<PR, 1>(qL, qR, gam, F);
+                    else
+                        hllc<PR, 1>(qL, qR, gam, F);
+#pragma unroll
+                    for (int i = 0; i < NF; i++) pt[i * 4 * 64] = F[i];
+                }
             }
             lds_barrier();
             // the stage-combine input y0 (stages 2 and 3): slots 0..3 copied by the load unit into
