@@ -11,7 +11,8 @@ R itself is a difference of volume and surface terms that nearly cancel (the
 density row is the divergence of a nearly solenoidal momentum), so its error
 is measured against the largest field norm of R:
   ||R_gpu,i - R_orc,i|| / max_j ||R_orc,j||  <=  FP64 1e-12, FP32 2e-5,
-  BF16X3 2e-3, BF16 0.5 (guard only).
+  BF16X3 1e-4 (measured up to 5.4e-5: the split products carry about 17 bits),
+  BF16 0.5 (guard only).
 """
 import math
 
@@ -29,7 +30,7 @@ torch = pytest.importorskip("torch")
 G = 5.0 / 3.0
 PRECS = ["fp64", "fp32", "bf16x3", "bf16"]
 TOL_STATE = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 5e-3}
-TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-3, "bf16": 0.5}
+TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 1e-4, "bf16": 0.5}
 
 
 @pytest.fixture(scope="module")
@@ -197,6 +198,27 @@ def test_edge_grids(dgm, n):
     r = s.rhs(y)
     err = rhs_err(state_host(r), O.rhs(cfg, y_or))
     assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("n", [(2, 3, 2), (16, 2, 3), (33, 2, 2)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_k3_x_block_edges(dgm, prec, n):
+    """k = 3 in the tiers of the 16-cell x-block kernel: a block of two valid cells (its right
+    neighbour in the block's own wrapped column), exactly one full block (both ghost cells are its
+    own columns 15 and 0), and two full blocks plus a ragged one of one cell; R against the
+    oracle."""
+    k, box = 3, (1.0, 1.0, 1.0)
+    cfg = O.make_cfg(k, n, box=box, gamma=G)
+    rng = np.random.default_rng(sum(n))
+    qp = synth.uniform_state(n, O.gauss_legendre(k + 1)[0], rho=1.0, vel=(0.1, 0.2, -0.1), p=1.0)
+    qp = qp * (1.0 + 0.05 * rng.standard_normal(qp.shape))  # tiny meshes hold no turbulence band
+    y_or = O.project(cfg, qp)
+    s = dgm.Solver(k, n, box=box, gamma=G, precision=prec)
+    r = s.rhs(state_dev(y_or, s.dtype))
+    r_or = O.rhs(cfg, y_or.astype(np.float32).astype(np.float64))
+    err = rhs_err(state_host(r), r_or)
+    print(f"rhs k=3 {n} {prec}: L2 error per field / max field norm {err}")
+    assert np.all(np.isfinite(err)) and np.all(err <= TOL_RHS[prec]), err
 
 
 @pytest.mark.parametrize("ny", [19, 17])
