@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 G = 5.0 / 3.0
 TOL_STATE = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 5e-3}
-TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 1e-4, "bf16": 0.5}
+TOL_RHS = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 3e-4, "bf16": 0.5}
 
 
 @pytest.fixture(scope="module")
