@@ -265,37 +265,42 @@ __device__ inline double powpos(double x, double y) { return pow(x, y); }
 // (gamma-1) <= u_R - u_L) are sampled from the two rarefactions and the vacuum between them.
 template <class PR, int AXIS, class C>
 __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
-    const C g1 = gam - C(1), gp = gam + C(1), z = g1 / (C(2) * gam);
-    const C iL = C(1) / qL[0], iR = C(1) / qR[0];
+    // quotients as products with reciprocals (PR::rcp: the hardware reciprocal in the FP32 tiers,
+    // 1/x in FP64); the ones of gamma alone are wave-uniform
+    const C g1 = gam - C(1), gp = gam + C(1), z = g1 * PR::rcp(C(2) * gam);
+    const C g1i = PR::rcp(g1), gpi = PR::rcp(gp);
+    const C iL = PR::rcp(qL[0]), iR = PR::rcp(qR[0]);
     const C rL = qL[0], rR = qR[0];
     const C uL = qL[1 + AXIS] * iL, uR = qR[1 + AXIS] * iR;
     const C pL = g1 * (qL[4] - C(0.5) * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
     const C pR = g1 * (qR[4] - C(0.5) * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
     const C cL = PR::sqrt_(gam * pL * iL), cR = PR::sqrt_(gam * pR * iR);
-    // f_K and its derivative
-    auto wave = [&](C p, C rK, C pK, C cK, C &df) -> C {
+    const C ipL = PR::rcp(pL), ipR = PR::rcp(pR);
+    // f_K and its derivative (shock: A_K = 2 / ((gamma + 1) rho_K), B_K = (gamma - 1) / (gamma + 1) p_K)
+    auto wave = [&](C p, C iK, C pK, C ipK, C cK, C &df) -> C {
         if (p > pK) {
-            const C A = C(2) / (gp * rK), Bk = g1 / gp * pK;
-            const C sq = PR::sqrt_(A / (p + Bk));
-            df = sq * (C(1) - C(0.5) * (p - pK) / (p + Bk));
+            const C A = C(2) * gpi * iK, Bk = g1 * gpi * pK;
+            const C ipb = PR::rcp(p + Bk);
+            const C sq = PR::sqrt_(A * ipb);
+            df = sq * (C(1) - C(0.5) * (p - pK) * ipb);
             return (p - pK) * sq;
         }
-        const C pr = p / pK;
+        const C pr = p * ipK;
         const C t = powpos(pr, z);
-        df = t / (pr * rK * cK);
-        return C(2) * cK / g1 * (t - C(1));
+        df = t * PR::rcp(pr * cK) * iK;
+        return C(2) * cK * g1i * (t - C(1));
     };
     C W0, W1, W2;  // face state: rho, normal velocity, pressure
     bool from_left;
     const C du = uR - uL;
     auto fan = [&](C rK, C uK, C pK, C cK, C sgn) {  // sgn = -1 left fan, +1 right fan
-        const C c = C(2) / gp - sgn * g1 / (gp * cK) * uK;
-        W0 = rK * powpos(c, C(2) / g1);
-        W1 = C(2) / gp * (-sgn * cK + C(0.5) * g1 * uK);
-        W2 = pK * powpos(c, C(2) * gam / g1);
+        const C c = C(2) * gpi - sgn * g1 * gpi * PR::rcp(cK) * uK;
+        W0 = rK * powpos(c, C(2) * g1i);
+        W1 = C(2) * gpi * (-sgn * cK + C(0.5) * g1 * uK);
+        W2 = pK * powpos(c, C(2) * gam * g1i);
     };
-    if (C(2) * (cL + cR) / g1 <= du) {
-        const C sL = uL + C(2) * cL / g1, sR = uR - C(2) * cR / g1;
+    if (C(2) * (cL + cR) * g1i <= du) {
+        const C sL = uL + C(2) * cL * g1i, sR = uR - C(2) * cR * g1i;
         if (C(0) <= sL) {
             from_left = true;
             if (C(0) <= uL - cL) { W0 = rL; W1 = uL; W2 = pL; }
@@ -319,7 +324,7 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
         C fl = 0, fr = 0, sl = 0, sr = 0, pold = p;  // the last evaluation: f_L, f_R, their slopes, at pold
         for (int it = 0; it < 24; it++) {
             C dfL, dfR;
-            const C a = wave(p, rL, pL, cL, dfL), b = wave(p, rR, pR, cR, dfR);
+            const C a = wave(p, iL, pL, ipL, cL, dfL), b = wave(p, iR, pR, ipR, cR, dfR);
             C pn = p - (a + b + du) * PR::rcp(dfL + dfR);
             pn = pn > tiny ? pn : C(0.1) * p;
             const C ch = __builtin_fabs(pn - p) * PR::rcp(pn + p);
@@ -334,19 +339,21 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
         from_left = C(0) <= us;
         const C rK = from_left ? rL : rR, uK = from_left ? uL : uR, pK = from_left ? pL : pR;
         const C cK = from_left ? cL : cR, sg = from_left ? C(-1) : C(1);
+        const C ppK = p * (from_left ? ipL : ipR);  // p* / p_K
         // in the frame mirrored for the right side, every test reads as for the left side
         if (p > pK) {
-            const C S = uK + sg * cK * PR::sqrt_(gp / (C(2) * gam) * p / pK + g1 / (C(2) * gam));
+            const C h2g = C(0.5) * PR::rcp(gam);
+            const C S = uK + sg * cK * PR::sqrt_(gp * h2g * ppK + g1 * h2g);
             if (sg * S <= C(0)) { W0 = rK; W1 = uK; W2 = pK; }
             else {
-                W0 = rK * (p / pK + g1 / gp) / (g1 / gp * p / pK + C(1));
+                W0 = rK * (ppK + g1 * gpi) * PR::rcp(g1 * gpi * ppK + C(1));
                 W1 = us; W2 = p;
             }
         } else {
             const C head = uK + sg * cK;
-            const C tail = us + sg * cK * powpos(p / pK, z);
+            const C tail = us + sg * cK * powpos(ppK, z);
             if (sg * head <= C(0)) { W0 = rK; W1 = uK; W2 = pK; }
-            else if (sg * tail >= C(0)) { W0 = rK * powpos(p / pK, C(1) / gam); W1 = us; W2 = p; }
+            else if (sg * tail >= C(0)) { W0 = rK * powpos(ppK, PR::rcp(gam)); W1 = us; W2 = p; }
             else fan(rK, uK, pK, cK, sg);
         }
     }
@@ -356,7 +363,7 @@ __device__ inline void exact_rs(const C qL[5], const C qR[5], C gam, C F[5]) {
 #pragma unroll
     for (int a = 0; a < 3; a++) v[a] = qt[1 + a] * it;
     v[AXIS] = W1;
-    const C E = W2 / g1 + C(0.5) * W0 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const C E = W2 * g1i + C(0.5) * W0 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const C mflux = W0 * W1;
     F[0] = mflux;
 #pragma unroll
