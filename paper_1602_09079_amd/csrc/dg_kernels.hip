@@ -1395,6 +1395,9 @@ hipError_t launch_limit(int k, int prec, void *y, const double *tab, int np, lon
 // FP64 through pow
 __device__ inline float pow_d(float x, float p) { return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x)); }
 __device__ inline double pow_d(double x, double p) { return pow(x, p); }
+// 1/x in the precision of C (FP32: the hardware reciprocal, not an IEEE division)
+__device__ inline float rcp_d(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_d(double x) { return 1.0 / x; }
 
 constexpr int RESET_THREADS = 256;
 
@@ -1482,7 +1485,7 @@ __global__ __launch_bounds__(RESET_THREADS) void reset_kernel(S *__restrict__ y,
             for (int b = 0; b < n; b++)
 #pragma unroll
                 for (int a = 0; a < n; a++)
-                    e[b][a] = C(0.5) * m2[b][a] / rho[b][a] + cc * rho[b][a] * pow_d(rho[b][a] * ir0, g);
+                    e[b][a] = C(0.5) * m2[b][a] * rcp_d(rho[b][a]) + cc * rho[b][a] * pow_d(rho[b][a] * ir0, g);
             C s1[K + 1][n];
 #pragma unroll
             for (int u = 0; u <= K; u++)
