@@ -77,16 +77,16 @@ constexpr int K3_DKS = 2;            // K steps (of 4) of the driving product: w
 __host__ __device__ inline long long k3_drive_row_floats(int dks) { return 3LL * 4 * dks * 64; }
 
 // k = 4 stage kernel (stage_k4.hip): A-operand fragments of its 16x16x4 / 4x4x1 products
-// (64 values each, in the storage precision), in this order: PHI[t][s] (values at the 16 points of volume tile t, K step s
-// over the modes), GRAD[t][d][rt][s] (minus the weighted d-derivatives, result row tile rt, K step
-// s over the tile's points), SRC[t][rt][s] (minus the weighted basis / 8), TRACE[f][ft][s] (values
-// at the 16 points of face tile ft of face f), then LIFT[f][rt][s] (K step s over the face's 32
-// rows).
+// (64 values each, in the storage precision), in this order: PHI[t][s] (values at the 16 points
+// of volume tile t, K step s over the modes), GRAD[t][d][rt][s] (minus the weighted
+// d-derivatives, result row tile rt, K step s over the tile's points), TRACE[f][ft][s] (values at
+// the 16 points of face tile ft of face f), LIFT[f][rt][s] (K step s over the face's 32 rows),
+// then SRC[t][rt][s] (minus the weighted basis / 8, read only with the driving).
 constexpr int K4_BLK = 14;  // cells updated per x-block (16 columns with the two halo cells)
-constexpr int K4_PHI = 0, K4_GRAD = K4_PHI + 8 * 9, K4_SRC = K4_GRAD + 8 * 3 * 3 * 4, K4_TRACE = K4_SRC + 8 * 3 * 4,
-              K4_LIFT = K4_TRACE + 6 * 2 * 9, K4_NFRAG = K4_LIFT + 6 * 3 * 8;
-// LDS of the kernel: FP32 the fragments before LIFT, FP64 (8-byte values) the GRAD fragments
-constexpr int k4_lds_bytes(int prec) { return prec == DG_FP64 ? (K4_SRC - K4_GRAD) * 64 * 8 : K4_LIFT * 64 * 4; }
+constexpr int K4_PHI = 0, K4_GRAD = K4_PHI + 8 * 9, K4_TRACE = K4_GRAD + 8 * 3 * 3 * 4, K4_LIFT = K4_TRACE + 6 * 2 * 9,
+              K4_SRC = K4_LIFT + 6 * 3 * 8, K4_NFRAG = K4_SRC + 8 * 3 * 4;
+// LDS of the kernel: FP32 the fragments before SRC, FP64 (8-byte values) the GRAD fragments
+constexpr int k4_lds_bytes(int prec) { return prec == DG_FP64 ? (K4_TRACE - K4_GRAD) * 64 * 8 : K4_SRC * 64 * 4; }
 
 // Stage kernel launch shape.  FP32-storage tiers: workgroups of 8 waves that own
 // 8 consecutive y rows of one x-block and sweep z together, sharing y-face traces

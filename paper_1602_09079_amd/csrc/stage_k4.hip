@@ -22,10 +22,11 @@
 //   face solved by both of its cells with the same arithmetic, so that they get the same flux.
 // - Padding rows repeat the last point in the trace and value tables (a valid state) and are zero
 //   in the tables that take their results, so they add nothing.
-// - FP32: the tables of the volume products and the traces (141 KiB) sit in LDS, shared by the
-//   eight waves (two per SIMD) of the one workgroup per compute unit, the lift tables (36 KiB) are
-//   read through the caches.  FP64: the gradient tables (144 KiB) sit in LDS, the rest is read
-//   through the caches, and one wave per SIMD holds the weights and results in 512 registers.
+// - FP32: the value, gradient, trace and lift tables (153 KiB) sit in LDS, shared by the eight
+//   waves (two per SIMD) of the one workgroup per compute unit, the source tables (24 KiB, read
+//   only with the driving) through the caches.  FP64: the gradient tables (144 KiB) sit in LDS,
+//   the rest is read through the caches, and one wave per SIMD holds the weights and results in
+//   512 registers.
 //   The waves take x-blocks independently (no barrier after the table copy).
 
 #include "dg_device.h"
@@ -74,8 +75,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == DG_FP64 ? 1 : 2, PREC == DG_FP64 ? 1 
     using C = typename PR::C;
     using Acc = typename PR::Acc;
     constexpr int ESZ = sizeof(C);
-    // the fragments staged in LDS: FP32 all before the lift tables, FP64 the gradient tables
-    constexpr int L0 = F64 ? K4_GRAD : 0, L1 = F64 ? K4_SRC : K4_LIFT;
+    // the fragments staged in LDS: FP32 all before the source tables, FP64 the gradient tables
+    constexpr int L0 = F64 ? K4_GRAD : 0, L1 = F64 ? K4_TRACE : K4_SRC;
     extern __shared__ __attribute__((aligned(16))) char lds[];
     {
         const int4 *src = reinterpret_cast<const int4 *>(static_cast<const char *>(a.tables) + (size_t)L0 * 64 * ESZ);
