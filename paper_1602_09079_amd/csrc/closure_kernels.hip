@@ -89,16 +89,16 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
     const int g = lane >> 4;
     const long long ntasks = (a.ncells + 15) / 16;
     double s0 = 0.0, s4 = 0.0;  // this wave's sums of the mean-row corrections, in task order
-    for (long long wave = (long long)blockIdx.x * (CL_THREADS / 64) + (threadIdx.x >> 6); wave < ntasks;
-         wave += (long long)gridDim.x * (CL_THREADS / 64)) {
-        const long long cell0 = wave * 16;
-        const bool live = cell0 + col < a.ncells;
-        const long long cell = live ? cell0 + col : a.ncells - 1;
-        const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const long long slabn = (long long)CL_ROWS * nx;  // 5 fields x 4 modes rows per slab
+    const S *y = reinterpret_cast<const S *>(a.y);
+    // offsets of the 7 cells whose weights are this lane's features in task w (column col)
+    auto task_bases = [&](long long w, long long base[7]) {
+        const long long c0 = w * 16;
+        const long long cell = c0 + col < a.ncells ? c0 + col : a.ncells - 1;
         const int x = (int)(cell % nx);
         const long long rr = cell / nx;
         const int yy = (int)(rr % ny), zz = (int)(rr / ny);
-        const long long slabn = (long long)CL_ROWS * nx;  // 5 fields x 4 modes rows per slab
         auto at = [&](int dx, int dy, int dz) -> long long {
             int xi = x + dx, yi = yy + dy, zi = zz + dz;
             xi = xi < 0 ? xi + nx : (xi >= nx ? xi - nx : xi);
@@ -106,7 +106,6 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
             zi = zi < 0 ? zi + nz : (zi >= nz ? zi - nz : zi);
             return ((long long)zi * ny + yi) * slabn + xi;
         };
-        long long base[7];
         base[0] = at(0, 0, 0);
         base[1] = at(-1, 0, 0);
         base[2] = at(1, 0, 0);
@@ -114,7 +113,24 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
         base[4] = at(0, 1, 0);
         base[5] = at(0, 0, -1);
         base[6] = at(0, 0, 1);
-        const S *y = reinterpret_cast<const S *>(a.y);
+    };
+    // the raw features of task w (value s: field s % 5, mode g, of cell s / 5 of the 7), requested
+    // one task ahead, after the layer that used the previous ones
+    float fv[35];
+    auto load_feat = [&](long long w) {
+        long long bs[7];
+        task_bases(w, bs);
+    #pragma unroll
+        for (int s = 0; s < 35; s++) fv[s] = (float)y[bs[s / 5] + (long long)((s % 5) * 4 + g) * nx];
+    };
+    const long long wstride = (long long)gridDim.x * (CL_THREADS / 64);
+    long long wave0 = (long long)blockIdx.x * (CL_THREADS / 64) + (threadIdx.x >> 6);
+    if (wave0 < ntasks) load_feat(wave0);
+    for (long long wave = wave0; wave < ntasks; wave += wstride) {
+        const long long cell0 = wave * 16;
+        const bool live = cell0 + col < a.ncells;
+        long long base[7];
+        task_bases(wave, base);
         const float *b1 = a.params + CL_NH * CL_NIN;
         const float *b2 = b1 + CL_NH + CL_NH * CL_NH;
         const float *b3 = b2 + CL_NH + CL_NOUT * CL_NH;
@@ -130,10 +146,8 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
         for (int t = 0; t < 8; t++) h1[t] = f4c{0, 0, 0, 0};
     #pragma unroll
         for (int s = 0; s < 35; s++) {
-            const int j = s / 5, i = s % 5;
             const int f = 4 * s + g;
-            const float v = (float)y[base[j] + (long long)(i * 4 + g) * nx];
-            const float b = (v - a.fmean[f]) * a.fistd[f];
+            const float b = (fv[s] - a.fmean[f]) * a.fistd[f];
     #pragma unroll
             for (int t = 0; t < 8; t++) h1[t] = mfma4(w1l[(t * 35 + s) * 64], b, h1[t]);
         }
@@ -142,6 +156,9 @@ __global__ __launch_bounds__(CL_THREADS) void closure_kernel(ClosureArgs a) {
     #pragma unroll
             for (int r = 0; r < 4; r++) h1[t][r] = tanh_act(h1[t][r] + b1[16 * t + 4 * g + r]);
 
+        asm volatile("" ::: "memory");
+        if (wave + wstride < ntasks) load_feat(wave + wstride);
+        asm volatile("" ::: "memory");
         // layer 2: 128 -> 128
         f4c h2[8];
     #pragma unroll
