@@ -82,7 +82,19 @@ __host__ __device__ inline long long k3_drive_row_floats(int dks) { return 3LL *
 // d-derivatives, result row tile rt, K step s over the tile's points), TRACE[f][ft][s] (values at
 // the 16 points of face tile ft of face f), LIFT[f][rt][s] (K step s over the face's 32 rows),
 // then SRC[t][rt][s] (minus the weighted basis / 8, read only with the driving).
-constexpr int K4_BLK = 14;  // cells updated per x-block (16 columns with the two halo cells)
+constexpr int K4_BLK = 16;  // cells per x-block
+// x-degree of mode l in the graded order of the basis (total degree d, then the x-degree
+// descending, then the y-degree descending)
+__host__ __device__ constexpr int graded_mode_u(int l) {
+    int n = 0;
+    for (int d = 0; d < 16; d++)
+        for (int a = d; a >= 0; a--)
+            for (int b = d - a; b >= 0; b--) {
+                if (n == l) return a;
+                n++;
+            }
+    return -1;
+}
 constexpr int K4_PHI = 0, K4_GRAD = K4_PHI + 8 * 9, K4_TRACE = K4_GRAD + 8 * 3 * 3 * 4, K4_LIFT = K4_TRACE + 6 * 2 * 9,
               K4_SRC = K4_LIFT + 6 * 3 * 8, K4_NFRAG = K4_SRC + 8 * 3 * 4;
 // LDS of the kernel: FP32 the fragments before SRC, FP64 (8-byte values) the GRAD fragments

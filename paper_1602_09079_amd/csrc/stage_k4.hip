@@ -1,13 +1,17 @@
 // The SSP stage kernel for k = 4 (N = 35 modes, 5^3 volume points, 5^2 points per face) in FP32
-// and FP64 on the matrix cores.  It evaluates the same quadrature form as quad_stage_kernel in
-// dg_kernels.hip (Bauer et al., arXiv 1602.09079, Sec. 2.3, eqs. dg:eqn:volume_int and
-// dg:eqn:surface_int, the driving source of Sec. 3.1, the Shu-Osher combine of the SSP-RK3
-// step), with the cells of an x-block as the columns of 16x16x4 FP32 / FP64 MFMAs and the basis
-// tables as their A operands:
+// and FP64 on the matrix cores: the quadrature form of the volume and surface integrals (Bauer et
+// al., arXiv 1602.09079, Sec. 2.3, eqs. dg:eqn:volume_int and dg:eqn:surface_int, the driving
+// source of Sec. 3.1, the Shu-Osher combine of the SSP-RK3 step), with the cells of an x-block as
+// the columns of 16x16x4 FP32 / FP64 MFMAs and the basis tables as their A operands:
 //
-// - One wave per x-block: 16 consecutive cells of a (z, y) row, columns 1..14 updated, columns 0
-//   and 15 the halo of the x faces.  Lane (g, c) holds cell c and, of every field, the modes
-//   4s + g, s = 0..8 (the B operand of the K step s of every product over the modes).
+// - One wave per x-block: 16 consecutive cells of a (z, y) row, all updated.  Lane (g, c) holds
+//   cell c and, of every field, the modes 4s + g, s = 0..8 (the B operand of the K step s of every
+//   product over the modes).  The x faces on the block's edges take the cell before and the cell
+//   after from one extra "ghost" product (column 0: the cell before; column 15: the cell after
+//   with its odd-x-degree modes negated, which turns the +x trace table into the -x one); the
+//   16 points of column 15's +x face are gathered into the lanes of columns 12..15 and solved in
+//   one pass.  A ragged last block takes its right neighbour from the wrapped column after the
+//   last valid one.
 // - Volume, one tile of 16 points at a time: point values (8 tiles of 16 rows over the 125
 //   points, 9 K steps), the Euler fluxes and the driving source at the lane's 4 points, then
 //   their contraction with the weighted gradients and basis (K = the tile's 16 points, 4 steps).
@@ -18,8 +22,9 @@
 // - Faces, one tile of 16 points at a time (2 tiles over the 25 points): the traces of the cell
 //   and of its neighbour on the face, the Riemann flux at the lane's 4 points, the lift (K = the
 //   32 face rows, 8 steps).  x faces: the neighbour is the next column (DPP row shifts), each
-//   face solved once; y and z faces: the neighbouring blocks' traces from their weights, each
-//   face solved by both of its cells with the same arithmetic, so that they get the same flux.
+//   face inside the block solved once; the block-edge faces and the y and z faces (whose
+//   neighbours' traces come from their weights) are solved by both of their cells with the same
+//   arithmetic, so that they get the same flux.
 // - Padding rows repeat the last point in the trace and value tables (a valid state) and are zero
 //   in the tables that take their results, so they add nothing.
 // - FP32: the value, gradient, trace and lift tables (153 KiB) sit in LDS, shared by the eight
@@ -50,13 +55,20 @@ __device__ inline double dpp(double v) {
                   (unsigned)__builtin_amdgcn_update_dpp(0, (int)h.y, CTRL, 0xf, 0xf, true)};
     return __builtin_bit_cast(double, o);
 }
-template <class T>
-__device__ inline T shl1(T v) {
-    return dpp<0x101>(v);
+template <int N, class T>
+__device__ inline T shl(T v) {
+    return dpp<0x100 + N>(v);
 }
-template <class T>
-__device__ inline T shr1(T v) {
-    return dpp<0x111>(v);
+template <int N, class T>
+__device__ inline T shr(T v) {
+    return dpp<0x110 + N>(v);
+}
+// modes with odd x-degree: bit l (k = 4, 35 modes)
+constexpr unsigned long long k4_oddu_mask() {
+    unsigned long long m = 0;
+    for (int l = 0; l < 35; l++)
+        if (graded_mode_u(l) & 1) m |= 1ull << l;
+    return m;
 }
 __device__ inline f4 mfma16(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
 __device__ inline d4 mfma16(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
@@ -201,10 +213,11 @@ __attribute__((amdgpu_waves_per_eu(PREC == DG_FP64 ? 1 : 2, PREC == DG_FP64 ? 1 
         const int bx = (int)(item % nbx);
         const long long row = item / nbx;
         const int iy = (int)(row % ny), iz = (int)(row / ny);
-        int x = bx * K4_BLK - 1 + col;  // column 0: the cell before the block
-        const bool store = col >= 1 && col <= K4_BLK && x < nx;
-        x = x < 0 ? x + nx : x;
-        x = x >= nx ? x % nx : x;
+        const int x0 = bx * K4_BLK;
+        const int vc = nx - x0 < K4_BLK ? nx - x0 : K4_BLK;  // valid columns of the block
+        int x = x0 + col;
+        const bool store = col < vc;
+        x = x >= nx ? x % nx : x;  // a ragged block's column vc holds the wrapped right neighbour
         const unsigned xb = (unsigned)x * ESZ;
 
         C b[NF][9];
@@ -294,22 +307,78 @@ __attribute__((amdgpu_waves_per_eu(PREC == DG_FP64 ? 1 : 2, PREC == DG_FP64 ? 1 
         // registers across the phases before them)
         asm volatile("" ::: "memory");
         // ---- x faces: the - face of column c between columns c - 1 and c; the + face of c is the
-        // - face of c + 1
+        // - face of c + 1.  The cells before and after the block from one "ghost" product: column 0
+        // holds the cell before, column 15 the cell after with its odd-x-degree modes negated, which
+        // turns the +x trace table into the -x one
+        C tg[2][NF][4];
+        {
+            C bg[NF][9];
+            const int xa = x0 == 0 ? nx - 1 : x0 - 1, xr = x0 + K4_BLK;
+            const int xz = col < 8 ? xa : (xr >= nx ? xr % nx : xr);
+            load_b(yin, row, (unsigned)xz * ESZ, bg);
+            constexpr unsigned long long odd = k4_oddu_mask();
+#pragma unroll
+            for (int s = 0; s < 9; s++) {
+                const bool neg = col >= 8 && ((odd >> (4 * s + g)) & 1ull);
+#pragma unroll
+                for (int i = 0; i < NF; i++) bg[i][s] = neg ? -bg[i][s] : bg[i][s];
+            }
+            trace(1, 0, bg, tg[0]);
+            trace(1, 1, bg, tg[1]);
+        }
+        const bool full = vc == K4_BLK;
 #pragma unroll
         for (int ft = 0; ft < 2; ft++) {
-            C tl[NF][4], tr[NF][4], Fm[NF][4];
-            trace(1, ft, b, tl);
+            C tl[NF][4], fo[5];
+            {
+                C tp[NF][4];
+                trace(1, ft, b, tp);
+                if (full) {
+                    // the + face of column 15: its 4 points of this lane group, one per lane of
+                    // columns 12..15, solved in one pass
+                    C ql[5], qr[5];
 #pragma unroll
-            for (int i = 0; i < NF; i++)
+                    for (int i = 0; i < NF; i++) {
+                        const C l1 = shl<1>(tp[i][1]), l2 = shl<2>(tp[i][2]), l3 = shl<3>(tp[i][3]);
+                        const C r1 = shl<1>(tg[ft][i][1]), r2 = shl<2>(tg[ft][i][2]), r3 = shl<3>(tg[ft][i][3]);
+                        const C dflt = i == 0 ? C(1) : (i == 4 ? C(2) : C(0));  // lanes without a point
+                        ql[i] = col == 15 ? tp[i][0] : (col == 14 ? l1 : (col == 13 ? l2 : (col == 12 ? l3 : dflt)));
+                        qr[i] = col == 15 ? tg[ft][i][0] : (col == 14 ? r1 : (col == 13 ? r2 : (col == 12 ? r3 : dflt)));
+                    }
+                    if constexpr (RS == 1)
+                        exact_rs<PR, 0>(ql, qr, gam, fo);
+                    else
+                        hllc<PR, 0>(ql, qr, gam, fo);
+                }
 #pragma unroll
-                for (int r = 0; r < 4; r++) tl[i][r] = shr1(tl[i][r]);
-            trace(0, ft, b, tr);
-            riemann(std::integral_constant<int, 0>{}, tl, tr, Fm);
+                for (int i = 0; i < NF; i++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const C sh = shr<1>(tp[i][r]);  // DPP outside any select: every lane active
+                        tl[i][r] = col == 0 ? tg[ft][i][r] : sh;
+                    }
+            }
+            C Fm[NF][4];
+            {
+                C tr[NF][4];
+                trace(0, ft, b, tr);
+                riemann(std::integral_constant<int, 0>{}, tl, tr, Fm);
+            }
             lift(0, ft, Fm, acc);
 #pragma unroll
-            for (int i = 0; i < NF; i++)
+            for (int i = 0; i < NF; i++) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) Fm[i][r] = shl1(Fm[i][r]);
+                for (int r = 0; r < 4; r++) Fm[i][r] = shl<1>(Fm[i][r]);  // the + face: column c + 1's - face
+                if (full) {
+                    const C f1 = shr<1>(fo[i]), f2 = shr<2>(fo[i]), f3 = shr<3>(fo[i]);
+                    if (col == 15) {
+                        Fm[i][0] = fo[i];
+                        Fm[i][1] = f1;
+                        Fm[i][2] = f2;
+                        Fm[i][3] = f3;
+                    }
+                }
+            }
             lift(1, ft, Fm, acc);
         }
         // ---- y and z faces: side 0 the - face (the neighbour on the left), side 1 the + face
