@@ -92,13 +92,14 @@ def test_steps_parity_k4(dgm, prec):
     assert np.all(err <= (1e-13 if prec == "fp64" else 1e-6)), err
 
 
+@pytest.mark.parametrize("n", [(31, 5, 4), (16, 4, 4)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_several_x_blocks_k4(dgm, prec):
-    """The stage kernel updates x-blocks of 14 cells (16 columns with the cell before and the
-    cell after): (31, 5, 4) has two full blocks and a ragged one of 3 cells, so x faces on block
-    edges inside the mesh (13/14, 27/28) and at the periodic wrap (30/0) are each formed by two
-    blocks.  R with the driving, then two device-CFL steps (stages 2 and 3 read y0)."""
-    n = (31, 5, 4)
+def test_several_x_blocks_k4(dgm, prec, n):
+    """The stage kernel updates x-blocks of 16 cells, their edge faces from a ghost product of
+    the cell before and the cell after: (31, 5, 4) has a full block and a ragged one of 15 cells
+    (x faces 15/16 inside the mesh and 30/0 at the periodic wrap, each formed by two blocks);
+    (16, 4, 4) is one full block whose cell after is its own first cell.  R with the driving,
+    then two device-CFL steps (stages 2 and 3 read y0)."""
     cfg, y = turb(n, seed=11, mach=0.5)
     s = dgm.Solver(K, n, gamma=G, precision=prec, forcing=True)
     nvec, al, frc = driving(dgm)
