@@ -251,11 +251,14 @@ std::vector<char> build_tables(const TableLayout &L, const double s[3]) {
 // index 8g + j is the result register j % 4 of lane group g of the preceding product, i.e. point
 // 4g + j % 4 of the node (volume) or face, and j / 4 selects the first or second table of the
 // chunk (x / y derivative; z derivative / source; - face / + face).  Result row 4g' + r' of row
-// tile rt is slot 4 rt + r' of lane group g' (row tile 1: r' = 0 only).
+// tile rt is slot 4 rt + r' of lane group g' (row tile 1: r' = 0 only).  After the LDS sets come
+// the K3_NS mode-to-mode fragments of the mass flux's volume term (products with the momentum
+// weights): the gradient tables contracted with the point values over the 64 volume points.
 std::vector<char> build_tables_k3(int prec, const double s[3]) {
     const Basis B(3);
     std::vector<double> t((size_t)K3_NFRAG * 64 * 8, 0.0);
     auto at = [&](int frag, int lane, int j) -> double & { return t[((size_t)frag * 64 + lane) * 8 + j]; };
+    std::vector<double> sm((size_t)K3_NS * 64 * 8, 0.0);
     auto rowmode = [](int rt, int row) {
         const int gg = row / 4, rr = row % 4;
         return rt == 0 ? k3_slot_mode(gg, rr) : (rr == 0 ? k3_slot_mode(gg, 4) : -1);
@@ -287,6 +290,20 @@ std::vector<char> build_tables_k3(int prec, const double s[3]) {
                     B.face_point(f, row, xi);
                     at(K3_T3 + f, lane, j) = B.phi(m, xi);
                 }
+            // S: the mass flux's volume term from the momentum weights, sum over the 64 volume
+            // points of -s_a dphi_a[mb](x_q) w_q phi[m](x_q)
+            if (m > 0)
+                for (int sf = 0; sf < K3_NS; sf++) {
+                    const int ax = sf < 3 ? sf : 2, rt = sf < 3 ? 0 : 1;
+                    const int mb = rowmode(rt, row);
+                    if (mb < 0) continue;
+                    double acc = 0.0;
+                    for (int q = 0; q < 64; q++) {
+                        B.point(q, xi);
+                        acc += -s[ax] * B.dphi(mb, ax, xi) * B.weight(q) * B.phi(m, xi);
+                    }
+                    sm[((size_t)sf * 64 + lane) * 8 + j] = acc;
+                }
             for (int ax = 0; ax < 3; ax++)  // T4: lift with the outward sign, - face then + face
                 for (int rt = 0; rt < 2; rt++) {
                     const int mb = rowmode(rt, row);
@@ -304,26 +321,37 @@ std::vector<char> build_tables_k3(int prec, const double s[3]) {
         // blocks: block 4g + c (lanes 4(4g + c) .. + 3) holds cells 4c .. 4c + 3 and contraction
         // index 8g + j, and its row i is row 4i of the tile, so lane l takes the value of lane
         // 4 (l % 4) + 16 (l / 16)
-        std::vector<char> blob((size_t)K3_SET * 2, 0);
+        std::vector<char> blob((size_t)K3_SET * 2 + (size_t)K3_NS * 2 * K3_FRAG, 0);
         float *f = reinterpret_cast<float *>(blob.data());
-        for (int frag = 0; frag < K3_NFRAG; frag++) {
+        for (int frag = 0; frag < K3_NFRAG + K3_NS; frag++) {
             const bool tile1 = (frag >= K3_T2B && frag < K3_T4 && (frag - K3_T2B) % 2 == 1) ||
-                               (frag >= K3_T4 && (frag - K3_T4) % 2 == 1);
+                               (frag >= K3_T4 && frag < K3_NFRAG && (frag - K3_T4) % 2 == 1) ||
+                               frag == K3_NFRAG + 3;
             for (int lane = 0; lane < 64; lane++) {
                 const int src = tile1 ? 4 * (lane % 4) + 16 * (lane / 16) : lane;
-                for (int j = 0; j < 8; j++) f[((size_t)(2 * frag + j / 4) * 64 + lane) * 4 + j % 4] = (float)at(frag, src, j);
+                for (int j = 0; j < 8; j++)
+                    f[((size_t)(2 * frag + j / 4) * 64 + lane) * 4 + j % 4] =
+                        (float)(frag < K3_NFRAG ? at(frag, src, j) : sm[((size_t)(frag - K3_NFRAG) * 64 + src) * 8 + j]);
             }
         }
         return blob;
     }
     const int ntab = prec == DG_BF16X3 ? 2 : 1;
-    std::vector<char> blob((size_t)K3_SET * ntab, 0);
+    constexpr size_t SB = (size_t)K3_NS * K3_FRAG;
+    std::vector<char> blob(((size_t)K3_SET + SB) * ntab, 0);
     uint16_t *hi = reinterpret_cast<uint16_t *>(blob.data());
     uint16_t *lo = reinterpret_cast<uint16_t *>(blob.data() + K3_SET);
     for (size_t i = 0; i < t.size(); i++) {
         const uint16_t h = bf16_rne((float)t[i]);
         hi[i] = h;
         if (ntab == 2) lo[i] = bf16_rne((float)(t[i] - (double)bf16_to_float(h)));
+    }
+    uint16_t *shi = reinterpret_cast<uint16_t *>(blob.data() + (size_t)K3_SET * ntab);
+    uint16_t *slo = reinterpret_cast<uint16_t *>(blob.data() + (size_t)K3_SET * ntab + SB);
+    for (size_t i = 0; i < sm.size(); i++) {
+        const uint16_t h = bf16_rne((float)sm[i]);
+        shi[i] = h;
+        if (ntab == 2) slo[i] = bf16_rne((float)(sm[i] - (double)bf16_to_float(h)));
     }
     return blob;
 }

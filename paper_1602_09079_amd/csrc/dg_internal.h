@@ -71,6 +71,10 @@ __host__ __device__ constexpr int k3_slot_mode(int g, int s) {
 constexpr int K3_FRAG = 1024;
 constexpr int K3_T1 = 0, K3_T3 = 4, K3_T2A = 10, K3_T2B = 14, K3_T4 = 22, K3_NFRAG = 28;
 constexpr int K3_SET = K3_NFRAG * K3_FRAG;
+// After the LDS sets, read through the caches: the mass flux's volume term as mode-to-mode
+// fragments (x, y and z derivative in the first row tile, z in the second), hi then lo set in
+// BF16X3, each fragment two 1 KiB halves in FP32
+constexpr int K3_NS = 4;
 constexpr int K3_BLK = 16;           // cells per x-block
 constexpr int K3_DKS = 2;            // K steps (of 4) of the driving product: wave numbers |n_x| <= 3
 // driving factor table per (z, y) row of cells: [component][z-node][K step][lane] floats

@@ -298,6 +298,47 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             return mma(c, frag, b, j0, j1);
         }
     };
+    // the mass flux's volume term: fragment sf of the mode-to-mode tables after the LDS sets, read
+    // through the caches (A operands requested by sload, used by smma)
+    constexpr unsigned SOFF = (unsigned)K3_SET * (PREC == DG_BF16 ? 1u : 2u);
+    constexpr unsigned STOT = SOFF + (unsigned)K3_NS * K3_FRAG * (PREC == DG_BF16 ? 1u : 2u);
+    struct SFrag {
+        bf8 hi, lo;
+        f4 v;
+        float v4;
+    };
+    auto sload = [&](int sf) -> SFrag {
+        const auto rs = slab_rsrc(reinterpret_cast<const unsigned *>(a.tables), (long long)(STOT / 4u), 0);
+        const unsigned vo = (unsigned)lane_base() * 16u;
+        SFrag o;
+        if constexpr (PREC == DG_FP32) {
+            const unsigned so = SOFF + 2u * (unsigned)sf * K3_FRAG;
+            o.v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0));
+            o.v4 = bload(0.0f, rs, vo, so + K3_FRAG);
+        } else {
+            o.hi = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, SOFF + (unsigned)sf * K3_FRAG, 0));
+            if constexpr (X3)
+                o.lo = __builtin_bit_cast(
+                    bf8, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, SOFF + (unsigned)(K3_NS + sf) * K3_FRAG, 0));
+        }
+        return o;
+    };
+    auto smma = [&](Acc c, const SFrag &f, const OP &b, bool tile1) -> Acc {
+        if constexpr (PREC == DG_FP32) {
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                c = tile1 ? __builtin_amdgcn_mfma_f32_4x4x1f32(f.v[r], b.v[r], c, 0, 0, 0)
+                          : __builtin_amdgcn_mfma_f32_16x16x4f32(f.v[r], b.v[r], c, 0, 0, 0);
+            return tile1 ? __builtin_amdgcn_mfma_f32_4x4x1f32(f.v4, b.v[4], c, 0, 0, 0)
+                         : __builtin_amdgcn_mfma_f32_16x16x4f32(f.v4, b.v[4], c, 0, 0, 0);
+        } else {
+            if constexpr (X3) {
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.lo, b.hi, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.hi, b.lo, c, 0, 0, 0);
+            }
+            return __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.hi, b.hi, c, 0, 0, 0);
+        }
+    };
     // FP32: the second row tile's result in register 0 (slot 4): this lane group's row summed over
     // the four lane groups' parts (two exchange steps, each lane keeping half of what remains)
     auto tile1_sum = [&](Acc c) -> Acc {
@@ -547,12 +588,22 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
                 for (int s = 0; s < K3_DKS; s++) hn[c][s] = drow[(c * 4 * K3_DKS + s) * 64 + lane];
         }
+        SFrag sfr[K3_NS];
+#pragma unroll
+        for (int sf = 0; sf < K3_NS; sf++) sfr[sf] = sload(sf);
         // the weights' operands, formed once for the four nodes
         OP w5[NF];
         {
 #pragma unroll
             for (int i = 0; i < NF; i++) w5[i] = wop(b, i);
         }
+        // mass: its flux deviation is the momentum deviation, a polynomial of the cell's modes, so
+        // its volume term is a fixed matrix on the momentum weights (the quadrature integrates
+        // the products exactly)
+        acc[0][0] = smma(acc[0][0], sfr[0], w5[1], false);
+        acc[0][0] = smma(acc[0][0], sfr[1], w5[2], false);
+        acc[0][0] = smma(acc[0][0], sfr[2], w5[3], false);
+        acc[0][1] = smma(acc[0][1], sfr[3], w5[3], true);
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             refresh();
@@ -587,19 +638,9 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 p[r] = g1 * (E - C(0.5) * (mx[r] * u[r] + my[r] * v[r] + mz[r] * w[r]));
                 ep[r] = E + p[r];
             }
-            // flux deviations F(q) - F(qbar); the mass fluxes' deviations are the momentum
-            // deviations themselves (GEMM1 results); m_a m_b / rho is formed once for both uses
+            // flux deviations F(q) - F(qbar) of the momentum and energy (the mass term is above);
+            // m_a m_b / rho is formed once for both uses
             C tmp[4];
-            // chunk (x, y) of field rho
-            {
-                C dx_[4], dy_[4];
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    dx_[r] = d[1][r];
-                    dy_[r] = d[2][r];
-                }
-                acc[0][0] = mma(acc[0][0], K3_T2A + t, join<PREC>(split4<PREC>(dx_, sk), split4<PREC>(dy_, sk)));
-            }
             HH hxy, hxz, hyz;
             {
 #pragma unroll
@@ -648,12 +689,6 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 acc[i][0] = mma(acc[i][0], K3_T2B + 2 * t, op, 0, j1);
                 acc[i][1] = mma1(acc[i][1], K3_T2B + 2 * t + 1, op, 0, j1);
             };
-            {
-                C dz_[4];
-#pragma unroll
-                for (int r = 0; r < 4; r++) dz_[r] = d[3][r];
-                chunk_b(0, split4<PREC>(dz_, sk), zero4<PREC>());
-            }
             {
                 HH hs = zero4<PREC>();
                 if constexpr (FORCE) {
