@@ -825,6 +825,99 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             lift(2, cur, Fz, nullptr, acc);  // -z face: flux carried from the previous step
             const float *drow = FORCE ? a.dtab + cidx(iy, z) * k3_drive_row_floats(K3_DKS) : nullptr;
             volume(cur, acc, drow);
+            C y044 = C(0);  // slot 4 of field 4 of y0 (stages 2 and 3)
+            // x faces: own traces, the ghost cells' traces, the -x face of every column (its left
+            // neighbour's +x trace in the adjacent lane), the +x flux from the right neighbour's -x
+            // flux, and for a full block the face on its high edge.  In BF16X3 with the driving the
+            // older wave of each SIMD (rows 0..3) forms them before the first y-face barrier, where
+            // it would otherwise wait for its partner, and the younger one after the y lift; the
+            // other kernels (measured slower that way) form them after the y lift in every wave
+            constexpr bool XEARLY = PREC == DG_BF16X3 && FORCE;
+            auto xfaces = [&](bool early) {
+                {
+                    C tl[NF][4], Fxp[NF][4], tm[NF][4];
+                    {
+                        C tp[NF][4], tg[NF][4];
+                        {
+                            // the ghost cells from their copy in LDS.  The copies were requested in the
+                            // previous step (or before the first) and requests complete in order: after
+                            // the y lift the 30 loads of the next block and, in stages 2 and 3, the 20
+                            // copies of y0 were issued after them; before the first barrier fewer
+                            // requests follow them, so that wave waits for all
+                            if (early)
+                                __builtin_amdgcn_s_waitcnt(wait_vm(0));
+                            else if (dma_y0 && act)
+                                __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + NF * 4));
+                            else
+                                __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL)));
+                            asm volatile("" ::: "memory");
+                            B3 gb;
+                            ghost_read(gr, gb);
+                            trace(1, gb, tg);  // column 0: +x trace of the cell before; 15: -x trace after
+                        }
+                        // the copies read above have been used: until the combine, their slots take slot 4
+                        // of y0 for fields 0..3 (stages 2 and 3); field 4's is loaded into a register
+                        __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+                        if (dma_y0 && act) {
+                            const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
+                            lds_c *gdst = lds_dst(ex_g);
+                            asm volatile("" ::: "memory");
+    #pragma unroll
+                            for (int i = 0; i < 4; i++)
+                                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                    r0, (__attribute__((address_space(3))) void *)(gdst + i * 64), 4, roff[4] + xoff,
+                                    (int)((unsigned)i * fbytes), 0, 0);
+                            asm volatile("" ::: "memory");
+                            y044 = bload(0.0f, r0, roff[4] + xoff, 4u * fbytes);
+                        }
+                        trace2(1, 0, cur, tp, tm);  // both x traces of the block from one operand
+                        if (vc == K3_BLK) {
+                            // the 16 points of column 15's +x face, one per lane of columns 12..15
+                            C ql[5], qr[5], fo[5];
+    #pragma unroll
+                            for (int i = 0; i < NF; i++) {
+                                // the DPP moves first, with every lane active, then the selects
+                                const C l1 = shl<1>(tp[i][1]), l2 = shl<2>(tp[i][2]), l3 = shl<3>(tp[i][3]);
+                                const C r1 = shl<1>(tg[i][1]), r2 = shl<2>(tg[i][2]), r3 = shl<3>(tg[i][3]);
+                                const C dflt = i == 0 ? C(1) : (i == 4 ? C(2) : C(0));  // lanes without a point
+                                ql[i] = col == 15 ? tp[i][0] : (col == 14 ? l1 : (col == 13 ? l2 : (col == 12 ? l3 : dflt)));
+                                qr[i] = col == 15 ? tg[i][0] : (col == 14 ? r1 : (col == 13 ? r2 : (col == 12 ? r3 : dflt)));
+                            }
+                            if constexpr (RS == 1)
+                                exact_rs<PR, 0>(ql, qr, gam, fo);
+                            else
+                                hllc<PR, 0>(ql, qr, gam, fo);
+    #pragma unroll
+                            for (int i = 0; i < NF; i++) {
+                                Fxp[i][0] = fo[i];
+                                Fxp[i][1] = shr<1>(fo[i]);
+                                Fxp[i][2] = shr<2>(fo[i]);
+                                Fxp[i][3] = shr<3>(fo[i]);
+                            }
+                        }
+    #pragma unroll
+                        for (int i = 0; i < NF; i++)
+    #pragma unroll
+                            for (int r = 0; r < 4; r++) {
+                                const C sh = shr<1>(tp[i][r]);  // DPP outside any select: every lane active
+                                tl[i][r] = gl ? tg[i][r] : sh;
+                            }
+                    }
+                    C Fxm[NF][4];
+                    riemann(std::integral_constant<int, 0>{}, tl, tm, Fxm);
+                    // the + face flux of a column is the - face flux of its right neighbour; column 15
+                    // of a full block keeps the flux of its high edge
+                    const bool edge = vc == K3_BLK && col == 15;
+    #pragma unroll
+                    for (int i = 0; i < NF; i++)
+    #pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const C sh = shl<1>(Fxm[i][r]);
+                            Fxp[i][r] = edge ? Fxp[i][r] : sh;
+                        }
+                    lift(0, cur, Fxm, Fxp, acc);
+                }
+            };
             // y faces shared by the rows of the workgroup: each face flux is solved once, by the
             // row below it; the faces at the group's ends use the neighbour rows' weights.  Row 0's
             // -y face is solved by four waves of SIMDs 1 and 2, one result register each (row 0
@@ -845,6 +938,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
                 }
                 ex_put(ex_t, wrow, tm);
             }
+            if (XEARLY && wave < 4) xfaces(true);
             lds_barrier();
             // Issue priority: the two waves of a SIMD are rows w and w + 4.  By default the older
             // one (w < 4) wins issue, runs ahead through the faces and then waits at the next
@@ -905,90 +999,7 @@ __global__ __launch_bounds__(K3_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
             lift(1, cur, Fym, Fyp, acc);
             B3 nxt;
             loadz(iy, z + 1, nxt);
-            C y044 = C(0);  // slot 4 of field 4 of y0 (stages 2 and 3)
-            // x faces: own traces, the ghost cells' traces, the -x face of every column (its left
-            // neighbour's +x trace in the adjacent lane), the +x flux from the right neighbour's
-            // -x flux, and for a full block the face on its high edge
-            {
-                C tl[NF][4], Fxp[NF][4], tm[NF][4];
-                {
-                    C tp[NF][4], tg[NF][4];
-                    {
-                        // the ghost cells from their copy in LDS.  The copies were requested in the
-                        // previous step (or before the first) and requests complete in order: the 30
-                        // loads of the next block and, in stages 2 and 3, the 20 copies of y0 were
-                        // issued after them
-                        if (dma_y0 && act)
-                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL) + NF * 4));
-                        else
-                            __builtin_amdgcn_s_waitcnt(wait_vm(NF * (1 + NSL)));
-                        asm volatile("" ::: "memory");
-                        B3 gb;
-                        ghost_read(gr, gb);
-                        trace(1, gb, tg);  // column 0: +x trace of the cell before; 15: -x trace after
-                    }
-                    // the copies read above have been used: until the combine, their slots take slot 4
-                    // of y0 for fields 0..3 (stages 2 and 3); field 4's is loaded into a register
-                    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
-                    if (dma_y0 && act) {
-                        const auto r0 = slab_rsrc(y0, slabn, cidx(iy, z));
-                        lds_c *gdst = lds_dst(ex_g);
-                        asm volatile("" ::: "memory");
-#pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                r0, (__attribute__((address_space(3))) void *)(gdst + i * 64), 4, roff[4] + xoff,
-                                (int)((unsigned)i * fbytes), 0, 0);
-                        asm volatile("" ::: "memory");
-                        y044 = bload(0.0f, r0, roff[4] + xoff, 4u * fbytes);
-                    }
-                    trace2(1, 0, cur, tp, tm);  // both x traces of the block from one operand
-                    if (vc == K3_BLK) {
-                        // the 16 points of column 15's +x face, one per lane of columns 12..15
-                        C ql[5], qr[5], fo[5];
-#pragma unroll
-                        for (int i = 0; i < NF; i++) {
-                            // the DPP moves first, with every lane active, then the selects
-                            const C l1 = shl<1>(tp[i][1]), l2 = shl<2>(tp[i][2]), l3 = shl<3>(tp[i][3]);
-                            const C r1 = shl<1>(tg[i][1]), r2 = shl<2>(tg[i][2]), r3 = shl<3>(tg[i][3]);
-                            const C dflt = i == 0 ? C(1) : (i == 4 ? C(2) : C(0));  // lanes without a point
-                            ql[i] = col == 15 ? tp[i][0] : (col == 14 ? l1 : (col == 13 ? l2 : (col == 12 ? l3 : dflt)));
-                            qr[i] = col == 15 ? tg[i][0] : (col == 14 ? r1 : (col == 13 ? r2 : (col == 12 ? r3 : dflt)));
-                        }
-                        if constexpr (RS == 1)
-                            exact_rs<PR, 0>(ql, qr, gam, fo);
-                        else
-                            hllc<PR, 0>(ql, qr, gam, fo);
-#pragma unroll
-                        for (int i = 0; i < NF; i++) {
-                            Fxp[i][0] = fo[i];
-                            Fxp[i][1] = shr<1>(fo[i]);
-                            Fxp[i][2] = shr<2>(fo[i]);
-                            Fxp[i][3] = shr<3>(fo[i]);
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < NF; i++)
-#pragma unroll
-                        for (int r = 0; r < 4; r++) {
-                            const C sh = shr<1>(tp[i][r]);  // DPP outside any select: every lane active
-                            tl[i][r] = gl ? tg[i][r] : sh;
-                        }
-                }
-                C Fxm[NF][4];
-                riemann(std::integral_constant<int, 0>{}, tl, tm, Fxm);
-                // the + face flux of a column is the - face flux of its right neighbour; column 15
-                // of a full block keeps the flux of its high edge
-                const bool edge = vc == K3_BLK && col == 15;
-#pragma unroll
-                for (int i = 0; i < NF; i++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const C sh = shl<1>(Fxm[i][r]);
-                        Fxp[i][r] = edge ? Fxp[i][r] : sh;
-                    }
-                lift(0, cur, Fxm, Fxp, acc);
-            }
+            if (!XEARLY || wave >= 4) xfaces(false);
             {  // +z face with block z+1; its flux is the -z flux of the next step
                 C tp[NF][4], tm[NF][4];
                 trace(5, cur, tp);
